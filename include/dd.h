@@ -1,0 +1,221 @@
+/*
+ * dd.h -- C ABI of the MI355X (gfx950) brute-force incoherent dedispersion
+ * library.
+ *
+ * What is computed.  The paper names dedispersion as the first GPU analysis
+ * module of the pipeline (Introduction) without printing its formula; this
+ * library implements the standard brute-force incoherent operator:
+ *   - a DM plan is a list of ranges; range r holds the trial DMs
+ *     lo + i*step for i < round((hi - lo)/step)   (half-open [lo, hi));
+ *   - channel c is delayed by
+ *       s[d][c] = floor(K*DM_d*(f_c^-2 - f_ref^-2)/(tsamp*ds_r) + 1/2)
+ *     samples of the range's binned series, K = 4.148808e3 s MHz^2 pc^-1
+ *     cm^3, f_ref = the highest channel frequency (so every s >= 0); the
+ *     table is computed once per plan in FP64 on the host;
+ *   - a range with downsample ds_r > 1 works on the series binned by summing
+ *     ds_r adjacent samples (bin 0 = samples [0, ds_r), partial bin dropped);
+ *   - out_r[d][t] = sum_c w_c * x_r[c][t + s[d][c]] for the valid samples
+ *     t < nout_r = floor(nsamp/ds_r) - max_{d in r, c} s[d][c];
+ *   - the output holds the ranges in plan order, each DM-major
+ *     [ndms_r][nout_r], starting at element out_offset_r.
+ *
+ * API shape (paper, "API Structure"): the caller describes the search in an
+ * immutable plan; the library derives the GPU strategy from it (tile
+ * shapes, workspace size) and exposes both for query; every call returns a
+ * status code, and a failing call leaves the plan valid (paper, "Plan and
+ * strategy" and "Pipeline").  Memory (paper, "Memory management", "Memory
+ * ownership"): the caller asks how much workspace a plan needs before
+ * allocating it; the caller owns the input (never modified), the output and
+ * the workspace; the plan owns its host tables and its device copy of the
+ * shift table, freed by dd_plan_destroy.  Unlike the paper's results
+ * buffers, the output buffer here belongs to the caller.
+ *
+ * Pointers named d_* are device pointers on the current HIP device; all
+ * other pointers are host pointers.  `stream` is a hipStream_t passed as
+ * void* (NULL = the default stream).  Device work is enqueued asynchronously
+ * on that stream; argument errors are reported synchronously, before
+ * anything is enqueued.  Asynchronous device faults surface at the caller's
+ * next synchronisation, as for any HIP launch.
+ *
+ * Thread safety: a plan is immutable after creation; calls on one plan
+ * from several host threads or streams are safe as long as each in-flight
+ * call has its own output and workspace.  dd_last_error() is per thread.
+ */
+#ifndef DD_MI355X_H
+#define DD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (paper, "Pipeline": success or error per call). */
+typedef enum {
+    DD_OK = 0,
+    DD_ERR_NULL = -1,          /* a required pointer is NULL */
+    DD_ERR_INVALID = -2,       /* a value is out of its domain (see each call) */
+    DD_ERR_EMPTY_OUTPUT = -3,  /* a range has nout_r <= 0: delays exceed the data */
+    DD_ERR_OVERFLOW = -4,      /* uint8 sums could exceed int32: 255*nchans*ds >= 2^31 */
+    DD_ERR_CAPACITY = -5,      /* output buffer smaller than dd_plan_info's out_elems */
+    DD_ERR_DTYPE = -6,         /* the call does not apply to the plan's data type */
+    DD_ERR_HIP = -7,           /* a HIP runtime call or launch failed */
+    DD_ERR_NOMEM = -8,         /* host or device allocation failed */
+    DD_ERR_WORKSPACE = -9      /* workspace smaller than dd_workspace_bytes */
+} dd_status;
+
+/* Input sample type.  DD_U8 input gives int32 output (exact sums);
+ * DD_F32 input gives float32 output and accepts per-channel weights. */
+typedef enum { DD_U8 = 0, DD_F32 = 1 } dd_dtype;
+
+/* One DM range, half-open [dm_lo, dm_hi) with step dm_step (pc cm^-3), and
+ * its time downsampling factor (1 = native resolution). */
+typedef struct {
+    double dm_lo;
+    double dm_hi;
+    double dm_step;
+    int32_t downsample;
+} dd_range;
+
+/* Opaque, immutable plan. */
+typedef struct dd_plan dd_plan;
+
+/* Largest number of ranges one plan may hold. */
+#define DD_MAX_RANGES 16
+
+/*
+ * Create a plan (paper, "Design of the API": one plan per module, strategy
+ * derived by the library).  Host-only: it validates the arguments, expands
+ * the DM ranges, computes the FP64 shift table, the per-range output sizes
+ * and offsets, the workspace size and the tile strategy.  No device memory
+ * is touched until dd_plan_prepare or the first compute call.
+ *
+ *   freqs_mhz  [nchans] channel centre frequencies in MHz, any order, all
+ *              finite and > 0 (copied).
+ *   tsamp_s    native sampling time in seconds, finite and > 0.
+ *   nsamp      samples per channel of the input, > 0.
+ *   ranges     [nranges] DM ranges (copied); 1 <= nranges <= DD_MAX_RANGES;
+ *              each needs finite dm_lo >= 0, dm_hi > dm_lo, dm_step > 0,
+ *              round((dm_hi - dm_lo)/dm_step) >= 1 and downsample >= 1
+ *              (<= 256 for DD_U8, so a binned sample fits 16 bits).
+ *   dtype      DD_U8 or DD_F32.
+ *   out        receives the plan; set to NULL on failure.
+ *
+ * Errors: DD_ERR_NULL, DD_ERR_INVALID, DD_ERR_EMPTY_OUTPUT (a range whose
+ * largest delay leaves no valid sample), DD_ERR_OVERFLOW (DD_U8 only),
+ * DD_ERR_NOMEM.
+ */
+dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s,
+                         int64_t nsamp, const dd_range *ranges, int32_t nranges,
+                         dd_dtype dtype, dd_plan **out);
+
+/* Release the plan, its host tables and every device copy it made.
+ * NULL-safe.  No call on the plan may be in flight on any stream. */
+void dd_plan_destroy(dd_plan *plan);
+
+/*
+ * Whole-plan sizes (paper, "Plan and strategy": the user may query the
+ * strategy).  Any output pointer may be NULL.
+ *   ndms_total       number of trial DMs over all ranges
+ *   out_elems        output elements over all ranges (sum ndms_r*nout_r)
+ *   overlap_samples  largest delay in native samples, max_r(ds_r*max shift):
+ *                    the overlap a streaming run must keep between chunks
+ */
+dd_status dd_plan_info(const dd_plan *plan, int32_t *ndms_total, int64_t *out_elems,
+                       int64_t *overlap_samples);
+
+/*
+ * Sizes of range r (0 <= r < nranges, else DD_ERR_INVALID).  Any output
+ * pointer may be NULL.  out_offset is in elements.
+ */
+dd_status dd_plan_range(const dd_plan *plan, int32_t r, int32_t *ndms, int64_t *nout,
+                        int64_t *out_offset, int32_t *max_shift, int32_t *downsample);
+
+/* Number of ranges of the plan. */
+dd_status dd_plan_nranges(const dd_plan *plan, int32_t *nranges);
+
+/* Copy the trial DMs (host, [ndms_total] doubles, ranges in plan order). */
+dd_status dd_plan_dms(const dd_plan *plan, double *dms_out);
+
+/* Copy the shift table (host, [ndms_total][nchans] int32, in binned samples
+ * of each DM's range). */
+dd_status dd_plan_shifts(const dd_plan *plan, int32_t *shifts_out);
+
+/*
+ * Tile strategy the plan chose (paper, "Design of the API": the strategy
+ * decides how input data are split and processed on the GPU).  Any output
+ * pointer may be NULL.
+ *   time_tile      output samples per workgroup
+ *   dm_tile        trial DMs per workgroup
+ *   chans_stage    largest number of channels staged in LDS at once
+ *   workgroups     workgroups of one forward launch
+ */
+dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_tile,
+                           int32_t *chans_stage, int64_t *workgroups);
+
+/*
+ * Device workspace a forward call needs, in bytes (paper, "Memory
+ * management": modules request GPU memory before it is allocated).  For
+ * DD_U8 it holds the binned copies of the input of every range with
+ * downsample > 1 (uint16); it may be 0, in which case d_ws may be NULL.
+ */
+dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes);
+
+/*
+ * Upload the plan's device tables to the current HIP device now (otherwise
+ * the first compute call on a device does it).  Call it before capturing
+ * compute calls in a HIP graph.  Errors: DD_ERR_NULL, DD_ERR_HIP,
+ * DD_ERR_NOMEM.
+ */
+dd_status dd_plan_prepare(dd_plan *plan);
+
+/*
+ * Forward dedispersion of one filterbank.
+ *   d_in          [nchans][nsamp] channel-major, uint8 (DD_U8) or float32
+ *                 (DD_F32); read only.
+ *   d_weights     [nchans] float32 per-channel weights, DD_F32 only; NULL
+ *                 means all ones.  Must be NULL for DD_U8 (else DD_ERR_DTYPE).
+ *   d_out         int32 (DD_U8) or float32 (DD_F32), out_capacity elements;
+ *                 elements [0, out_elems) are overwritten, the rest untouched.
+ *   d_ws/ws_bytes workspace of at least dd_workspace_bytes bytes (contents
+ *                 scratch; d_ws may be NULL when that size is 0).
+ *   stream        hipStream_t as void*.
+ * DD_U8 sums are exact in int32.  DD_F32 sums are formed in float32 in a
+ * fixed, call-independent order.
+ * Errors: DD_ERR_NULL, DD_ERR_DTYPE, DD_ERR_CAPACITY, DD_ERR_WORKSPACE,
+ * DD_ERR_HIP, DD_ERR_NOMEM.
+ */
+dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weights,
+                     void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
+                     void *stream);
+
+/*
+ * The two steps of dd_forward, for callers that schedule or time them
+ * separately (same arguments and errors as dd_forward):
+ *   dd_forward_bin  writes the binned copies of d_in that ranges with
+ *                   downsample > 1 read into the workspace (nothing to do,
+ *                   and DD_OK, when the workspace size is 0);
+ *   dd_forward_sum  the shift-and-sum of every range into d_out; the
+ *                   workspace must hold what dd_forward_bin wrote for the
+ *                   same d_in, and be unchanged since.
+ * dd_forward(...) is dd_forward_bin followed by dd_forward_sum on the same
+ * stream.
+ */
+dd_status dd_forward_bin(const dd_plan *plan, const void *d_in, void *d_ws, size_t ws_bytes,
+                         void *stream);
+dd_status dd_forward_sum(const dd_plan *plan, const void *d_in, const float *d_weights,
+                         void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
+                         void *stream);
+
+/* Text of a status code (static storage). */
+const char *dd_status_str(dd_status status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char *dd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_MI355X_H */

@@ -155,6 +155,9 @@ int oracle_dedisperse_u8_rows(const uint8_t *x, int32_t nchans, int64_t nsamp,
             free(s);
             return -2;
         }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int32_t c = 0; c < nchans; ++c)
             for (int64_t t = 0; t < nbin; ++t) {
                 int32_t v = 0;
@@ -259,6 +262,9 @@ int oracle_dedisperse_f32(const float *x, int32_t nchans, int64_t nsamp,
             free(s);
             return -2;
         }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int32_t c = 0; c < nchans; ++c) {
             const double w = weights ? (double)weights[c] : 1.0;
             for (int64_t t = 0; t < nbin; ++t) {

@@ -1,0 +1,177 @@
+"""MI355X (gfx950) brute-force incoherent dedispersion.
+
+A thin Python binding over the C ABI declared in ``include/dd.h``: every
+step of the computation runs in the HIP library ``libdd_mi355x.so`` built
+in this directory; this module only marshals arguments.  PyTorch supplies
+device memory (tensors) and streams.  There is no CPU fallback: if the
+library is missing, importing the compute entry points raises.
+
+Usage::
+
+    plan = Plan(freqs_mhz, tsamp_s, nsamp, [(lo, hi, step, ds), ...], "u8")
+    out = dedisperse(x_u8_cuda, plan)          # int32 [out_elems]
+    per_range = plan.split(out)                # list of [ndms_r, nout_r] views
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import DDError, check, lib, library_path  # noqa: F401
+
+DD_U8, DD_F32 = 0, 1
+_DTYPES = {"u8": DD_U8, "f32": DD_F32}
+
+
+class _Range(ctypes.Structure):
+    _fields_ = [("dm_lo", ctypes.c_double), ("dm_hi", ctypes.c_double),
+                ("dm_step", ctypes.c_double), ("downsample", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class RangeInfo:
+    ndms: int
+    nout: int
+    out_offset: int
+    max_shift: int
+    downsample: int
+
+
+class Plan:
+    """Immutable dedispersion plan (wraps dd_plan_create / dd_plan_destroy)."""
+
+    def __init__(self, freqs_mhz, tsamp_s: float, nsamp: int, ranges, dtype: str = "u8"):
+        L = lib()
+        f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
+        rg = (_Range * len(ranges))(*[_Range(float(a), float(b), float(c), int(d))
+                                      for (a, b, c, d) in ranges])
+        self._h = ctypes.c_void_p()
+        self.dtype = dtype
+        self.nchans = int(f.size)
+        self.nsamp = int(nsamp)
+        self.tsamp = float(tsamp_s)
+        check(L.dd_plan_create(f.ctypes.data_as(ctypes.c_void_p), f.size, float(tsamp_s),
+                               int(nsamp), rg, len(ranges), _DTYPES[dtype],
+                               ctypes.byref(self._h)), "dd_plan_create")
+        nd, oe, ov = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        check(L.dd_plan_info(self._h, ctypes.byref(nd), ctypes.byref(oe), ctypes.byref(ov)),
+              "dd_plan_info")
+        self.ndms_total, self.out_elems, self.overlap = nd.value, oe.value, ov.value
+        nr = ctypes.c_int32()
+        check(L.dd_plan_nranges(self._h, ctypes.byref(nr)), "dd_plan_nranges")
+        self.ranges = []
+        for r in range(nr.value):
+            a, b, c, d, e = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(),
+                             ctypes.c_int32(), ctypes.c_int32())
+            check(L.dd_plan_range(self._h, r, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                  ctypes.byref(d), ctypes.byref(e)), "dd_plan_range")
+            self.ranges.append(RangeInfo(a.value, b.value, c.value, d.value, e.value))
+        ws = ctypes.c_size_t()
+        check(L.dd_workspace_bytes(self._h, ctypes.byref(ws)), "dd_workspace_bytes")
+        self.workspace_bytes = ws.value
+        tt, dt, cs, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        check(L.dd_plan_strategy(self._h, ctypes.byref(tt), ctypes.byref(dt), ctypes.byref(cs),
+                                 ctypes.byref(wg)), "dd_plan_strategy")
+        self.strategy = {"time_tile": tt.value, "dm_tile": dt.value,
+                         "chans_stage": cs.value, "workgroups": wg.value}
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise DDError(-1, "plan has been closed")
+        return self._h
+
+    def dms(self) -> np.ndarray:
+        out = np.zeros(self.ndms_total, dtype=np.float64)
+        check(lib().dd_plan_dms(self.handle, out.ctypes.data_as(ctypes.c_void_p)), "dd_plan_dms")
+        return out
+
+    def shifts(self) -> np.ndarray:
+        out = np.zeros((self.ndms_total, self.nchans), dtype=np.int32)
+        check(lib().dd_plan_shifts(self.handle, out.ctypes.data_as(ctypes.c_void_p)),
+              "dd_plan_shifts")
+        return out
+
+    def prepare(self) -> None:
+        """Upload the device tables to the current device now."""
+        check(lib().dd_plan_prepare(self.handle), "dd_plan_prepare")
+
+    def split(self, out):
+        """Per-range [ndms_r, nout_r] views of a flat output."""
+        return [out[r.out_offset: r.out_offset + r.ndms * r.nout].view(r.ndms, r.nout)
+                if hasattr(out, "view") and not isinstance(out, np.ndarray)
+                else out[r.out_offset: r.out_offset + r.ndms * r.nout].reshape(r.ndms, r.nout)
+                for r in self.ranges]
+
+    def close(self) -> None:
+        if self._h:
+            lib().dd_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(plan: Plan, device=None):
+    """Allocate the workspace a plan asks for (dd_workspace_bytes)."""
+    import torch
+    return torch.empty(max(1, plan.workspace_bytes), dtype=torch.uint8,
+                       device=device or "cuda")
+
+
+_STEPS = {"all": "dd_forward", "sum": "dd_forward_sum"}
+
+
+def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step="all"):
+    """Forward dedispersion (dd_forward) of a channel-major [nchans, nsamp]
+    CUDA tensor.  Returns the flat output (int32 for u8 plans).
+
+    step="sum" runs only the shift-and-sum (dd_forward_sum); the workspace
+    must then hold what bin_input() wrote for the same input."""
+    import torch
+    want = torch.uint8 if plan.dtype == "u8" else torch.float32
+    if x.dtype != want or x.dim() != 2 or tuple(x.shape) != (plan.nchans, plan.nsamp):
+        raise ValueError(f"input must be {want} [{plan.nchans}, {plan.nsamp}], got "
+                         f"{x.dtype} {tuple(x.shape)}")
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("input must be a contiguous device tensor")
+    odt = torch.int32 if plan.dtype == "u8" else torch.float32
+    if out is None:
+        out = torch.empty(plan.out_elems, dtype=odt, device=x.device)
+    elif out.dtype != odt or not out.is_cuda or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous device {odt} tensor")
+    if ws is None and plan.workspace_bytes:
+        ws = workspace(plan, x.device)
+    wp = ctypes.c_void_p(weights.data_ptr()) if weights is not None else None
+    fn = _STEPS[step]
+    check(getattr(lib(), fn)(plan.handle, ctypes.c_void_p(x.data_ptr()), wp,
+                             ctypes.c_void_p(out.data_ptr()), out.numel(),
+                             ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
+                             ws.numel() if ws is not None else 0, _stream_ptr(stream)), fn)
+    return out
+
+
+def bin_input(x, plan: Plan, ws, stream=None):
+    """The binning step alone (dd_forward_bin) into the workspace ws."""
+    check(lib().dd_forward_bin(plan.handle, ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
+                               ws.numel() if ws is not None else 0, _stream_ptr(stream)),
+          "dd_forward_bin")
+    return ws

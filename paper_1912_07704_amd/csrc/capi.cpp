@@ -1,0 +1,186 @@
+// Host-only entry points of the C ABI: plan creation and queries, status
+// text and the per-thread error detail (paper, "API Structure": immutable
+// plans whose strategy fields the user may query, with error feedback).
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.h"
+
+namespace dd {
+const char *last_error();
+}
+
+using dd::clear_error;
+using dd::set_error;
+
+extern "C" {
+
+dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s, int64_t nsamp,
+                         const dd_range *ranges, int32_t nranges, dd_dtype dtype, dd_plan **out)
+{
+    clear_error();
+    if (!out) {
+        set_error("out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *out = nullptr;
+    dd_plan *pl = new (std::nothrow) dd_plan;
+    if (!pl) {
+        set_error("host allocation failed");
+        return DD_ERR_NOMEM;
+    }
+    std::string err;
+    dd_status st;
+    try {
+        st = dd::build_plan(freqs_mhz, nchans, tsamp_s, nsamp, ranges, nranges, dtype, &pl->p,
+                            &err);
+    } catch (...) {
+        st = DD_ERR_NOMEM;
+        err = "unexpected host failure while building the plan";
+    }
+    if (st == DD_OK) {
+        pl->p.device = dd::new_device_state();
+        if (!pl->p.device) {
+            st = DD_ERR_NOMEM;
+            err = "host allocation failed";
+        }
+    }
+    if (st != DD_OK) {
+        delete pl;
+        set_error(err);
+        return st;
+    }
+    *out = pl;
+    return DD_OK;
+}
+
+dd_status dd_plan_info(const dd_plan *plan, int32_t *ndms_total, int64_t *out_elems,
+                       int64_t *overlap_samples)
+{
+    clear_error();
+    if (!plan) {
+        set_error("plan must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (ndms_total)
+        *ndms_total = int32_t(plan->p.dms.size());
+    if (out_elems)
+        *out_elems = plan->p.out_elems;
+    if (overlap_samples)
+        *overlap_samples = plan->p.overlap;
+    return DD_OK;
+}
+
+dd_status dd_plan_nranges(const dd_plan *plan, int32_t *nranges)
+{
+    clear_error();
+    if (!plan || !nranges) {
+        set_error("plan and nranges must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *nranges = int32_t(plan->p.ranges.size());
+    return DD_OK;
+}
+
+dd_status dd_plan_range(const dd_plan *plan, int32_t r, int32_t *ndms, int64_t *nout,
+                        int64_t *out_offset, int32_t *max_shift, int32_t *downsample)
+{
+    clear_error();
+    if (!plan) {
+        set_error("plan must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (r < 0 || r >= int32_t(plan->p.ranges.size())) {
+        set_error("range index out of bounds");
+        return DD_ERR_INVALID;
+    }
+    const dd::RangeInfo &ri = plan->p.ranges[r];
+    if (ndms)
+        *ndms = ri.ndms;
+    if (nout)
+        *nout = ri.nout;
+    if (out_offset)
+        *out_offset = ri.out_offset;
+    if (max_shift)
+        *max_shift = ri.max_shift;
+    if (downsample)
+        *downsample = ri.ds;
+    return DD_OK;
+}
+
+dd_status dd_plan_dms(const dd_plan *plan, double *dms_out)
+{
+    clear_error();
+    if (!plan || !dms_out) {
+        set_error("plan and dms_out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    std::memcpy(dms_out, plan->p.dms.data(), plan->p.dms.size() * sizeof(double));
+    return DD_OK;
+}
+
+dd_status dd_plan_shifts(const dd_plan *plan, int32_t *shifts_out)
+{
+    clear_error();
+    if (!plan || !shifts_out) {
+        set_error("plan and shifts_out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    std::memcpy(shifts_out, plan->p.shifts.data(), plan->p.shifts.size() * sizeof(int32_t));
+    return DD_OK;
+}
+
+dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_tile,
+                           int32_t *chans_stage, int64_t *workgroups)
+{
+    clear_error();
+    if (!plan) {
+        set_error("plan must not be NULL");
+        return DD_ERR_NULL;
+    }
+    int32_t st = 0;
+    for (const dd::RangeInfo &ri : plan->p.ranges)
+        st = ri.stage_chans > st ? ri.stage_chans : st;
+    if (time_tile)
+        *time_tile = dd::kTimeTile;
+    if (dm_tile)
+        *dm_tile = dd::kDmTile;
+    if (chans_stage)
+        *chans_stage = st;
+    if (workgroups)
+        *workgroups = plan->p.blocks;
+    return DD_OK;
+}
+
+dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes)
+{
+    clear_error();
+    if (!plan || !bytes) {
+        set_error("plan and bytes must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *bytes = plan->p.ws_bytes;
+    return DD_OK;
+}
+
+const char *dd_status_str(dd_status status)
+{
+    switch (status) {
+    case DD_OK: return "DD_OK";
+    case DD_ERR_NULL: return "DD_ERR_NULL: a required pointer is NULL";
+    case DD_ERR_INVALID: return "DD_ERR_INVALID: an argument is out of its domain";
+    case DD_ERR_EMPTY_OUTPUT: return "DD_ERR_EMPTY_OUTPUT: a range has no valid output sample";
+    case DD_ERR_OVERFLOW: return "DD_ERR_OVERFLOW: uint8 sums could overflow int32";
+    case DD_ERR_CAPACITY: return "DD_ERR_CAPACITY: output buffer too small";
+    case DD_ERR_DTYPE: return "DD_ERR_DTYPE: call does not apply to the plan's data type";
+    case DD_ERR_HIP: return "DD_ERR_HIP: HIP runtime failure";
+    case DD_ERR_NOMEM: return "DD_ERR_NOMEM: allocation failed";
+    case DD_ERR_WORKSPACE: return "DD_ERR_WORKSPACE: workspace too small";
+    }
+    return "unknown dd_status";
+}
+
+const char *dd_last_error(void) { return dd::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,279 @@
+// Host core of the dedispersion library: plan validation, DM expansion, the
+// FP64 shift table, per-range sizes and the tile strategy.  Plain C++ with
+// no HIP dependency (paper, "Separate compilation and linking": host code
+// is built by the host compiler).  Build with -ffp-contract=off so the delay
+// is evaluated exactly in the order written.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+#include <string>
+
+#include "plan.h"
+
+namespace dd {
+
+namespace {
+
+constexpr double kDispersion = 4.148808e3;   // s MHz^2 pc^-1 cm^3
+
+thread_local std::string g_last_error;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+template <typename... A>
+std::string fmt(A &&...a)
+{
+    std::ostringstream os;
+    (os << ... << a);
+    return os.str();
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+const char *last_error() { return g_last_error.c_str(); }
+
+dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t nsamp,
+                     const dd_range *ranges, int32_t nranges, dd_dtype dtype, Plan *p,
+                     std::string *err)
+{
+    if (!freqs || !ranges || !p) {
+        *err = "freqs_mhz, ranges and out must not be NULL";
+        return DD_ERR_NULL;
+    }
+    if (dtype != DD_U8 && dtype != DD_F32) {
+        *err = fmt("unknown dtype ", int(dtype));
+        return DD_ERR_DTYPE;
+    }
+    if (nchans <= 0) {
+        *err = fmt("nchans must be > 0 (got ", nchans, ")");
+        return DD_ERR_INVALID;
+    }
+    if (!finite_pos(tsamp)) {
+        *err = "tsamp_s must be finite and > 0";
+        return DD_ERR_INVALID;
+    }
+    if (nsamp <= 0 || nsamp >= (int64_t(1) << 31)) {
+        *err = fmt("nsamp must be in [1, 2^31) (got ", nsamp, ")");
+        return DD_ERR_INVALID;
+    }
+    if (nranges <= 0 || nranges > DD_MAX_RANGES) {
+        *err = fmt("nranges must be in [1, ", DD_MAX_RANGES, "] (got ", nranges, ")");
+        return DD_ERR_INVALID;
+    }
+    double f_ref = 0.0;
+    for (int32_t c = 0; c < nchans; ++c) {
+        if (!finite_pos(freqs[c])) {
+            *err = fmt("channel ", c, " frequency must be finite and > 0");
+            return DD_ERR_INVALID;
+        }
+        f_ref = std::max(f_ref, freqs[c]);
+    }
+    int32_t max_ds = 1;
+    int64_t ndms_total = 0;
+    for (int32_t r = 0; r < nranges; ++r) {
+        const dd_range &g = ranges[r];
+        if (!std::isfinite(g.dm_lo) || !std::isfinite(g.dm_hi) || !finite_pos(g.dm_step) ||
+            g.dm_lo < 0.0 || !(g.dm_hi > g.dm_lo)) {
+            *err = fmt("range ", r, ": need finite 0 <= dm_lo < dm_hi and dm_step > 0");
+            return DD_ERR_INVALID;
+        }
+        const double n = std::floor((g.dm_hi - g.dm_lo) / g.dm_step + 0.5);
+        if (!(n >= 1.0) || n > double(1 << 24)) {
+            *err = fmt("range ", r, ": round((hi - lo)/step) must be in [1, 2^24]");
+            return DD_ERR_INVALID;
+        }
+        if (g.downsample < 1 || (dtype == DD_U8 && g.downsample > 256) ||
+            int64_t(g.downsample) > nsamp) {
+            *err = fmt("range ", r, ": downsample must be in [1, ",
+                       dtype == DD_U8 ? 256 : 1 << 30, "] and <= nsamp");
+            return DD_ERR_INVALID;
+        }
+        max_ds = std::max(max_ds, g.downsample);
+        ndms_total += int64_t(n);
+    }
+    if (dtype == DD_U8 && 255.0 * double(nchans) * double(max_ds) >= 2147483648.0) {
+        *err = fmt("255 * nchans * downsample = ", 255.0 * nchans * max_ds,
+                   " does not fit int32 output");
+        return DD_ERR_OVERFLOW;
+    }
+    if (double(ndms_total) * double(nchans) > 1.5e9) {
+        *err = "shift table larger than 1.5e9 entries";
+        return DD_ERR_INVALID;
+    }
+
+    try {
+        p->nchans = nchans;
+        p->tsamp = tsamp;
+        p->nsamp = nsamp;
+        p->dtype = dtype;
+        p->freqs.assign(freqs, freqs + nchans);
+        p->dms.clear();
+        p->dms.reserve(size_t(ndms_total));
+        p->shifts.assign(size_t(ndms_total) * nchans, 0);
+        p->ranges.assign(size_t(nranges), RangeInfo{});
+
+        // Per-channel dispersion measure of the band: f_c^-2 - f_ref^-2.
+        std::vector<double> delta(static_cast<size_t>(nchans));
+        for (int32_t c = 0; c < nchans; ++c)
+            delta[c] = 1.0 / (freqs[c] * freqs[c]) - 1.0 / (f_ref * f_ref);
+
+        int64_t out_off = 0;
+        int32_t dm_index = 0;
+        p->overlap = 0;
+        for (int32_t r = 0; r < nranges; ++r) {
+            const dd_range &g = ranges[r];
+            RangeInfo &ri = p->ranges[r];
+            ri.lo = g.dm_lo;
+            ri.hi = g.dm_hi;
+            ri.step = g.dm_step;
+            ri.ds = g.downsample;
+            ri.ndms = int32_t(std::floor((g.dm_hi - g.dm_lo) / g.dm_step + 0.5));
+            ri.dm_index = dm_index;
+            ri.nbin = nsamp / ri.ds;
+            int32_t smax = 0;
+            for (int32_t i = 0; i < ri.ndms; ++i) {
+                const double dm = g.dm_lo + double(i) * g.dm_step;
+                p->dms.push_back(dm);
+                int32_t *row = &p->shifts[size_t(dm_index + i) * nchans];
+                for (int32_t c = 0; c < nchans; ++c) {
+                    const double x = kDispersion * dm * delta[c] / (tsamp * ri.ds);
+                    const double s = std::floor(x + 0.5);
+                    if (!(s >= 0.0) || s > 2.0e9) {
+                        *err = fmt("range ", r, ": delay out of range at DM ", dm);
+                        return DD_ERR_EMPTY_OUTPUT;
+                    }
+                    row[c] = int32_t(s);
+                    smax = std::max(smax, row[c]);
+                }
+            }
+            ri.max_shift = smax;
+            ri.nout = ri.nbin - smax;
+            if (ri.nout <= 0) {
+                *err = fmt("range ", r, ": largest delay ", smax, " leaves no valid sample of ",
+                           ri.nbin, " binned samples");
+                return DD_ERR_EMPTY_OUTPUT;
+            }
+            ri.out_offset = out_off;
+            out_off += int64_t(ri.ndms) * ri.nout;
+            p->overlap = std::max<int64_t>(p->overlap, int64_t(smax) * ri.ds);
+            dm_index += ri.ndms;
+        }
+        p->out_elems = out_off;
+
+        // Binned copies: one per distinct downsample > 1, each binned from the
+        // largest earlier level that divides it (or from the raw input).
+        const size_t elem = dtype == DD_U8 ? sizeof(uint16_t) : sizeof(float);
+        std::vector<int32_t> dss;
+        for (const RangeInfo &ri : p->ranges)
+            if (ri.ds > 1)
+                dss.push_back(ri.ds);
+        std::sort(dss.begin(), dss.end());
+        dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
+        p->levels.clear();
+        size_t ws = 0;
+        for (int32_t ds : dss) {
+            BinLevel lv;
+            lv.ds = ds;
+            lv.src = -1;
+            lv.factor = ds;
+            for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
+                if (ds % p->levels[j].ds == 0) {
+                    lv.src = j;
+                    lv.factor = ds / p->levels[j].ds;
+                    break;
+                }
+            lv.nbin = nsamp / ds;
+            lv.ws_offset = ws;
+            lv.bytes = size_t(nchans) * size_t(lv.nbin) * elem;
+            ws = align_up(ws + lv.bytes, kWsAlign);
+            p->levels.push_back(lv);
+        }
+        for (RangeInfo &ri : p->ranges) {
+            ri.level = -1;
+            for (size_t j = 0; j < p->levels.size(); ++j)
+                if (p->levels[j].ds == ri.ds)
+                    ri.level = int32_t(j);
+        }
+        p->ws_bytes = ws;
+
+        // Tile strategy: a time tile of kTimeTile samples by a DM tile of
+        // kDmTile trials per workgroup; channels are staged in LDS in groups
+        // small enough that 16-bit partial sums cannot carry.
+        int64_t blocks = 0;
+        size_t lds = 0;
+        for (int32_t r = 0; r < nranges; ++r) {
+            RangeInfo &ri = p->ranges[r];
+            int32_t span = 0;
+            for (int32_t d0 = 0; d0 < ri.ndms; d0 += kDmTile) {
+                const int32_t d1 = std::min(ri.ndms, d0 + kDmTile) - 1;
+                const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
+                const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d1) * nchans];
+                for (int32_t c = 0; c < nchans; ++c)
+                    span = std::max(span, s1[c] - s0[c]);
+            }
+            ri.span = span;
+            ri.row_words = 64 * kWaveWords + span / 2 + 1;
+            int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
+            int32_t stage = std::max(1, std::min(kMaxStageChans, cap));
+            if (stage > 1)
+                stage &= ~1;
+            auto bytes_for = [&](int32_t st) {
+                return size_t(2) * size_t((st + 1) & ~1) * size_t(ri.row_words) * 4;
+            };
+            while (stage > 2 && bytes_for(stage) > 64 * 1024)
+                stage -= 2;
+            if (bytes_for(stage) > kMaxLdsBytes) {
+                *err = fmt("range ", r, ": delay spread ", span,
+                           " inside one DM tile needs more LDS than a workgroup has; use a "
+                           "finer DM step");
+                return DD_ERR_INVALID;
+            }
+            ri.stage_chans = stage;
+            lds = std::max(lds, bytes_for(stage));
+            ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
+            ri.ndm_tiles = (ri.ndms + kDmTile - 1) / kDmTile;
+            ri.block_start = blocks;
+            blocks += ri.ntime_tiles * ri.ndm_tiles;
+        }
+        p->blocks = blocks;
+        p->lds_bytes = lds;
+
+        // Device tables of the integer kernel (see plan.h).
+        size_t noff = 0, nbase = 0;
+        for (RangeInfo &ri : p->ranges) {
+            ri.ndms_pad = ri.ndm_tiles * kDmTile;
+            ri.off_offset = noff;
+            ri.base_offset = nbase;
+            noff += size_t(nchans) * ri.ndms_pad;
+            nbase += size_t(nchans) * ri.ndm_tiles;
+        }
+        p->offT.assign(noff, 0);
+        p->baseT.assign(nbase, 0);
+        for (RangeInfo &ri : p->ranges) {
+            for (int32_t c = 0; c < nchans; ++c) {
+                int32_t *base = &p->baseT[ri.base_offset + size_t(c) * ri.ndm_tiles];
+                int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
+                for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile)
+                    base[tile] = p->shifts[size_t(ri.dm_index + tile * kDmTile) * nchans + c];
+                for (int32_t d = 0; d < ri.ndms_pad; ++d) {
+                    const int32_t dv = std::min(d, ri.ndms - 1);
+                    const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] -
+                                      base[dv / kDmTile];
+                    off[d] = (o & 1) * ri.row_words + (o >> 1);
+                }
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        *err = "host allocation failed";
+        return DD_ERR_NOMEM;
+    }
+    return DD_OK;
+}
+
+}  // namespace dd

@@ -1,0 +1,102 @@
+// Host-side plan of the dedispersion library (internal).  No HIP types:
+// the host core (plan.cpp) is plain C++ and builds with any host compiler.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+
+namespace dd {
+
+// Tile geometry of the integer forward kernel: each wavefront covers
+// kWaveWords 32-bit words per lane (two samples per word) of one time tile,
+// for kDmPerWave trial DMs; a workgroup holds kWaves wavefronts, one DM
+// group each.
+constexpr int kWaves = 4;
+constexpr int kWaveWords = 4;                    // words per lane
+constexpr int kDmPerWave = 8;
+constexpr int kTimeTile = 128 * kWaveWords;      // samples per workgroup
+constexpr int kDmTile = kWaves * kDmPerWave;     // DMs per workgroup
+constexpr int kMaxStageChans = 16;               // channels staged at once
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+constexpr size_t kWsAlign = 256;
+
+// One binned copy of the input held in the workspace.
+struct BinLevel {
+    int32_t ds = 1;          // total binning factor
+    int32_t src = -1;        // index of the level it is binned from (-1 = raw input)
+    int32_t factor = 1;      // ds / ds of the source
+    int64_t nbin = 0;        // floor(nsamp / ds)
+    size_t ws_offset = 0;    // byte offset in the workspace
+    size_t bytes = 0;
+};
+
+struct RangeInfo {
+    double lo = 0, hi = 0, step = 0;
+    int32_t ds = 1;
+    int32_t ndms = 0;
+    int32_t dm_index = 0;        // first DM of the range in the plan's DM list
+    int64_t nbin = 0;
+    int64_t nout = 0;
+    int64_t out_offset = 0;      // elements
+    int32_t max_shift = 0;
+    int32_t level = -1;          // binned copy used (-1 = raw input)
+    // strategy
+    int32_t stage_chans = 0;     // channels per LDS stage
+    int32_t span = 0;            // largest delay spread inside one DM tile
+    int32_t row_words = 0;       // 32-bit words per staged channel copy
+    int64_t ntime_tiles = 0;
+    int32_t ndm_tiles = 0;
+    int64_t block_start = 0;     // first workgroup of the range
+    int32_t ndms_pad = 0;        // ndms rounded up to a multiple of kDmTile
+    size_t off_offset = 0;       // element offset of this range in offT
+    size_t base_offset = 0;      // element offset of this range in baseT
+};
+
+struct Plan {
+    int32_t nchans = 0;
+    double tsamp = 0;
+    int64_t nsamp = 0;
+    dd_dtype dtype = DD_U8;
+    std::vector<double> freqs;
+    std::vector<double> dms;               // [ndms_total]
+    std::vector<int32_t> shifts;           // [ndms_total][nchans]
+    // Device tables of the integer kernel, per range, concatenated:
+    //  baseT[c][tile]   delay of the first DM of each DM tile (staging origin)
+    //  offT[c][d]       LDS word offset of DM d inside the staged channel:
+    //                   (o & 1) * row_words + (o >> 1), o = s[d][c] - baseT[c][tile(d)];
+    //                   DMs past the last (up to ndms_pad) repeat the last one.
+    std::vector<int32_t> baseT;
+    std::vector<int32_t> offT;
+    std::vector<RangeInfo> ranges;
+    std::vector<BinLevel> levels;
+    int64_t out_elems = 0;
+    int64_t overlap = 0;
+    size_t ws_bytes = 0;
+    int64_t blocks = 0;                    // workgroups of one forward launch
+    size_t lds_bytes = 0;                  // dynamic LDS of the forward kernel
+    void *device = nullptr;                // device-side state (owned by the HIP unit)
+};
+
+// Host core (plan.cpp).  On failure returns a negative status and writes a
+// message into *err.
+dd_status build_plan(const double *freqs_mhz, int32_t nchans, double tsamp_s, int64_t nsamp,
+                     const dd_range *ranges, int32_t nranges, dd_dtype dtype, Plan *p,
+                     std::string *err);
+
+// Device-side state of a plan (allocated by the HIP unit, freed by
+// dd_plan_destroy).
+void *new_device_state();
+
+// Thread-local error text shared by every entry point.
+void set_error(const std::string &msg);
+void clear_error();
+
+}  // namespace dd
+
+struct dd_plan {
+    dd::Plan p;
+};

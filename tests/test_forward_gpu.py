@@ -1,0 +1,257 @@
+"""Parity of the HIP integer forward with the CPU oracle (bit-exact int32).
+
+Every call goes through the C ABI (dd_forward / dd_forward_bin /
+dd_forward_sum) on cuda:0.  Each test prints its case before touching the
+GPU so a failing run names it.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cref
+from oracle import dedisp as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+dd = pytest.importorskip("paper_1912_07704_amd")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_forward(x, freqs, tsamp, ranges, out_extra=0, canary=-123456789):
+    plan = dd.Plan(freqs, tsamp, x.shape[1], ranges)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = torch.full((plan.out_elems + out_extra,), canary, dtype=torch.int32, device="cuda")
+    dd.dedisperse(xt, plan, out=out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), plan
+
+
+def oracle_flat(x, freqs, tsamp, ranges):
+    if x.shape[0] * x.shape[1] <= 2_000_000 and len(ranges) <= 3:
+        outs, _ = O.dedisperse(x, freqs, tsamp, ranges)
+        return O.concat(outs)
+    return cref.dedisperse_u8(x, freqs, tsamp, ranges).astype(np.int64)
+
+
+def test_tiny_workload_bit_exact():
+    w = synth.tiny()
+    say("tiny", w.name)
+    x = w.make_input()
+    got, plan = gpu_forward(x, w.freqs, w.tsamp, w.ranges, out_extra=1000)
+    want = cref.dedisperse_u8(x, w.freqs, w.tsamp, w.ranges)
+    assert np.array_equal(got[: plan.out_elems], want)
+    assert (got[plan.out_elems:] == -123456789).all(), "wrote past out_elems"
+
+
+def random_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    while True:
+        nch = int(rng.integers(1, 300))
+        nsamp = int(rng.integers(64, 8193))
+        f_top = float(rng.uniform(1000.0, 1700.0))
+        bw = float(rng.uniform(10.0, 400.0))
+        freqs = synth.band_freqs(f_top, f_top - bw, nch)
+        if seed % 3 == 1:
+            freqs = freqs[::-1].copy()          # ascending band
+        if seed % 5 == 2:
+            freqs = rng.permutation(freqs)      # arbitrary channel order
+        tsamp = float(rng.choice([64e-6, 2.56e-4, 1e-3]))
+        ranges, lo = [], 0.0
+        for _ in range(int(rng.integers(1, 4))):
+            step = float(rng.choice([0.1, 0.5, 1.0, 3.0]))
+            n = int(rng.integers(1, 80))
+            ranges.append((lo, lo + n * step, step, int(rng.choice([1, 2, 3, 4, 6, 8, 16]))))
+            lo += n * step
+        try:
+            O.expand_plan(freqs, tsamp, nsamp, ranges)
+        except ValueError:
+            continue
+        x = rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8)
+        return x, freqs, tsamp, ranges
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_shapes_bit_exact(seed):
+    x, freqs, tsamp, ranges = random_case(seed)
+    say("random", seed, x.shape, ranges)
+    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=64)
+    assert np.array_equal(got[: plan.out_elems], oracle_flat(x, freqs, tsamp, ranges))
+    assert (got[plan.out_elems:] == -123456789).all()
+
+
+EDGES = {
+    # one channel: the output is the binned input itself
+    "one_channel": (1, 300, [(0.0, 5.0, 1.0, 1), (5.0, 7.0, 1.0, 3)]),
+    # odd channel count with a partial LDS stage, a partial DM tile (33 DMs)
+    "odd_channels_partial_dm_tile": (17, 2000, [(0.0, 33.0, 1.0, 1)]),
+    # exactly one DM, exactly one valid output sample
+    "single_dm_single_sample": (8, 0, [(40.0, 41.0, 1.0, 1)]),
+    # the largest binning factor of the integer path
+    "downsample_256": (6, 6000, [(0.0, 2.0, 1.0, 256)]),
+    # binning cascades: 6 from 2 (factor 3), 9 from 3 and 12 from 6
+    "cascade": (40, 3000, [(0.0, 10.0, 1.0, 2), (10.0, 20.0, 1.0, 6), (20.0, 30.0, 2.0, 3),
+                           (30.0, 40.0, 2.0, 9), (40.0, 50.0, 2.0, 12)]),
+    # a DM tile whose delay spread is large (coarse step, low frequencies)
+    "wide_spread": (64, 20000, [(0.0, 400.0, 12.5, 1)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGES))
+def test_edge_cases_bit_exact(name):
+    nch, nsamp, ranges = EDGES[name]
+    freqs = synth.band_freqs(1500.0, 1200.0, nch) if nch > 1 else np.array([1400.0])
+    tsamp = 1e-3
+    if name == "single_dm_single_sample":
+        s = O.shift_table(freqs, tsamp, [40.0])
+        nsamp = int(s.max()) + 1
+    if name == "wide_spread":
+        freqs = synth.band_freqs(500.0, 300.0, nch)
+        tsamp = 1e-3
+    rng = np.random.default_rng(hash(name) % 2**32)
+    x = rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8)
+    if name == "downsample_256":
+        x[:] = 255                               # the largest binned value, 255*256
+    say("edge", name, x.shape, ranges)
+    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=8)
+    want = oracle_flat(x, freqs, tsamp, ranges)
+    assert np.array_equal(got[: plan.out_elems], want)
+    if name == "single_dm_single_sample":
+        assert plan.out_elems == 1
+
+
+def test_all_255_and_all_zero_extremes():
+    """Saturated input: every sum reaches its bound (255*nchans*ds) without a
+    carry between the packed 16-bit halves."""
+    freqs = synth.band_freqs(1670.0, 1370.0, 1024)
+    ranges = [(0.0, 40.0, 1.0, 1), (40.0, 80.0, 2.0, 16)]
+    for val in (255, 0):
+        x = np.full((1024, 8192), val, dtype=np.uint8)
+        say("extreme", val)
+        got, plan = gpu_forward(x, freqs, 64e-6, ranges)
+        outs = plan.split(got)
+        assert (outs[0] == 255 * 1024 * (val // 255)).all()
+        assert (outs[1] == 255 * 1024 * 16 * (val // 255)).all()
+
+
+def test_steps_compose_and_repeat_bit_identically():
+    w = synth.ska_single_beam(nsamp=1 << 15, nchans=512)
+    say("steps", w.name)
+    x = torch.from_numpy(w.make_input()).cuda()
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    ws = dd.workspace(plan)
+    a = dd.dedisperse(x, plan, ws=ws)
+    dd.bin_input(x, plan, ws)
+    b = dd.dedisperse(x, plan, ws=ws, step="sum")
+    c = dd.dedisperse(x, plan)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    want = cref.dedisperse_u8(w.make_input(), w.freqs, w.tsamp, w.ranges)
+    assert np.array_equal(a.cpu().numpy(), want)
+
+
+def test_other_stream():
+    w = synth.tiny()
+    say("stream", w.name)
+    x = torch.from_numpy(w.make_input()).cuda()
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = dd.dedisperse(x, plan)
+    s.synchronize()
+    want = cref.dedisperse_u8(w.make_input(), w.freqs, w.tsamp, w.ranges)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_forced_allocation_failure_is_reported():
+    w = synth.tiny()
+    say("fault-hook alloc")
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    x = torch.zeros((w.nchans, w.nsamp), dtype=torch.uint8, device="cuda")
+    os.environ["DD_FAULT"] = "alloc"
+    try:
+        with pytest.raises(dd.DDError) as e:
+            dd.dedisperse(x, plan)
+        assert e.value.status == -8
+    finally:
+        del os.environ["DD_FAULT"]
+    out = dd.dedisperse(x, plan)           # the plan is still usable
+    torch.cuda.synchronize()
+    assert int(out.abs().max()) == 0
+
+
+# ---------------------------------------------------------------------------
+# Full-size SKA-like beam (the benchmark's workload and launch configuration)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def ska():
+    w = synth.ska_single_beam()
+    say("ska full size: generating input")
+    x = w.make_input()
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    xt = torch.from_numpy(x).cuda()
+    say("ska full size: forward")
+    out = dd.dedisperse(xt, plan)
+    torch.cuda.synchronize()
+    return w, x, plan, out
+
+
+def test_ska_full_size_rows_bit_exact(ska):
+    """Whole rows at the DM-tile edges and inside tiles of every range,
+    against the C oracle's rows."""
+    w, x, plan, out = ska
+    outs = plan.split(out)
+    for r, (rg, ri) in enumerate(zip(w.ranges, plan.ranges)):
+        rows = sorted({0, 1, 31, 32, 33, ri.ndms // 2, ri.ndms - 2, ri.ndms - 1})
+        say("ska rows", r, rows)
+        for d in rows:
+            want = cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, d, d + 1, ri.nout)[0]
+            got = outs[r][d].cpu().numpy()
+            assert np.array_equal(got, want), (r, d)
+
+
+def test_ska_full_size_sampled_outputs(ska):
+    w, x, plan, out = ska
+    op = O.expand_plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    outs = plan.split(out)
+    rng = np.random.default_rng(77)
+    for r, ri in enumerate(plan.ranges):
+        d = rng.integers(0, ri.ndms, 300)
+        t = rng.integers(0, ri.nout, 300)
+        t[:20] = ri.nout - 1 - np.arange(20)          # the ragged end of the last tile
+        say("ska samples", r)
+        got = outs[r][torch.from_numpy(d).cuda(), torch.from_numpy(t).cuda()].cpu().numpy()
+        assert np.array_equal(got, O.dedisperse_at(x, op, r, d, t))
+
+
+def test_ska_pulses_recovered(ska):
+    w, x, plan, out = ska
+    outs = plan.split(out)
+    dms = plan.dms()
+    f = w.freqs
+    dmax = 1.0 / f.min() ** 2 - 1.0 / f.max() ** 2
+    for p in w.pulses:
+        r = next(i for i, rg in enumerate(w.ranges) if rg[0] <= p.dm < rg[1])
+        ri = plan.ranges[r]
+        ds = ri.downsample
+        o = outs[r].double()
+        o = o - o.mean(dim=1, keepdim=True)
+        wb = max(1, -(-p.width // ds))
+        cs = torch.nn.functional.pad(torch.cumsum(o, dim=1), (1, 0))
+        box = cs[:, wb:] - cs[:, :-wb]
+        lo = max(0, p.t0 // ds - 300)
+        hi = min(box.shape[1], p.t0 // ds + 300)
+        sub = box[:, lo:hi]
+        k = int(torch.argmax(sub))
+        d, t = divmod(k, sub.shape[1])
+        dm_found = dms[sum(q.ndms for q in plan.ranges[:r]) + d]
+        tol = 1.5 * (w.ranges[r][2] + p.width * w.tsamp / (O.K_DM * dmax))
+        say("pulse", p, dm_found, (t + lo) * ds)
+        assert abs(dm_found - p.dm) <= tol
+        assert abs((t + lo) * ds - p.t0) <= p.width + ds
