@@ -157,8 +157,10 @@ dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_
 /*
  * Device workspace a forward call needs, in bytes (paper, "Memory
  * management": modules request GPU memory before it is allocated).  For
- * DD_U8 it holds the binned copies of the input of every range with
- * downsample > 1 (uint16); it may be 0, in which case d_ws may be NULL.
+ * DD_U8 it holds one 16-bit copy of the input per distinct downsample of
+ * the plan (1 included): the samples, or the sums of ds adjacent samples,
+ * in padded rows.  The workspace passed to a compute call must be at least
+ * this large and 256-byte aligned (DD_ERR_WORKSPACE otherwise).
  */
 dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes);
 

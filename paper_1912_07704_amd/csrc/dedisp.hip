@@ -24,6 +24,7 @@ using dd::Plan;
 using dd::RangeInfo;
 
 constexpr int kWave = 64;
+constexpr int kWavesPerBlock = dd::kWaves;
 constexpr int kBlock = dd::kWaves * kWave;
 constexpr int kNW = dd::kWaveWords;
 constexpr int kDW = dd::kDmPerWave;
@@ -99,24 +100,43 @@ dd_status device_tables(const Plan &p, DeviceTables **out)
 }
 
 // ---------------------------------------------------------------------------
-// Binning: dst[c][t] = sum_{k<f} src[c][f*t + k], t < nbin (uint16 result).
+// Binning into 16-bit rows: dst[c][t] = sum_{k<f} src[c][f*t + k], t < nbin.
+// Each thread forms four consecutive bins.
 // ---------------------------------------------------------------------------
 
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_bin_u16(const Tin *__restrict__ src, int64_t src_stride,
-                                                 uint16_t *__restrict__ dst, int64_t nbin,
-                                                 int factor)
+__global__ __launch_bounds__(256) void k_bin_u16(const Tin *__restrict__ src, int64_t src_pitch,
+                                                 uint16_t *__restrict__ dst, int64_t dst_pitch,
+                                                 int64_t nbin, int factor, int nchans)
 {
-    const int64_t c = blockIdx.y;
-    const Tin *row = src + c * src_stride;
-    uint16_t *out = dst + c * nbin;
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nbin;
-         t += int64_t(gridDim.x) * blockDim.x) {
-        const Tin *p = row + t * factor;
-        uint32_t s = 0;
-        for (int k = 0; k < factor; ++k)
-            s += p[k];
-        out[t] = uint16_t(s);
+    const int64_t nq = (nbin + 3) / 4;
+    for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y) {
+        const Tin *row = src + c * src_pitch;
+        uint16_t *out = dst + c * dst_pitch;
+        for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < nq;
+             q += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t t = 4 * q;
+            uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (t + i < nbin) {
+                    const Tin *p = row + (t + i) * factor;
+                    for (int k = 0; k < factor; ++k)
+                        v[i] += p[k];
+                }
+            }
+            if (t + 4 <= nbin) {
+                ushort4 w;
+                w.x = uint16_t(v[0]);
+                w.y = uint16_t(v[1]);
+                w.z = uint16_t(v[2]);
+                w.w = uint16_t(v[3]);
+                *reinterpret_cast<ushort4 *>(out + t) = w;
+            } else {
+                for (int i = 0; i < 4 && t + i < nbin; ++i)
+                    out[t + i] = uint16_t(v[i]);
+            }
+        }
     }
 }
 
@@ -128,34 +148,36 @@ __global__ __launch_bounds__(256) void k_bin_u16(const Tin *__restrict__ src, in
 // sample pairs t0 + 2*(l + 64k) + {0, 1}, k < kNW, so a wave's LDS reads of
 // one word index are 64 consecutive dwords (no bank conflict).
 //
-// Channels are staged in LDS in groups.  Staged channel c holds the window
-// v[i] = x_r[c][t0 + s[d0][c] + i] (d0 = first DM of the tile) twice: as
-// even-aligned pairs P0[m] = v[2m] | v[2m+1] << 16 and odd-aligned pairs
-// P1[m] = v[2m+1] | v[2m+2] << 16.  The pair a lane needs for a DM with
-// relative delay o = s[d][c] - s[d0][c] is then one aligned dword,
-// P_{o&1}[(o>>1) + l + 64k], whatever the parity of o.
+// The range reads a 16-bit copy of the input (binned by its downsample).
+// Channels are staged in LDS in groups of C.  For channel c the staged
+// window starts at the 16-byte aligned word t0/2 + baseT[tile][c] of its
+// row, so it arrives by direct global-to-LDS loads; a second copy of the
+// window, shifted by one sample, is then formed in LDS.  With the even
+// (A) and odd (B) copies, the 32-bit word a lane needs for any delay is one
+// aligned dword; offT[c][d] names it (copy, alignment and parity folded in
+// on the host).  Stages are double-buffered: the loads of stage s+1 are in
+// flight while stage s is summed.
 //
 // Each dword carries two 16-bit partial sums.  Two channels are added per
-// instruction (v_add3_u32).  A stage holds at most 65535/(255*ds) channels,
-// so no 16-bit half can carry into the other; after each stage the halves
-// are widened into int32 accumulators, which hold the exact result.
+// instruction (v_add3_u32).  At most 65535/(255*ds) channels are added
+// before the halves are widened into int32 accumulators, so no half can
+// carry into the other and the int32 result is exact.
 // ---------------------------------------------------------------------------
 
 struct RangeArgs {
-    const void *src;          // uint8 [nchans][src_stride] or uint16 binned rows
-    const int32_t *offT;      // [nchans][ndms_pad] LDS word offsets of each DM
-    const int32_t *baseT;     // [nchans][ndm_tiles] delay of each tile's first DM
-    int64_t src_stride;       // elements per channel row of src
-    int64_t nbin;             // valid samples per row of src
+    const uint16_t *src;      // 16-bit rows of this range's level
+    const int32_t *offT;      // [nchans][ndms_pad] word offsets of each DM
+    const int32_t *baseT;     // [ndm_tiles][nchans] first word of each staged window
+    int64_t pitch;            // samples per row of src
     int64_t nout;
     int64_t out_offset;
     int64_t block_start;
-    int32_t src_u16;
     int32_t ndms;
+    int32_t ndms_pad;
+    int32_t ndm_tiles;
     int32_t stage_chans;
     int32_t row_words;
-    int32_t ndm_tiles;
-    int32_t ndms_pad;
+    int32_t widen_every;
 };
 
 struct FwdArgs {
@@ -167,16 +189,41 @@ struct FwdArgs {
     int32_t nchans;
 };
 
-__device__ __forceinline__ uint32_t sample_at(const RangeArgs &R, int64_t c, int64_t t)
+// Barrier for LDS traffic only: outstanding global loads (the prefetch of
+// the next stage) stay in flight.
+__device__ __forceinline__ void lds_barrier()
 {
-    if (t >= R.nbin)
-        return 0u;
-    if (R.src_u16)
-        return static_cast<const uint16_t *>(R.src)[c * R.src_stride + t];
-    return static_cast<const uint8_t *>(R.src)[c * R.src_stride + t];
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__global__ __launch_bounds__(kBlock) void k_dedisp_u8(const FwdArgs a)
+__device__ __forceinline__ void wait_loads()
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// Start the direct-to-LDS loads of the windows of channels [cs, cs + cn)
+// into the A copy at `buf` (row j at buf + j*Wr).  One wave instruction
+// moves 64 lanes x 16 bytes of one row.
+__device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int tile, int64_t t0,
+                                            int cs, int cn, uint32_t *buf, int wave, int lane)
+{
+    const int Wr = R.row_words;
+    const int chunks = Wr >> 2;
+    const int ipr = (chunks + kWave - 1) / kWave;
+    for (int i = wave; i < cn * ipr; i += kWavesPerBlock) {
+        const int j = i / ipr;
+        const int part = i - j * ipr;
+        const int q = part * kWave + lane;
+        const int64_t c = cs + j;
+        const int32_t w0 = R.baseT[int64_t(tile) * nchans + c];
+        if (q < chunks) {
+            const uint16_t *g = R.src + c * R.pitch + t0 + 2 * int64_t(w0) + 8 * q;
+            __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
 {
     extern __shared__ uint32_t lds[];
 
@@ -202,12 +249,12 @@ __global__ __launch_bounds__(kBlock) void k_dedisp_u8(const FwdArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int ndms = R.ndms;
     const int dpad = R.ndms_pad;
-    const int ntiles = R.ndm_tiles;
     const int dw0 = d0 + wave * kDW;
     const int nchans = a.nchans;
     const int C = R.stage_chans;
-    const int Cp = (C + 1) & ~1;
-    const int Lw = R.row_words;
+    const int Wr = R.row_words;
+    const int CW = C * Wr;              // words of one copy of a stage
+    const int nst = (nchans + C - 1) / C;
 
     uint32_t acc16[kDW][kNW];
     int32_t acc32[kDW][kNW][2];
@@ -220,63 +267,80 @@ __global__ __launch_bounds__(kBlock) void k_dedisp_u8(const FwdArgs a)
             acc32[dd][k][1] = 0;
         }
 
-    for (int c0 = 0; c0 < nchans; c0 += C) {
+    stage_issue(R, nchans, tile, t0, 0, min(C, nchans), lds, wave, lane);
+    for (int st = 0; st < nst; ++st) {
+        const int c0 = st * C;
         const int cn = min(C, nchans - c0);
-        // Stage the channel windows (rows past the last channel are zero).
-        for (int j = 0; j < Cp; ++j) {
-            uint32_t *P0 = lds + (2 * j) * Lw;
-            uint32_t *P1 = P0 + Lw;
-            if (j < cn) {
-                const int64_t c = c0 + j;
-                const int64_t tb = t0 + R.baseT[c * ntiles + tile];
-                for (int m = tid; m < Lw; m += kBlock) {
-                    const int64_t t = tb + 2 * m;
-                    const uint32_t v0 = sample_at(R, c, t);
-                    const uint32_t v1 = sample_at(R, c, t + 1);
-                    const uint32_t v2 = sample_at(R, c, t + 2);
-                    P0[m] = v0 | (v1 << 16);
-                    P1[m] = v1 | (v2 << 16);
-                }
-            } else {
-                for (int m = tid; m < Lw; m += kBlock) {
-                    P0[m] = 0u;
-                    P1[m] = 0u;
-                }
-            }
-        }
-        __syncthreads();
+        uint32_t *A = lds + (st & 1) * (2 * CW);
+        uint32_t *B = A + CW;
 
-        for (int jp = 0; jp < Cp; jp += 2) {
+        wait_loads();
+        lds_barrier();
+        // Odd-aligned copy: B[j][m] = (A[j][m] >> 16) | (A[j][m+1] << 16),
+        // four words per thread and step.
+        const int quads = Wr >> 2;
+        for (int g = tid; g < cn * quads; g += kBlock) {
+            const int j = g / quads;
+            const int m = (g - j * quads) * 4;
+            const uint32_t *src = A + j * Wr + m;
+            const uint4 v = *reinterpret_cast<const uint4 *>(src);
+            const uint32_t nx = src[4];
+            uint4 o;
+            o.x = __builtin_amdgcn_alignbyte(v.y, v.x, 2);
+            o.y = __builtin_amdgcn_alignbyte(v.z, v.y, 2);
+            o.z = __builtin_amdgcn_alignbyte(v.w, v.z, 2);
+            o.w = __builtin_amdgcn_alignbyte(nx, v.w, 2);
+            *reinterpret_cast<uint4 *>(B + j * Wr + m) = o;
+        }
+        if (st + 1 < nst) {
+            const int cs = c0 + C;
+            stage_issue(R, nchans, tile, t0, cs, min(C, nchans - cs),
+                        lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+        }
+        lds_barrier();
+
+        for (int jp = 0; jp < cn; jp += 2) {
             // Offsets of this wave's DMs in the two staged channels; the
             // table is padded so the 8 entries are aligned and in bounds.
             const int32_t *oa = R.offT + int64_t(c0 + jp) * dpad + dw0;
-            const int32_t *ob = jp + 1 < cn ? oa + dpad : oa;
             const int4 a0 = *reinterpret_cast<const int4 *>(oa);
             const int4 a1 = *reinterpret_cast<const int4 *>(oa + 4);
-            const int4 b0 = *reinterpret_cast<const int4 *>(ob);
-            const int4 b1 = *reinterpret_cast<const int4 *>(ob + 4);
             const int offa[kDW] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-            const int offb[kDW] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-            const uint32_t *rowa = lds + (2 * jp) * Lw + lane;
-            const uint32_t *rowb = rowa + 2 * Lw;
+            const uint32_t *rowa = A + jp * Wr + lane;
+            if (jp + 1 < cn) {
+                const int32_t *ob = oa + dpad;
+                const int4 b0 = *reinterpret_cast<const int4 *>(ob);
+                const int4 b1 = *reinterpret_cast<const int4 *>(ob + 4);
+                const int offb[kDW] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                const uint32_t *rowb = rowa + Wr;
 #pragma unroll
-            for (int dd = 0; dd < kDW; ++dd) {
-                const uint32_t *pa = rowa + offa[dd];
-                const uint32_t *pb = rowb + offb[dd];
+                for (int dd = 0; dd < kDW; ++dd) {
+                    const uint32_t *pa = rowa + offa[dd];
+                    const uint32_t *pb = rowb + offb[dd];
 #pragma unroll
-                for (int k = 0; k < kNW; ++k)
-                    acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                    for (int k = 0; k < kNW; ++k)
+                        acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                }
+            } else {
+#pragma unroll
+                for (int dd = 0; dd < kDW; ++dd) {
+                    const uint32_t *pa = rowa + offa[dd];
+#pragma unroll
+                    for (int k = 0; k < kNW; ++k)
+                        acc16[dd][k] += pa[kWave * k];
+                }
             }
         }
+        if ((st + 1) % R.widen_every == 0 || st + 1 == nst) {
 #pragma unroll
-        for (int dd = 0; dd < kDW; ++dd)
+            for (int dd = 0; dd < kDW; ++dd)
 #pragma unroll
-            for (int k = 0; k < kNW; ++k) {
-                acc32[dd][k][0] += int32_t(acc16[dd][k] & 0xffffu);
-                acc32[dd][k][1] += int32_t(acc16[dd][k] >> 16);
-                acc16[dd][k] = 0u;
-            }
-        __syncthreads();
+                for (int k = 0; k < kNW; ++k) {
+                    acc32[dd][k][0] += int32_t(acc16[dd][k] & 0xffffu);
+                    acc32[dd][k][1] += int32_t(acc16[dd][k] >> 16);
+                    acc16[dd][k] = 0u;
+                }
+        }
     }
 
 #pragma unroll
@@ -310,19 +374,20 @@ dd_status launch_check(const char *what)
 
 dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t stream)
 {
-    // Binned copies, each from its source level, in increasing order.
+    // 16-bit copies, each from its source level (or the raw input), in
+    // increasing downsample order.
     for (const dd::BinLevel &lv : p.levels) {
         uint16_t *dst = reinterpret_cast<uint16_t *>(d_ws + lv.ws_offset);
-        const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 255) / 256, 1024)),
-                        unsigned(p.nchans));
+        const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 1023) / 1024, 1024)),
+                        unsigned(std::min<int32_t>(p.nchans, 65535)));
         if (lv.src < 0) {
             hipLaunchKernelGGL(k_bin_u16<uint8_t>, grid, dim3(256), 0, stream, d_in, p.nsamp,
-                               dst, lv.nbin, lv.factor);
+                               dst, lv.pitch, lv.nbin, lv.factor, p.nchans);
         } else {
             const dd::BinLevel &sl = p.levels[lv.src];
             const uint16_t *src = reinterpret_cast<const uint16_t *>(d_ws + sl.ws_offset);
-            hipLaunchKernelGGL(k_bin_u16<uint16_t>, grid, dim3(256), 0, stream, src, sl.nbin,
-                               dst, lv.nbin, lv.factor);
+            hipLaunchKernelGGL(k_bin_u16<uint16_t>, grid, dim3(256), 0, stream, src, sl.pitch,
+                               dst, lv.pitch, lv.nbin, lv.factor, p.nchans);
         }
         dd_status st = launch_check("k_bin_u16");
         if (st != DD_OK)
@@ -331,8 +396,8 @@ dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t str
     return DD_OK;
 }
 
-dd_status sum_u8(const Plan &p, const DeviceTables &t, const uint8_t *d_in, int32_t *d_out,
-                 const char *d_ws, hipStream_t stream)
+dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const char *d_ws,
+                 hipStream_t stream)
 {
     FwdArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -343,28 +408,21 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, const uint8_t *d_in, int3
     a.nchans = p.nchans;
     for (size_t i = 0; i < p.ranges.size(); ++i) {
         const RangeInfo &ri = p.ranges[i];
+        const dd::BinLevel &lv = p.levels[ri.level];
         RangeArgs &R = a.r[i];
-        if (ri.level < 0) {
-            R.src = d_in;
-            R.src_stride = p.nsamp;
-            R.src_u16 = 0;
-        } else {
-            const dd::BinLevel &lv = p.levels[ri.level];
-            R.src = d_ws + lv.ws_offset;
-            R.src_stride = lv.nbin;
-            R.src_u16 = 1;
-        }
+        R.src = reinterpret_cast<const uint16_t *>(d_ws + lv.ws_offset);
+        R.pitch = lv.pitch;
         R.offT = t.offT + ri.off_offset;
         R.baseT = t.baseT + ri.base_offset;
-        R.ndms_pad = ri.ndms_pad;
-        R.nbin = ri.nbin;
         R.nout = ri.nout;
         R.out_offset = ri.out_offset;
         R.block_start = ri.block_start;
         R.ndms = ri.ndms;
+        R.ndms_pad = ri.ndms_pad;
+        R.ndm_tiles = ri.ndm_tiles;
         R.stage_chans = ri.stage_chans;
         R.row_words = ri.row_words;
-        R.ndm_tiles = ri.ndm_tiles;
+        R.widen_every = ri.widen_every;
     }
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
@@ -404,6 +462,10 @@ dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float 
     if (ws_bytes < p.ws_bytes || (p.ws_bytes > 0 && !d_ws)) {
         dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
                       std::to_string(p.ws_bytes));
+        return DD_ERR_WORKSPACE;
+    }
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+        dd::set_error("workspace must be 256-byte aligned");
         return DD_ERR_WORKSPACE;
     }
     return DD_OK;
@@ -469,8 +531,8 @@ dd_status dd_forward_sum(const dd_plan *plan, const void *d_in, const float *d_w
     st = device_tables(plan->p, &t);
     if (st != DD_OK)
         return st;
-    return sum_u8(plan->p, *t, static_cast<const uint8_t *>(d_in), static_cast<int32_t *>(d_out),
-                  static_cast<const char *>(d_ws), static_cast<hipStream_t>(stream));
+    return sum_u8(plan->p, *t, static_cast<int32_t *>(d_out), static_cast<const char *>(d_ws),
+                  static_cast<hipStream_t>(stream));
 }
 
 dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weights, void *d_out,
@@ -489,8 +551,7 @@ dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weigh
     st = bin_u8(plan->p, static_cast<const uint8_t *>(d_in), static_cast<char *>(d_ws), s);
     if (st != DD_OK)
         return st;
-    return sum_u8(plan->p, *t, static_cast<const uint8_t *>(d_in), static_cast<int32_t *>(d_out),
-                  static_cast<const char *>(d_ws), s);
+    return sum_u8(plan->p, *t, static_cast<int32_t *>(d_out), static_cast<const char *>(d_ws), s);
 }
 
 }  // extern "C"

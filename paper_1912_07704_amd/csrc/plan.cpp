@@ -166,45 +166,10 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         }
         p->out_elems = out_off;
 
-        // Binned copies: one per distinct downsample > 1, each binned from the
-        // largest earlier level that divides it (or from the raw input).
-        const size_t elem = dtype == DD_U8 ? sizeof(uint16_t) : sizeof(float);
-        std::vector<int32_t> dss;
-        for (const RangeInfo &ri : p->ranges)
-            if (ri.ds > 1)
-                dss.push_back(ri.ds);
-        std::sort(dss.begin(), dss.end());
-        dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
-        p->levels.clear();
-        size_t ws = 0;
-        for (int32_t ds : dss) {
-            BinLevel lv;
-            lv.ds = ds;
-            lv.src = -1;
-            lv.factor = ds;
-            for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
-                if (ds % p->levels[j].ds == 0) {
-                    lv.src = j;
-                    lv.factor = ds / p->levels[j].ds;
-                    break;
-                }
-            lv.nbin = nsamp / ds;
-            lv.ws_offset = ws;
-            lv.bytes = size_t(nchans) * size_t(lv.nbin) * elem;
-            ws = align_up(ws + lv.bytes, kWsAlign);
-            p->levels.push_back(lv);
-        }
-        for (RangeInfo &ri : p->ranges) {
-            ri.level = -1;
-            for (size_t j = 0; j < p->levels.size(); ++j)
-                if (p->levels[j].ds == ri.ds)
-                    ri.level = int32_t(j);
-        }
-        p->ws_bytes = ws;
-
         // Tile strategy: a time tile of kTimeTile samples by a DM tile of
-        // kDmTile trials per workgroup; channels are staged in LDS in groups
-        // small enough that 16-bit partial sums cannot carry.
+        // kDmTile trials per workgroup.  Channels are staged in LDS in groups
+        // (double-buffered, two copies each), and the 16-bit partial sums are
+        // widened before 65535/(255*ds) channels have been added.
         int64_t blocks = 0;
         size_t lds = 0;
         for (int32_t r = 0; r < nranges; ++r) {
@@ -218,16 +183,17 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
                     span = std::max(span, s1[c] - s0[c]);
             }
             ri.span = span;
-            ri.row_words = 64 * kWaveWords + span / 2 + 1;
-            int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
+            const int32_t imax = 64 * kWaveWords + 2 + ((span + 1) >> 1);
+            ri.row_words = (imax + 2 + 3) / 4 * 4;
+            const int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
             int32_t stage = std::max(1, std::min(kMaxStageChans, cap));
             if (stage > 1)
                 stage &= ~1;
             auto bytes_for = [&](int32_t st) {
-                return size_t(2) * size_t((st + 1) & ~1) * size_t(ri.row_words) * 4;
+                return size_t(16) * size_t(st) * size_t(ri.row_words);
             };
-            while (stage > 2 && bytes_for(stage) > 64 * 1024)
-                stage -= 2;
+            while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
+                stage = stage > 2 ? stage - 2 : 1;
             if (bytes_for(stage) > kMaxLdsBytes) {
                 *err = fmt("range ", r, ": delay spread ", span,
                            " inside one DM tile needs more LDS than a workgroup has; use a "
@@ -235,19 +201,61 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
                 return DD_ERR_INVALID;
             }
             ri.stage_chans = stage;
+            ri.widen_every = std::max(1, cap / stage);
             lds = std::max(lds, bytes_for(stage));
             ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
             ri.ndm_tiles = (ri.ndms + kDmTile - 1) / kDmTile;
+            ri.ndms_pad = ri.ndm_tiles * kDmTile;
             ri.block_start = blocks;
             blocks += ri.ntime_tiles * ri.ndm_tiles;
         }
         p->blocks = blocks;
         p->lds_bytes = lds;
 
+        // 16-bit copies of the input: one per distinct downsample (1 included),
+        // each binned from the largest earlier level (ds > 1) that divides it,
+        // or from the raw input.
+        const size_t elem = dtype == DD_U8 ? sizeof(uint16_t) : sizeof(float);
+        std::vector<int32_t> dss;
+        for (const RangeInfo &ri : p->ranges)
+            dss.push_back(ri.ds);
+        std::sort(dss.begin(), dss.end());
+        dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
+        p->levels.clear();
+        size_t ws = 0;
+        for (int32_t ds : dss) {
+            BinLevel lv;
+            lv.ds = ds;
+            lv.src = -1;
+            lv.factor = ds;
+            for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
+                if (p->levels[j].ds > 1 && ds % p->levels[j].ds == 0) {
+                    lv.src = j;
+                    lv.factor = ds / p->levels[j].ds;
+                    break;
+                }
+            lv.nbin = nsamp / ds;
+            lv.pitch = (lv.nbin + 8 + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+            int32_t reach = 0;     // samples the staging may read past a row start + nbin
+            for (const RangeInfo &ri : p->ranges)
+                if (ri.ds == ds)
+                    reach = std::max(reach, 2 * ri.row_words + 16);
+            lv.ws_offset = ws;
+            lv.bytes = (size_t(nchans) * size_t(lv.pitch) + size_t(reach)) * elem;
+            ws = align_up(ws + lv.bytes, kWsAlign);
+            p->levels.push_back(lv);
+        }
+        for (RangeInfo &ri : p->ranges) {
+            ri.level = -1;
+            for (size_t j = 0; j < p->levels.size(); ++j)
+                if (p->levels[j].ds == ri.ds)
+                    ri.level = int32_t(j);
+        }
+        p->ws_bytes = ws;
+
         // Device tables of the integer kernel (see plan.h).
         size_t noff = 0, nbase = 0;
         for (RangeInfo &ri : p->ranges) {
-            ri.ndms_pad = ri.ndm_tiles * kDmTile;
             ri.off_offset = noff;
             ri.base_offset = nbase;
             noff += size_t(nchans) * ri.ndms_pad;
@@ -256,16 +264,19 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         p->offT.assign(noff, 0);
         p->baseT.assign(nbase, 0);
         for (RangeInfo &ri : p->ranges) {
+            const int32_t copy_words = ri.stage_chans * ri.row_words;
             for (int32_t c = 0; c < nchans; ++c) {
-                int32_t *base = &p->baseT[ri.base_offset + size_t(c) * ri.ndm_tiles];
                 int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
-                for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile)
-                    base[tile] = p->shifts[size_t(ri.dm_index + tile * kDmTile) * nchans + c];
-                for (int32_t d = 0; d < ri.ndms_pad; ++d) {
-                    const int32_t dv = std::min(d, ri.ndms - 1);
-                    const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] -
-                                      base[dv / kDmTile];
-                    off[d] = (o & 1) * ri.row_words + (o >> 1);
+                for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile) {
+                    const int32_t b = p->shifts[size_t(ri.dm_index + tile * kDmTile) * nchans + c];
+                    const int32_t par = b & 1;
+                    const int32_t e = ((b - par) / 2) & 3;
+                    p->baseT[ri.base_offset + size_t(tile) * nchans + c] = (b - par) / 2 - e;
+                    for (int32_t d = tile * kDmTile; d < (tile + 1) * kDmTile; ++d) {
+                        const int32_t dv = std::min(d, ri.ndms - 1);
+                        const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] - b;
+                        off[d] = ((o + par) & 1) * copy_words + e + ((o + par) >> 1);
+                    }
                 }
             }
         }

@@ -15,22 +15,27 @@ namespace dd {
 // kWaveWords 32-bit words per lane (two samples per word) of one time tile,
 // for kDmPerWave trial DMs; a workgroup holds kWaves wavefronts, one DM
 // group each.
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;
 constexpr int kWaveWords = 4;                    // words per lane
 constexpr int kDmPerWave = 8;
 constexpr int kTimeTile = 128 * kWaveWords;      // samples per workgroup
 constexpr int kDmTile = kWaves * kDmPerWave;     // DMs per workgroup
 constexpr int kMaxStageChans = 16;               // channels staged at once
 constexpr size_t kMaxLdsBytes = 160 * 1024;
+constexpr size_t kLdsTwoBlocks = 80 * 1024;      // LDS that still fits two workgroups per CU
+constexpr int kLevelAlign = 64;                  // samples; row pitch granule of a level
 constexpr size_t kWsAlign = 256;
 
-// One binned copy of the input held in the workspace.
+// One 16-bit copy of the input, binned by ds (ds = 1: the samples widened
+// to 16 bits), held in the workspace as rows of `pitch` samples followed by
+// a tail the staging loads may reach into.
 struct BinLevel {
     int32_t ds = 1;          // total binning factor
     int32_t src = -1;        // index of the level it is binned from (-1 = raw input)
     int32_t factor = 1;      // ds / ds of the source
     int64_t nbin = 0;        // floor(nsamp / ds)
-    size_t ws_offset = 0;    // byte offset in the workspace
+    int64_t pitch = 0;       // samples per row (multiple of kLevelAlign, > nbin)
+    size_t ws_offset = 0;    // byte offset in the workspace (256-byte aligned)
     size_t bytes = 0;
 };
 
@@ -43,11 +48,12 @@ struct RangeInfo {
     int64_t nout = 0;
     int64_t out_offset = 0;      // elements
     int32_t max_shift = 0;
-    int32_t level = -1;          // binned copy used (-1 = raw input)
+    int32_t level = -1;          // 16-bit copy of the input this range reads
     // strategy
     int32_t stage_chans = 0;     // channels per LDS stage
+    int32_t widen_every = 1;     // stages between widenings of the 16-bit sums
     int32_t span = 0;            // largest delay spread inside one DM tile
-    int32_t row_words = 0;       // 32-bit words per staged channel copy
+    int32_t row_words = 0;       // 32-bit words per staged channel copy (multiple of 4)
     int64_t ntime_tiles = 0;
     int32_t ndm_tiles = 0;
     int64_t block_start = 0;     // first workgroup of the range
@@ -64,11 +70,16 @@ struct Plan {
     std::vector<double> freqs;
     std::vector<double> dms;               // [ndms_total]
     std::vector<int32_t> shifts;           // [ndms_total][nchans]
-    // Device tables of the integer kernel, per range, concatenated:
-    //  baseT[c][tile]   delay of the first DM of each DM tile (staging origin)
-    //  offT[c][d]       LDS word offset of DM d inside the staged channel:
-    //                   (o & 1) * row_words + (o >> 1), o = s[d][c] - baseT[c][tile(d)];
-    //                   DMs past the last (up to ndms_pad) repeat the last one.
+    // Device tables of the integer kernel, per range, concatenated.  With
+    // b = s[d0][c] the delay of the first DM d0 of a DM tile, p = b & 1 and
+    // e = ((b - p)/2) & 3:
+    //  baseT[tile][c]  first 32-bit word of the staged window, relative to
+    //                  sample t0 of the time tile: (b - p)/2 - e  (so the
+    //                  window starts 16-byte aligned);
+    //  offT[c][d]      word offset of DM d inside the staged channel:
+    //                  ((o + p) & 1) * stage_chans * row_words + e + ((o + p) >> 1),
+    //                  o = s[d][c] - b; the first term picks the odd-aligned
+    //                  copy.  DMs past the last (up to ndms_pad) repeat the last.
     std::vector<int32_t> baseT;
     std::vector<int32_t> offT;
     std::vector<RangeInfo> ranges;

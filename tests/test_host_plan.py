@@ -64,9 +64,9 @@ def test_ska_plan_sizes_and_workspace():
     p = plan_of(w)
     assert p.out_elems == 536529400
     assert p.overlap == 22560
-    # binned uint16 copies for ds = 2, 4, 8, 16 (each 256-byte aligned)
-    want = sum(4096 * (w.nsamp // ds) * 2 for ds in (2, 4, 8, 16))
-    assert want <= p.workspace_bytes < want + 4 * 256
+    # 16-bit copies for ds = 1, 2, 4, 8, 16 (padded rows)
+    want = sum(4096 * (w.nsamp // ds) * 2 for ds in (1, 2, 4, 8, 16))
+    assert want <= p.workspace_bytes < want * 1.01
     assert p.strategy["workgroups"] > 8 * 256
 
 
