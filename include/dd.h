@@ -159,7 +159,8 @@ dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_
  * management": modules request GPU memory before it is allocated).  For
  * DD_U8 it holds one 16-bit copy of the input per distinct downsample of
  * the plan (1 included): the samples, or the sums of ds adjacent samples,
- * in padded rows.  The workspace passed to a compute call must be at least
+ * in padded rows.  For DD_F32 it holds the weighted float32 copies and the
+ * buffers of dd_adjoint.  The workspace passed to a compute call must be at least
  * this large and 256-byte aligned (DD_ERR_WORKSPACE otherwise).
  */
 dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes);
@@ -184,7 +185,7 @@ dd_status dd_plan_prepare(dd_plan *plan);
  *                 scratch; d_ws may be NULL when that size is 0).
  *   stream        hipStream_t as void*.
  * DD_U8 sums are exact in int32.  DD_F32 sums are formed in float32 in a
- * fixed, call-independent order.
+ * fixed, call-independent order (weights applied to each binned sample).
  * Errors: DD_ERR_NULL, DD_ERR_DTYPE, DD_ERR_CAPACITY, DD_ERR_WORKSPACE,
  * DD_ERR_HIP, DD_ERR_NOMEM.
  */
@@ -194,21 +195,45 @@ dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weigh
 
 /*
  * The two steps of dd_forward, for callers that schedule or time them
- * separately (same arguments and errors as dd_forward):
- *   dd_forward_bin  writes the binned copies of d_in that ranges with
- *                   downsample > 1 read into the workspace (nothing to do,
- *                   and DD_OK, when the workspace size is 0);
- *   dd_forward_sum  the shift-and-sum of every range into d_out; the
- *                   workspace must hold what dd_forward_bin wrote for the
- *                   same d_in, and be unchanged since.
+ * separately:
+ *   dd_forward_bin  writes into the workspace the copies of d_in the ranges
+ *                   read: one per distinct downsample, binned by summing ds
+ *                   samples (uint16 for DD_U8; float32 multiplied by
+ *                   d_weights for DD_F32, NULL = ones).  Same argument rules
+ *                   as dd_forward.
+ *   dd_forward_sum  the shift-and-sum of every range into d_out, reading
+ *                   only the workspace, which must hold what dd_forward_bin
+ *                   wrote and be unchanged since.
  * dd_forward(...) is dd_forward_bin followed by dd_forward_sum on the same
  * stream.
  */
-dd_status dd_forward_bin(const dd_plan *plan, const void *d_in, void *d_ws, size_t ws_bytes,
-                         void *stream);
-dd_status dd_forward_sum(const dd_plan *plan, const void *d_in, const float *d_weights,
-                         void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
-                         void *stream);
+dd_status dd_forward_bin(const dd_plan *plan, const void *d_in, const float *d_weights,
+                         void *d_ws, size_t ws_bytes, void *stream);
+dd_status dd_forward_sum(const dd_plan *plan, void *d_out, int64_t out_capacity, void *d_ws,
+                         size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of the DD_F32 forward (the transpose of the linear map x -> out
+ * for fixed weights, and its derivative in the weights), for the gradient
+ * of a loss L given g = dL/dout:
+ *   G_r[c][tau] = sum_{d in r, 0 <= tau - s[d][c] < nout_r} g_r[d][tau - s[d][c]]
+ *   d_grad_in[c][t] = w_c * sum_r G_r[c][floor(t/ds_r)]  (t < ds_r*nbin_r terms)
+ *   d_grad_w[c]     = sum_t x[c][t] * sum_r G_r[c][floor(t/ds_r)]
+ *   d_grad_out  [out_elems] float32, the layout of dd_forward's output.
+ *   d_in        [nchans][nsamp] float32 input of the forward (needed when
+ *               d_grad_w is not NULL).
+ *   d_weights   [nchans] or NULL (ones).
+ *   d_grad_in   [nchans][nsamp] float32, overwritten; NULL to skip.
+ *   d_grad_w    [nchans] float32, overwritten; NULL to skip.
+ *   d_ws        workspace as for dd_forward (the adjoint uses its own part).
+ * Sums are formed in float32 in a fixed order (the weight gradient by
+ * fixed-shape tree reductions), so results do not depend on scheduling.
+ * Errors: DD_ERR_NULL, DD_ERR_DTYPE (DD_U8 plan), DD_ERR_WORKSPACE,
+ * DD_ERR_HIP, DD_ERR_NOMEM.
+ */
+dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *d_in,
+                     const float *d_weights, float *d_grad_in, float *d_grad_w, void *d_ws,
+                     size_t ws_bytes, void *stream);
 
 /* Text of a status code (static storage). */
 const char *dd_status_str(dd_status status);

@@ -41,8 +41,10 @@ def lib():
         L.oracle_dedisperse_u8_rows.argtypes = [P, i32, i64, P, f64, P, i32, i32, P, i32]
         L.oracle_dedisperse_u8.argtypes = [P, i32, i64, P, f64, P, i32, P, i64, i32]
         L.oracle_dedisperse_f32.argtypes = [P, i32, i64, P, f64, P, i32, P, P, i64, i32]
+        L.oracle_adjoint_f32.argtypes = [P, i32, i64, P, f64, P, i32, P, P, P, P, i32]
         for f in ("oracle_plan_sizes", "oracle_range_shifts", "oracle_dedisperse_u8_rows",
-                  "oracle_dedisperse_u8", "oracle_dedisperse_f32", "oracle_max_threads"):
+                  "oracle_dedisperse_u8", "oracle_dedisperse_f32", "oracle_adjoint_f32",
+                  "oracle_max_threads"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -122,6 +124,24 @@ def dedisperse_f32(x: np.ndarray, freqs, tsamp, ranges, weights=None,
     if rc:
         raise ValueError(f"oracle_dedisperse_f32 failed ({rc})")
     return out
+
+
+def adjoint_f32(x: np.ndarray, freqs, tsamp, ranges, g: np.ndarray, weights=None,
+                threads: int = 0):
+    """(dX, dw) in double for the concatenated output gradient g."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    rg = _ranges(ranges)
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    dX = np.zeros(x.shape, dtype=np.float64)
+    dw = np.zeros(x.shape[0], dtype=np.float64)
+    rc = lib().oracle_adjoint_f32(_ptr(x), x.shape[0], x.shape[1], _ptr(f), tsamp, _ptr(rg),
+                                  len(rg), None if w is None else _ptr(w), _ptr(g), _ptr(dX),
+                                  _ptr(dw), threads)
+    if rc:
+        raise ValueError(f"oracle_adjoint_f32 failed ({rc})")
+    return dX, dw
 
 
 def max_threads() -> int:

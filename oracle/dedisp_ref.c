@@ -303,3 +303,83 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Adjoint of the float forward (transpose of x -> out for fixed weights, and
+ * the derivative in the weights), in double:
+ *   G_r[c][tau] = sum_{d in r, 0 <= tau - s[d][c] < nout_r} g_r[d][tau - s[d][c]]
+ *   dX[c][ds*tau + k] = w_c * sum_r G_r[c][tau]           (k < ds)
+ *   dw[c] = sum_r sum_tau x_r[c][tau] * G_r[c][tau]
+ * g is the concatenated per-range output gradient (double).  dX is
+ * [nchans][nsamp] double (may be NULL), dw [nchans] double (may be NULL).
+ * OpenMP runs over channels.
+ */
+int oracle_adjoint_f32(const float *x, int32_t nchans, int64_t nsamp,
+                       const double *freqs, double tsamp, const double *ranges,
+                       int32_t nranges, const float *weights, const double *g,
+                       double *dX, double *dw, int32_t nthreads)
+{
+    if (!x || !g || check_common(nchans, nsamp, tsamp, freqs, ranges, nranges))
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    if (dX)
+        memset(dX, 0, sizeof(double) * nchans * nsamp);
+    if (dw)
+        memset(dw, 0, sizeof(double) * nchans);
+    int64_t off = 0;
+    for (int32_t r = 0; r < nranges; ++r) {
+        const double *rg = ranges + 4 * r;
+        const int ds = (int)rg[3];
+        const int64_t nd = range_ndms(rg);
+        int32_t *s = (int32_t *)malloc(sizeof(int32_t) * nd * nchans);
+        if (!s)
+            return -2;
+        range_shifts(freqs, nchans, tsamp, rg, s);
+        const int64_t nbin = nsamp / ds;
+        const int64_t nout = nbin - max_of(s, nd * nchans);
+        if (nout <= 0) {
+            free(s);
+            return -4;
+        }
+        int err = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (int32_t c = 0; c < nchans; ++c) {
+            double *G = (double *)calloc((size_t)nbin, sizeof(double));
+            if (!G) {
+                err = 1;
+                continue;
+            }
+            for (int64_t d = 0; d < nd; ++d) {
+                const double *gr = g + off + d * nout;
+                const int64_t sh = s[d * nchans + c];
+                for (int64_t t = 0; t < nout; ++t)
+                    G[t + sh] += gr[t];
+            }
+            const double w = weights ? (double)weights[c] : 1.0;
+            double acc = 0.0;
+            for (int64_t tau = 0; tau < nbin; ++tau) {
+                double xs = 0.0;
+                for (int k = 0; k < ds; ++k) {
+                    const int64_t t = tau * ds + k;
+                    xs += (double)x[(int64_t)c * nsamp + t];
+                    if (dX)
+                        dX[(int64_t)c * nsamp + t] += w * G[tau];
+                }
+                acc += xs * G[tau];
+            }
+            if (dw)
+                dw[c] += acc;
+            free(G);
+        }
+        free(s);
+        if (err)
+            return -2;
+        off += nd * nout;
+    }
+    return 0;
+}

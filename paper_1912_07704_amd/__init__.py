@@ -136,15 +136,11 @@ def workspace(plan: Plan, device=None):
                        device=device or "cuda")
 
 
-_STEPS = {"all": "dd_forward", "sum": "dd_forward_sum"}
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step="all"):
-    """Forward dedispersion (dd_forward) of a channel-major [nchans, nsamp]
-    CUDA tensor.  Returns the flat output (int32 for u8 plans).
-
-    step="sum" runs only the shift-and-sum (dd_forward_sum); the workspace
-    must then hold what bin_input() wrote for the same input."""
+def _check_input(x, plan):
     import torch
     want = torch.uint8 if plan.dtype == "u8" else torch.float32
     if x.dtype != want or x.dim() != 2 or tuple(x.shape) != (plan.nchans, plan.nsamp):
@@ -152,26 +148,119 @@ def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step
                          f"{x.dtype} {tuple(x.shape)}")
     if not x.is_cuda or not x.is_contiguous():
         raise ValueError("input must be a contiguous device tensor")
+
+
+def _check_weights(weights, plan):
+    import torch
+    if weights is None:
+        return
+    if (weights.dtype != torch.float32 or not weights.is_cuda or not weights.is_contiguous()
+            or weights.numel() != plan.nchans):
+        raise ValueError(f"weights must be a contiguous device float32 tensor of {plan.nchans}")
+
+
+def _out_tensor(plan, out, device):
+    import torch
     odt = torch.int32 if plan.dtype == "u8" else torch.float32
     if out is None:
-        out = torch.empty(plan.out_elems, dtype=odt, device=x.device)
-    elif out.dtype != odt or not out.is_cuda or not out.is_contiguous():
+        return torch.empty(plan.out_elems, dtype=odt, device=device)
+    if out.dtype != odt or not out.is_cuda or not out.is_contiguous():
         raise ValueError(f"out must be a contiguous device {odt} tensor")
-    if ws is None and plan.workspace_bytes:
-        ws = workspace(plan, x.device)
-    wp = ctypes.c_void_p(weights.data_ptr()) if weights is not None else None
-    fn = _STEPS[step]
-    check(getattr(lib(), fn)(plan.handle, ctypes.c_void_p(x.data_ptr()), wp,
-                             ctypes.c_void_p(out.data_ptr()), out.numel(),
-                             ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
-                             ws.numel() if ws is not None else 0, _stream_ptr(stream)), fn)
     return out
 
 
-def bin_input(x, plan: Plan, ws, stream=None):
+def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step="all"):
+    """Forward dedispersion of a channel-major [nchans, nsamp] device tensor
+    (dd_forward).  Returns the flat output: int32 for u8 plans, float32 for
+    f32 plans (per-channel float32 `weights` allowed there).
+
+    step="sum" runs only the shift-and-sum (dd_forward_sum); the workspace
+    must then hold what bin_input() wrote for the same input."""
+    if step not in ("all", "sum"):
+        raise ValueError("step must be 'all' or 'sum'")
+    if step == "all":
+        _check_input(x, plan)
+        _check_weights(weights, plan)
+    out = _out_tensor(plan, out, x.device if x is not None else "cuda")
+    if ws is None:
+        if step == "sum":
+            raise ValueError("step='sum' needs the workspace bin_input() filled")
+        ws = workspace(plan, out.device)
+    if step == "all":
+        check(lib().dd_forward(plan.handle, _ptr(x), _ptr(weights), _ptr(out), out.numel(),
+                               _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_forward")
+    else:
+        check(lib().dd_forward_sum(plan.handle, _ptr(out), out.numel(), _ptr(ws), ws.numel(),
+                                   _stream_ptr(stream)), "dd_forward_sum")
+    return out
+
+
+def bin_input(x, plan: Plan, ws, weights=None, stream=None):
     """The binning step alone (dd_forward_bin) into the workspace ws."""
-    check(lib().dd_forward_bin(plan.handle, ctypes.c_void_p(x.data_ptr()),
-                               ctypes.c_void_p(ws.data_ptr()) if ws is not None else None,
+    _check_input(x, plan)
+    _check_weights(weights, plan)
+    check(lib().dd_forward_bin(plan.handle, _ptr(x), _ptr(weights), _ptr(ws),
                                ws.numel() if ws is not None else 0, _stream_ptr(stream)),
           "dd_forward_bin")
     return ws
+
+
+def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=True, ws=None,
+            stream=None):
+    """Gradients of sum(grad_out * forward(x, w)) for an f32 plan
+    (dd_adjoint).  Returns (dX or None, dw or None)."""
+    import torch
+    if plan.dtype != "f32":
+        raise ValueError("the adjoint is defined for f32 plans")
+    if (grad_out.dtype != torch.float32 or not grad_out.is_cuda or not grad_out.is_contiguous()
+            or grad_out.numel() != plan.out_elems):
+        raise ValueError(f"grad_out must be a contiguous device float32 tensor of {plan.out_elems}")
+    if grad_w:
+        if x is None:
+            raise ValueError("x is needed for the weight gradient")
+        _check_input(x, plan)
+    _check_weights(weights, plan)
+    dev = grad_out.device
+    dx = torch.empty((plan.nchans, plan.nsamp), dtype=torch.float32, device=dev) if grad_in else None
+    dw = torch.empty(plan.nchans, dtype=torch.float32, device=dev) if grad_w else None
+    if ws is None:
+        ws = workspace(plan, dev)
+    check(lib().dd_adjoint(plan.handle, _ptr(grad_out), _ptr(x), _ptr(weights), _ptr(dx),
+                           _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_adjoint")
+    return dx, dw
+
+
+def _autograd_fn():
+    import torch
+
+    class DedispFn(torch.autograd.Function):
+        """out = dedisperse(x, w) with a hand-written adjoint: backward runs
+        dd_adjoint.  Saves (x, w), not the output."""
+
+        @staticmethod
+        def forward(ctx, x, weights, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(x, weights)
+            return dedisperse(x, plan, weights=weights)
+
+        @staticmethod
+        def backward(ctx, g):
+            x, weights = ctx.saved_tensors
+            need_x, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            dx, dw = adjoint(g.contiguous(), ctx.plan, x=x, weights=weights,
+                             grad_in=need_x, grad_w=need_w)
+            return dx, dw, None
+
+    return DedispFn
+
+
+_FN = None
+
+
+def dedisperse_autograd(x, weights, plan: Plan):
+    """Differentiable float32 dedispersion: gradients flow to x and to the
+    per-channel weights through the hand-written HIP adjoint."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_fn()
+    return _FN.apply(x, weights, plan)

@@ -22,8 +22,9 @@ SIGNATURES = {
     "dd_workspace_bytes": (ctypes.c_int, [P, P]),
     "dd_plan_prepare": (ctypes.c_int, [P]),
     "dd_forward": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),
-    "dd_forward_bin": (ctypes.c_int, [P, P, P, SZ, P]),
-    "dd_forward_sum": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),
+    "dd_forward_bin": (ctypes.c_int, [P, P, P, P, SZ, P]),
+    "dd_forward_sum": (ctypes.c_int, [P, P, I64, P, SZ, P]),
+    "dd_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, SZ, P]),
     "dd_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "dd_last_error": (ctypes.c_char_p, []),
 }

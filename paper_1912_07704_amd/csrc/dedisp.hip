@@ -79,18 +79,21 @@ dd_status device_tables(const Plan &p, DeviceTables **out)
         return DD_ERR_NOMEM;
     }
     DeviceTables t;
-    const size_t ob = p.offT.size() * sizeof(int32_t);
-    const size_t bb = p.baseT.size() * sizeof(int32_t);
-    e = hipMalloc(&t.offT, ob + bb);
+    // integer plans use offT/baseT, float plans offF/baseF
+    const std::vector<int32_t> &hoff = p.dtype == DD_U8 ? p.offT : p.offF;
+    const std::vector<int32_t> &hbase = p.dtype == DD_U8 ? p.baseT : p.baseF;
+    const size_t ob = hoff.size() * sizeof(int32_t);
+    const size_t bb = hbase.size() * sizeof(int32_t);
+    e = hipMalloc(&t.offT, ob + bb + 16);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         dd::set_error(std::string("hipMalloc of the delay tables: ") + hipGetErrorString(e));
         return DD_ERR_NOMEM;
     }
-    t.baseT = t.offT + p.offT.size();
-    e = hipMemcpy(t.offT, p.offT.data(), ob, hipMemcpyHostToDevice);
+    t.baseT = t.offT + hoff.size();
+    e = hipMemcpy(t.offT, hoff.data(), ob, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(t.baseT, p.baseT.data(), bb, hipMemcpyHostToDevice);
+        e = hipMemcpy(t.baseT, hbase.data(), bb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(t.offT);
         return hip_fail(e, "hipMemcpy of the delay tables");
@@ -360,6 +363,268 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Float32 path.
+//
+// k_level_f32:     weighted (binned) 32-bit copies of the input,
+//                  dst[c][t] = w_c * sum_{k<f} src[c][f*t + k].
+// k_shiftsum_f32:  out[a][t] = sum_b rows[b][t + S[a][b]], the forward (a =
+//                  DM, b = channel) and the adjoint (a = channel, b = DM over
+//                  zero-padded output-gradient rows, S = P - s).  Staging as
+//                  in the integer kernel (direct global-to-LDS loads,
+//                  double-buffered), one float per sample, lane l holding
+//                  t0 + l + 64k; two rows are added per step in a fixed order.
+// k_pad_rows_f32:  the output gradient of one range with P zeros in front.
+// k_adj_finalize:  dX[c][t] = w_c * G[c][t], G summed over ranges at each
+//                  range's resolution, and per-chunk partials of
+//                  dw_c = sum_t x[c][t] * G[c][t] (fixed-order tree sums).
+// k_reduce_rows:   dw_c = sum of its chunk partials (fixed-order tree).
+// ---------------------------------------------------------------------------
+
+constexpr int kFW = dd::kF32Words;
+constexpr int kFP = dd::kF32PerWave;
+constexpr int kFTileT = dd::kF32TimeTile;
+constexpr int kFTileA = dd::kF32OutTile;
+
+__global__ __launch_bounds__(256) void k_level_f32(const float *__restrict__ src, int64_t src_pitch,
+                                                   const float *__restrict__ w,
+                                                   float *__restrict__ dst, int64_t dst_pitch,
+                                                   int64_t nbin, int factor, int nchans)
+{
+    for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y) {
+        const float *row = src + c * src_pitch;
+        float *out = dst + c * dst_pitch;
+        const float wc = w ? w[c] : 1.0f;
+        for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nbin;
+             t += int64_t(gridDim.x) * blockDim.x) {
+            const float *p = row + t * factor;
+            float s = 0.0f;
+            for (int k = 0; k < factor; ++k)
+                s += p[k];
+            out[t] = w ? wc * s : s;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ g, int64_t nout,
+                                                      int64_t P, float *__restrict__ gpad,
+                                                      int64_t gpitch, int nrows)
+{
+    for (int64_t d = blockIdx.y; d < nrows; d += gridDim.y) {
+        const float *row = g + d * nout;
+        float *out = gpad + d * gpitch;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < gpitch;
+             i += int64_t(gridDim.x) * blockDim.x)
+            out[i] = (i >= P && i < P + nout) ? row[i - P] : 0.0f;
+    }
+}
+
+struct SumArgs {
+    const float *src;         // rows, `pitch` floats apart
+    const int32_t *off;       // [nrows][nouts_pad]
+    const int32_t *base;      // [nout_tiles][nrows]
+    float *dst;               // output rows, `dst_pitch` floats apart
+    int64_t pitch;
+    int64_t dst_pitch;
+    int64_t nt;
+    int64_t block_start;
+    int32_t nrows;
+    int32_t nouts;
+    int32_t nouts_pad;
+    int32_t nout_tiles;
+    int32_t stage_rows;
+    int32_t row_words;
+};
+
+struct SumBatch {
+    SumArgs p[DD_MAX_RANGES];
+    int64_t nblocks;
+    int64_t per_xcd;
+    int32_t nprob;
+};
+
+__device__ __forceinline__ void stage_issue_f32(const SumArgs &R, int tile, int64_t t0, int bs,
+                                                int bn, float *buf, int wave, int lane)
+{
+    const int Wr = R.row_words;
+    const int chunks = Wr >> 2;
+    const int ipr = (chunks + kWave - 1) / kWave;
+    for (int i = wave; i < bn * ipr; i += kWavesPerBlock) {
+        const int j = i / ipr;
+        const int part = i - j * ipr;
+        const int q = part * kWave + lane;
+        const int64_t b = bs + j;
+        const int32_t m = R.base[int64_t(tile) * R.nrows + b];
+        if (q < chunks) {
+            const float *g = R.src + b * R.pitch + t0 + m + 4 * q;
+            __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_shiftsum_f32(const SumBatch a)
+{
+    extern __shared__ float ldsf[];
+    const int64_t bid = blockIdx.x;
+    const int64_t L = (bid % kXcds) * a.per_xcd + bid / kXcds;
+    if (L >= a.nblocks)
+        return;
+    int r = 0;
+    for (int i = 1; i < a.nprob; ++i)
+        if (L >= a.p[i].block_start)
+            r = i;
+    const SumArgs &R = a.p[r];
+    const int64_t lb = L - R.block_start;
+    const int64_t tt = lb / R.nout_tiles;
+    const int tile = int(lb - tt * R.nout_tiles);
+    const int64_t t0 = tt * kFTileT;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int aw0 = tile * kFTileA + wave * kFP;
+    const int C = R.stage_rows;
+    const int Wr = R.row_words;
+    const int CW = C * Wr;
+    const int nrows = R.nrows;
+    const int npad = R.nouts_pad;
+    const int nst = (nrows + C - 1) / C;
+
+    float acc[kFP][kFW];
+#pragma unroll
+    for (int dd = 0; dd < kFP; ++dd)
+#pragma unroll
+        for (int k = 0; k < kFW; ++k)
+            acc[dd][k] = 0.0f;
+
+    stage_issue_f32(R, tile, t0, 0, min(C, nrows), ldsf, wave, lane);
+    for (int st = 0; st < nst; ++st) {
+        const int b0 = st * C;
+        const int bn = min(C, nrows - b0);
+        const float *A = ldsf + (st & 1) * CW;
+        wait_loads();
+        lds_barrier();
+        if (st + 1 < nst) {
+            const int bs = b0 + C;
+            stage_issue_f32(R, tile, t0, bs, min(C, nrows - bs), ldsf + ((st + 1) & 1) * CW,
+                            wave, lane);
+        }
+        for (int jp = 0; jp < bn; jp += 2) {
+            static_assert(kFP == 4, "offsets are loaded as one int4 per row");
+            const int32_t *oa = R.off + int64_t(b0 + jp) * npad + aw0;
+            const int4 a0 = *reinterpret_cast<const int4 *>(oa);
+            const int offa[kFP] = {a0.x, a0.y, a0.z, a0.w};
+            const float *rowa = A + jp * Wr + lane;
+            if (jp + 1 < bn) {
+                const int32_t *ob = oa + npad;
+                const int4 b0v = *reinterpret_cast<const int4 *>(ob);
+                const int offb[kFP] = {b0v.x, b0v.y, b0v.z, b0v.w};
+                const float *rowb = rowa + Wr;
+#pragma unroll
+                for (int dd = 0; dd < kFP; ++dd) {
+                    const float *pa = rowa + offa[dd];
+                    const float *pb = rowb + offb[dd];
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k)
+                        acc[dd][k] += pa[kWave * k] + pb[kWave * k];
+                }
+            } else {
+#pragma unroll
+                for (int dd = 0; dd < kFP; ++dd) {
+                    const float *pa = rowa + offa[dd];
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k)
+                        acc[dd][k] += pa[kWave * k];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int dd = 0; dd < kFP; ++dd) {
+        const int ao = aw0 + dd;
+        if (ao >= R.nouts)
+            break;
+        float *row = R.dst + int64_t(ao) * R.dst_pitch;
+#pragma unroll
+        for (int k = 0; k < kFW; ++k) {
+            const int64_t t = t0 + lane + kWave * k;
+            if (t < R.nt)
+                row[t] = acc[dd][k];
+        }
+    }
+}
+
+struct FinRange {
+    const float *G;
+    int64_t Gpitch;
+    int64_t nbin;
+    int32_t ds;
+    int32_t pad_;
+};
+
+struct FinArgs {
+    FinRange r[DD_MAX_RANGES];
+    const float *x;
+    const float *w;
+    float *dX;
+    float *partial;
+    int64_t nsamp;
+    int64_t chunk_len;
+    int32_t nranges;
+    int32_t nchunks;
+};
+
+__global__ __launch_bounds__(256) void k_adj_finalize(const FinArgs a)
+{
+    __shared__ float red[256];
+    const int64_t c = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int64_t t_begin = int64_t(chunk) * a.chunk_len;
+    const int64_t t_end = min(a.nsamp, t_begin + a.chunk_len);
+    const float wc = a.w ? a.w[c] : 1.0f;
+    float acc = 0.0f;
+    for (int64_t t = t_begin + threadIdx.x; t < t_end; t += 256) {
+        float g = 0.0f;
+        for (int r = 0; r < a.nranges; ++r) {
+            const FinRange &R = a.r[r];
+            if (t < int64_t(R.ds) * R.nbin)
+                g += R.G[c * R.Gpitch + t / R.ds];
+        }
+        if (a.dX)
+            a.dX[c * a.nsamp + t] = wc * g;
+        if (a.x)
+            acc += a.x[c * a.nsamp + t] * g;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        a.partial[c * a.nchunks + chunk] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_rows(const float *__restrict__ partial, int n,
+                                                     float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int64_t c = blockIdx.x;
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256)
+        acc += partial[c * n + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[c] = red[0];
+}
+
 dd_status launch_check(const char *what)
 {
     if (fault_requested("launch")) {
@@ -435,6 +700,148 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
     return launch_check("k_dedisp_u8");
 }
 
+
+dd_status bin_f32(const Plan &p, const float *d_in, const float *d_w, char *d_ws, hipStream_t stream)
+{
+    for (const dd::BinLevel &lv : p.levels) {
+        float *dst = reinterpret_cast<float *>(d_ws + lv.ws_offset);
+        const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 255) / 256, 1024)),
+                        unsigned(std::min<int32_t>(p.nchans, 65535)));
+        if (lv.src < 0) {
+            hipLaunchKernelGGL(k_level_f32, grid, dim3(256), 0, stream, d_in, p.nsamp, d_w, dst,
+                               lv.pitch, lv.nbin, lv.factor, p.nchans);
+        } else {
+            const dd::BinLevel &sl = p.levels[lv.src];
+            const float *src = reinterpret_cast<const float *>(d_ws + sl.ws_offset);
+            hipLaunchKernelGGL(k_level_f32, grid, dim3(256), 0, stream, src, sl.pitch,
+                               static_cast<const float *>(nullptr), dst, lv.pitch, lv.nbin,
+                               lv.factor, p.nchans);
+        }
+        dd_status st = launch_check("k_level_f32");
+        if (st != DD_OK)
+            return st;
+    }
+    return DD_OK;
+}
+
+SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *src, int64_t pitch,
+                 float *dst, int64_t dst_pitch)
+{
+    SumArgs R;
+    std::memset(&R, 0, sizeof(R));
+    R.src = src;
+    R.off = t.offT + sp.off_offset;
+    R.base = t.baseT + sp.base_offset;
+    R.dst = dst;
+    R.pitch = pitch;
+    R.dst_pitch = dst_pitch;
+    R.nt = sp.nt;
+    R.block_start = sp.block_start;
+    R.nrows = sp.nrows;
+    R.nouts = sp.nouts;
+    R.nouts_pad = sp.nouts_pad;
+    R.nout_tiles = sp.nout_tiles;
+    R.stage_rows = sp.stage_rows;
+    R.row_words = sp.row_words;
+    return R;
+}
+
+dd_status launch_sum(SumBatch &a, int64_t blocks, size_t lds, hipStream_t stream)
+{
+    a.nblocks = blocks;
+    a.per_xcd = (blocks + kXcds - 1) / kXcds;
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_shiftsum_f32),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dd::kMaxLdsBytes));
+    });
+    hipLaunchKernelGGL(k_shiftsum_f32, dim3(unsigned(a.per_xcd * kXcds)), dim3(kBlock), lds,
+                       stream, a);
+    return launch_check("k_shiftsum_f32");
+}
+
+dd_status sum_f32(const Plan &p, const DeviceTables &t, float *d_out, const char *d_ws,
+                  hipStream_t stream)
+{
+    SumBatch a;
+    std::memset(&a, 0, sizeof(a));
+    a.nprob = int32_t(p.ranges.size());
+    for (size_t i = 0; i < p.ranges.size(); ++i) {
+        const RangeInfo &ri = p.ranges[i];
+        const dd::BinLevel &lv = p.levels[ri.level];
+        a.p[i] = sum_args(ri.fwd, t, reinterpret_cast<const float *>(d_ws + lv.ws_offset),
+                          lv.pitch, d_out + ri.out_offset, ri.nout);
+    }
+    return launch_sum(a, p.blocks, p.lds_bytes, stream);
+}
+
+dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, const float *d_x,
+                      const float *d_w, float *d_dx, float *d_dw, char *d_ws, hipStream_t stream)
+{
+    SumBatch a;
+    std::memset(&a, 0, sizeof(a));
+    a.nprob = int32_t(p.ranges.size());
+    for (size_t i = 0; i < p.ranges.size(); ++i) {
+        const RangeInfo &ri = p.ranges[i];
+        float *gpad = reinterpret_cast<float *>(d_ws + ri.gpad_offset);
+        const dim3 grid(unsigned(std::min<int64_t>((ri.gpitch + 255) / 256, 1024)),
+                        unsigned(std::min<int32_t>(ri.ndms, 65535)));
+        hipLaunchKernelGGL(k_pad_rows_f32, grid, dim3(256), 0, stream, d_g + ri.out_offset,
+                           ri.nout, int64_t(ri.max_shift), gpad, ri.gpitch, ri.ndms);
+        dd_status st = launch_check("k_pad_rows_f32");
+        if (st != DD_OK)
+            return st;
+        a.p[i] = sum_args(ri.adj, t, gpad, ri.gpitch,
+                          reinterpret_cast<float *>(d_ws + ri.G_offset), ri.Gpitch);
+    }
+    dd_status st = launch_sum(a, p.adj_blocks, p.adj_lds_bytes, stream);
+    if (st != DD_OK)
+        return st;
+    FinArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.nranges = int32_t(p.ranges.size());
+    for (size_t i = 0; i < p.ranges.size(); ++i) {
+        const RangeInfo &ri = p.ranges[i];
+        f.r[i].G = reinterpret_cast<const float *>(d_ws + ri.G_offset);
+        f.r[i].Gpitch = ri.Gpitch;
+        f.r[i].nbin = ri.nbin;
+        f.r[i].ds = ri.ds;
+    }
+    float *partial = reinterpret_cast<float *>(d_ws + p.dw_offset);
+    f.x = d_dw ? d_x : nullptr;
+    f.w = d_w;
+    f.dX = d_dx;
+    f.partial = partial;
+    f.nsamp = p.nsamp;
+    f.chunk_len = p.dw_chunk_len;
+    f.nchunks = p.dw_chunks;
+    hipLaunchKernelGGL(k_adj_finalize, dim3(unsigned(p.dw_chunks), unsigned(p.nchans)), dim3(256),
+                       0, stream, f);
+    st = launch_check("k_adj_finalize");
+    if (st != DD_OK || !d_dw)
+        return st;
+    hipLaunchKernelGGL(k_reduce_rows, dim3(unsigned(p.nchans)), dim3(256), 0, stream, partial,
+                       p.dw_chunks, d_dw);
+    return launch_check("k_reduce_rows");
+}
+
+dd_status forward_bin(const Plan &p, const void *d_in, const float *d_w, char *d_ws,
+                      hipStream_t stream)
+{
+    if (p.dtype == DD_U8)
+        return bin_u8(p, static_cast<const uint8_t *>(d_in), d_ws, stream);
+    return bin_f32(p, static_cast<const float *>(d_in), d_w, d_ws, stream);
+}
+
+dd_status forward_sum(const Plan &p, const DeviceTables &t, void *d_out, const char *d_ws,
+                      hipStream_t stream)
+{
+    if (p.dtype == DD_U8)
+        return sum_u8(p, t, static_cast<int32_t *>(d_out), d_ws, stream);
+    return sum_f32(p, t, static_cast<float *>(d_out), d_ws, stream);
+}
+
 // Argument checks shared by the compute entry points (synchronous, before
 // any HIP call).
 dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float *d_weights,
@@ -450,9 +857,9 @@ dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float 
         dd::set_error("per-channel weights apply to DD_F32 plans only");
         return DD_ERR_DTYPE;
     }
-    if (p.dtype != DD_U8) {
-        dd::set_error("this build computes DD_U8 plans only");
-        return DD_ERR_DTYPE;
+    if (reinterpret_cast<uintptr_t>(d_in) % 4 != 0) {
+        dd::set_error("d_in must be 4-byte aligned");
+        return DD_ERR_INVALID;
     }
     if (need_out && out_capacity < p.out_elems) {
         dd::set_error("out_capacity " + std::to_string(out_capacity) + " < out_elems " +
@@ -507,23 +914,23 @@ dd_status dd_plan_prepare(dd_plan *plan)
     return device_tables(plan->p, &t);
 }
 
-dd_status dd_forward_bin(const dd_plan *plan, const void *d_in, void *d_ws, size_t ws_bytes,
-                         void *stream)
+dd_status dd_forward_bin(const dd_plan *plan, const void *d_in, const float *d_weights,
+                         void *d_ws, size_t ws_bytes, void *stream)
 {
     dd::clear_error();
-    dd_status st = check_forward_args(plan, d_in, nullptr, nullptr, 0, d_ws, ws_bytes, false);
+    dd_status st = check_forward_args(plan, d_in, d_weights, nullptr, 0, d_ws, ws_bytes, false);
     if (st != DD_OK)
         return st;
-    return bin_u8(plan->p, static_cast<const uint8_t *>(d_in), static_cast<char *>(d_ws),
-                  static_cast<hipStream_t>(stream));
+    return forward_bin(plan->p, d_in, d_weights, static_cast<char *>(d_ws),
+                       static_cast<hipStream_t>(stream));
 }
 
-dd_status dd_forward_sum(const dd_plan *plan, const void *d_in, const float *d_weights,
-                         void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
-                         void *stream)
+dd_status dd_forward_sum(const dd_plan *plan, void *d_out, int64_t out_capacity, void *d_ws,
+                         size_t ws_bytes, void *stream)
 {
     dd::clear_error();
-    dd_status st = check_forward_args(plan, d_in, d_weights, d_out, out_capacity, d_ws, ws_bytes,
+    static const char dummy = 0;
+    dd_status st = check_forward_args(plan, &dummy, nullptr, d_out, out_capacity, d_ws, ws_bytes,
                                       true);
     if (st != DD_OK)
         return st;
@@ -531,8 +938,8 @@ dd_status dd_forward_sum(const dd_plan *plan, const void *d_in, const float *d_w
     st = device_tables(plan->p, &t);
     if (st != DD_OK)
         return st;
-    return sum_u8(plan->p, *t, static_cast<int32_t *>(d_out), static_cast<const char *>(d_ws),
-                  static_cast<hipStream_t>(stream));
+    return forward_sum(plan->p, *t, d_out, static_cast<const char *>(d_ws),
+                       static_cast<hipStream_t>(stream));
 }
 
 dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weights, void *d_out,
@@ -548,10 +955,37 @@ dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weigh
     if (st != DD_OK)
         return st;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    st = bin_u8(plan->p, static_cast<const uint8_t *>(d_in), static_cast<char *>(d_ws), s);
+    st = forward_bin(plan->p, d_in, d_weights, static_cast<char *>(d_ws), s);
     if (st != DD_OK)
         return st;
-    return sum_u8(plan->p, *t, static_cast<int32_t *>(d_out), static_cast<const char *>(d_ws), s);
+    return forward_sum(plan->p, *t, d_out, static_cast<const char *>(d_ws), s);
+}
+
+dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *d_in,
+                     const float *d_weights, float *d_grad_in, float *d_grad_w, void *d_ws,
+                     size_t ws_bytes, void *stream)
+{
+    dd::clear_error();
+    if (!plan || !d_grad_out || (d_grad_w && !d_in)) {
+        dd::set_error("plan and d_grad_out must not be NULL, and d_in is needed for d_grad_w");
+        return DD_ERR_NULL;
+    }
+    const Plan &p = plan->p;
+    if (p.dtype != DD_F32) {
+        dd::set_error("the adjoint is defined for DD_F32 plans");
+        return DD_ERR_DTYPE;
+    }
+    if (ws_bytes < p.ws_bytes || !d_ws || reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+        dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
+                      std::to_string(p.ws_bytes) + " or not 256-byte aligned");
+        return DD_ERR_WORKSPACE;
+    }
+    DeviceTables *t = nullptr;
+    dd_status st = device_tables(p, &t);
+    if (st != DD_OK)
+        return st;
+    return adjoint_f32(p, *t, d_grad_out, d_in, d_weights, d_grad_in, d_grad_w,
+                       static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -32,11 +32,159 @@ std::string fmt(A &&...a)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+
+// Tables of one float32 shift-and-sum problem (see plan.h).  S(a, b) gives
+// the delay of row b for output a; it must be >= 0.
+template <typename SFn>
+dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S,
+                            std::vector<int32_t> &offF, std::vector<int32_t> &baseF,
+                            int64_t *blocks, size_t *lds, std::string *err, const char *what)
+{
+    sp.nrows = nrows;
+    sp.nouts = nouts;
+    sp.nt = nt;
+    sp.nout_tiles = (nouts + kF32OutTile - 1) / kF32OutTile;
+    sp.nouts_pad = sp.nout_tiles * kF32OutTile;
+    sp.ntime_tiles = (nt + kF32TimeTile - 1) / kF32TimeTile;
+    int32_t span = 0;
+    std::vector<int32_t> mins(size_t(sp.nout_tiles) * nrows);
+    for (int32_t tile = 0; tile < sp.nout_tiles; ++tile) {
+        const int32_t a0 = tile * kF32OutTile;
+        const int32_t a1 = std::min(nouts, a0 + kF32OutTile);
+        for (int32_t b = 0; b < nrows; ++b) {
+            int32_t lo = S(a0, b), hi = lo;
+            for (int32_t a = a0 + 1; a < a1; ++a) {
+                const int32_t v = S(a, b);
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            mins[size_t(tile) * nrows + b] = lo;
+            span = std::max(span, hi - lo);
+        }
+    }
+    sp.span = span;
+    sp.row_words = (kF32TimeTile + 3 + span + 4 + 3) / 4 * 4;
+    int32_t stage = kF32MaxStage;
+    auto bytes_for = [&](int32_t st) { return size_t(8) * size_t(st) * size_t(sp.row_words); };
+    while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
+        stage = stage > 2 ? stage - 2 : 1;
+    if (bytes_for(stage) > kMaxLdsBytes) {
+        *err = fmt(what, ": delay spread ", span,
+                   " inside one tile needs more LDS than a workgroup has; use a finer DM step");
+        return DD_ERR_INVALID;
+    }
+    sp.stage_rows = stage;
+    *lds = std::max(*lds, bytes_for(stage));
+    sp.block_start = *blocks;
+    *blocks += sp.ntime_tiles * sp.nout_tiles;
+    sp.off_offset = offF.size();
+    sp.base_offset = baseF.size();
+    offF.resize(offF.size() + size_t(nrows) * sp.nouts_pad);
+    baseF.resize(baseF.size() + size_t(sp.nout_tiles) * nrows);
+    for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
+        for (int32_t b = 0; b < nrows; ++b) {
+            const int32_t m = mins[size_t(tile) * nrows + b];
+            const int32_t e = m & 3;
+            baseF[sp.base_offset + size_t(tile) * nrows + b] = m - e;
+            for (int32_t a = tile * kF32OutTile; a < (tile + 1) * kF32OutTile; ++a) {
+                const int32_t av = std::min(a, nouts - 1);
+                offF[sp.off_offset + size_t(b) * sp.nouts_pad + a] = e + S(av, b) - m;
+            }
+        }
+    return DD_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 const char *last_error() { return g_last_error.c_str(); }
+
+
+// Float32 plans: weighted 32-bit level copies, forward and adjoint problems
+// of the generic shift-and-sum, and the adjoint's workspace buffers.
+dd_status build_f32(Plan *p, std::string *err)
+{
+    const int32_t nchans = p->nchans;
+    const int64_t nsamp = p->nsamp;
+    size_t ws = 0;
+    // levels (one per distinct downsample, cascaded like the integer path)
+    std::vector<int32_t> dss;
+    for (const RangeInfo &ri : p->ranges)
+        dss.push_back(ri.ds);
+    std::sort(dss.begin(), dss.end());
+    dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
+    p->levels.clear();
+    p->offF.clear();
+    p->baseF.clear();
+    int64_t blocks = 0, ablocks = 0;
+    size_t lds = 0, alds = 0;
+    for (int32_t r = 0; r < int32_t(p->ranges.size()); ++r) {
+        RangeInfo &ri = p->ranges[r];
+        const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
+        auto Sf = [&](int32_t a, int32_t b) { return sh[size_t(a) * nchans + b]; };
+        dd_status st = build_sum_problem(ri.fwd, nchans, ri.ndms, ri.nout, Sf, p->offF, p->baseF,
+                                         &blocks, &lds, err, "forward");
+        if (st != DD_OK)
+            return st;
+    }
+    for (int32_t r = 0; r < int32_t(p->ranges.size()); ++r) {
+        RangeInfo &ri = p->ranges[r];
+        const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
+        const int32_t P = ri.max_shift;
+        auto Sa = [&](int32_t a, int32_t b) { return P - sh[size_t(b) * nchans + a]; };
+        dd_status st = build_sum_problem(ri.adj, ri.ndms, nchans, ri.nbin, Sa, p->offF, p->baseF,
+                                         &ablocks, &alds, err, "adjoint");
+        if (st != DD_OK)
+            return st;
+    }
+    p->blocks = blocks;
+    p->lds_bytes = lds;
+    p->adj_blocks = ablocks;
+    p->adj_lds_bytes = alds;
+    for (int32_t ds : dss) {
+        BinLevel lv;
+        lv.ds = ds;
+        lv.src = -1;
+        lv.factor = ds;
+        for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
+            if (p->levels[j].ds > 1 && ds % p->levels[j].ds == 0) {
+                lv.src = j;
+                lv.factor = ds / p->levels[j].ds;
+                break;
+            }
+        lv.nbin = nsamp / ds;
+        lv.pitch = (lv.nbin + 8 + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+        int32_t reach = 0;
+        for (const RangeInfo &ri : p->ranges)
+            if (ri.ds == ds)
+                reach = std::max(reach, ri.fwd.row_words + 16);
+        lv.ws_offset = ws;
+        lv.bytes = (size_t(nchans) * size_t(lv.pitch) + size_t(reach)) * sizeof(float);
+        ws = align_up(ws + lv.bytes, kWsAlign);
+        p->levels.push_back(lv);
+    }
+    for (RangeInfo &ri : p->ranges)
+        for (size_t j = 0; j < p->levels.size(); ++j)
+            if (p->levels[j].ds == ri.ds)
+                ri.level = int32_t(j);
+    // adjoint buffers
+    for (RangeInfo &ri : p->ranges) {
+        const int64_t reach = ri.nbin + ri.max_shift + ri.adj.row_words + 16;
+        ri.gpitch = (reach + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+        ri.gpad_offset = ws;
+        ws = align_up(ws + size_t(ri.ndms) * size_t(ri.gpitch) * sizeof(float), kWsAlign);
+        ri.Gpitch = (ri.nbin + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+        ri.G_offset = ws;
+        ws = align_up(ws + size_t(nchans) * size_t(ri.Gpitch) * sizeof(float), kWsAlign);
+    }
+    p->dw_chunk_len = 4096;
+    p->dw_chunks = int32_t((nsamp + p->dw_chunk_len - 1) / p->dw_chunk_len);
+    p->dw_offset = ws;
+    ws = align_up(ws + size_t(nchans) * size_t(p->dw_chunks) * sizeof(float), kWsAlign);
+    p->ws_bytes = ws;
+    return DD_OK;
+}
 
 dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t nsamp,
                      const dd_range *ranges, int32_t nranges, dd_dtype dtype, Plan *p,
@@ -165,6 +313,9 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             dm_index += ri.ndms;
         }
         p->out_elems = out_off;
+
+        if (dtype == DD_F32)
+            return build_f32(p, err);
 
         // Tile strategy: a time tile of kTimeTile samples by a DM tile of
         // kDmTile trials per workgroup.  Channels are staged in LDS in groups

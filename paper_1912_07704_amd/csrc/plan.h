@@ -26,6 +26,35 @@ constexpr size_t kLdsTwoBlocks = 80 * 1024;      // LDS that still fits two work
 constexpr int kLevelAlign = 64;                  // samples; row pitch granule of a level
 constexpr size_t kWsAlign = 256;
 
+// Float32 path: one generic shift-and-sum over rows staged in LDS,
+//   out[a][t] = sum_b rows[b][t + S[a][b]],  t < nt,
+// used for the forward (a = DM, b = channel, rows = weighted binned input,
+// S = s) and for the adjoint (a = channel, b = DM, rows = the output
+// gradient with P zeros on both sides, S = P - s).  A workgroup owns
+// kF32OutTile outputs (8 per wave) by kF32TimeTile samples (lane l holds
+// t0 + l + 64k, k < kF32Words).
+constexpr int kF32Words = 8;
+constexpr int kF32PerWave = 4;
+constexpr int kF32TimeTile = 64 * kF32Words;
+constexpr int kF32OutTile = kWaves * kF32PerWave;
+constexpr int kF32MaxStage = 16;
+
+struct SumProblem {
+    int32_t nrows = 0;          // b: rows summed
+    int32_t nouts = 0;          // a: output rows
+    int64_t nt = 0;             // output samples per output row
+    int32_t stage_rows = 0;     // rows staged in LDS at once
+    int32_t row_words = 0;      // floats per staged row window (multiple of 4)
+    int32_t span = 0;           // largest spread of S inside one output tile
+    int32_t nout_tiles = 0;
+    int32_t nouts_pad = 0;      // nout_tiles * kF32OutTile
+    int64_t ntime_tiles = 0;
+    int64_t block_start = 0;
+    size_t off_offset = 0;      // offF: [nrows][nouts_pad] = e + S[a][b] - m
+    size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e, with
+                                // m = min over the tile of S[.][b], e = m & 3
+};
+
 // One 16-bit copy of the input, binned by ds (ds = 1: the samples widened
 // to 16 bits), held in the workspace as rows of `pitch` samples followed by
 // a tail the staging loads may reach into.
@@ -60,6 +89,13 @@ struct RangeInfo {
     int32_t ndms_pad = 0;        // ndms rounded up to a multiple of kDmTile
     size_t off_offset = 0;       // element offset of this range in offT
     size_t base_offset = 0;      // element offset of this range in baseT
+    // float32 plans
+    SumProblem fwd;              // forward of this range
+    SumProblem adj;              // adjoint of this range (rows = DMs, outputs = channels)
+    int64_t gpitch = 0;          // floats per padded output-gradient row
+    size_t gpad_offset = 0;      // workspace bytes: padded gradient rows [ndms][gpitch]
+    int64_t Gpitch = 0;          // floats per row of the channel gradient G_r
+    size_t G_offset = 0;         // workspace bytes: G_r [nchans][Gpitch]
 };
 
 struct Plan {
@@ -89,6 +125,15 @@ struct Plan {
     size_t ws_bytes = 0;
     int64_t blocks = 0;                    // workgroups of one forward launch
     size_t lds_bytes = 0;                  // dynamic LDS of the forward kernel
+    // float32 plans: tables of the generic shift-and-sum (forward problems
+    // then adjoint problems), and the adjoint's reduction buffer.
+    std::vector<int32_t> offF;
+    std::vector<int32_t> baseF;
+    int64_t adj_blocks = 0;
+    size_t adj_lds_bytes = 0;
+    int32_t dw_chunks = 0;                 // time chunks of the weight-gradient reduction
+    int64_t dw_chunk_len = 0;
+    size_t dw_offset = 0;                  // workspace bytes: partials [nchans][dw_chunks]
     void *device = nullptr;                // device-side state (owned by the HIP unit)
 };
 

@@ -363,6 +363,23 @@ def test_adjoint_matches_explicit_transpose():
     np.testing.assert_allclose(dX.ravel(), (A.T @ y) * np.repeat(w, x.shape[1]), rtol=1e-12)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_c_adjoint_matches_numpy_adjoint(seed):
+    rng = np.random.default_rng(300 + seed)
+    nch = int(rng.integers(1, 20))
+    nsamp = int(rng.integers(300, 1500))
+    freqs = np.sort(rng.uniform(1000.0, 1500.0, nch))[::-1].copy()
+    ranges = [(0.0, 8.0, 1.0, 1), (8.0, 16.0, 2.0, 3)]
+    x = rng.standard_normal((nch, nsamp)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, nch).astype(np.float32)
+    plan = O.expand_plan(freqs, 1e-3, nsamp, ranges)
+    gs = [rng.standard_normal((len(r.dms), r.nout)) for r in plan]
+    dX, dw = O.adjoint(gs, x.astype(np.float64), plan, w.astype(np.float64), nsamp)
+    cX, cw = cref.adjoint_f32(x, freqs, 1e-3, ranges, O.concat(gs), w)
+    np.testing.assert_allclose(cX, dX, rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(cw, dw, rtol=1e-12, atol=1e-9)
+
+
 def test_weight_gradient_finite_differences():
     """L(w) = sum g * out(w) is linear in w, so central differences are exact
     up to rounding."""
