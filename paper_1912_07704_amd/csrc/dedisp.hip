@@ -171,10 +171,11 @@ struct RangeArgs {
     const uint16_t *src;      // 16-bit rows of this range's level
     const int32_t *offT;      // [nchans][ndms_pad] word offsets of each DM
     const int32_t *baseT;     // [ndm_tiles][nchans] first word of each staged window
+    int32_t *out;             // [ndms][nout] output rows of this range
     int64_t pitch;            // samples per row of src
     int64_t nout;
-    int64_t out_offset;
     int64_t block_start;
+    int32_t nchans;
     int32_t ndms;
     int32_t ndms_pad;
     int32_t ndm_tiles;
@@ -185,11 +186,9 @@ struct RangeArgs {
 
 struct FwdArgs {
     RangeArgs r[DD_MAX_RANGES];
-    int32_t *out;
     int64_t nblocks;
     int64_t per_xcd;
     int32_t nranges;
-    int32_t nchans;
 };
 
 // Barrier for LDS traffic only: outstanding global loads (the prefetch of
@@ -226,23 +225,10 @@ __device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int 
     }
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
+// One work item: range R, item index lb inside the range (time tile major,
+// DM tile minor).  `lds` holds two stages of two copies each.
+__device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, uint32_t *lds)
 {
-    extern __shared__ uint32_t lds[];
-
-    // Workgroups with consecutive logical index run on one XCD, so the DM
-    // tiles of a time tile share that XCD's L2.
-    const int64_t b = blockIdx.x;
-    const int64_t L = (b % kXcds) * a.per_xcd + b / kXcds;
-    if (L >= a.nblocks)
-        return;
-    int r = 0;
-    for (int i = 1; i < a.nranges; ++i)
-        if (L >= a.r[i].block_start)
-            r = i;
-    const RangeArgs &R = a.r[r];
-
-    const int64_t lb = L - R.block_start;
     const int64_t tt = lb / R.ndm_tiles;
     const int tile = int(lb - tt * R.ndm_tiles);
     const int d0 = tile * kTileD;
@@ -253,7 +239,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const int ndms = R.ndms;
     const int dpad = R.ndms_pad;
     const int dw0 = d0 + wave * kDW;
-    const int nchans = a.nchans;
+    const int nchans = R.nchans;
     const int C = R.stage_chans;
     const int Wr = R.row_words;
     const int CW = C * Wr;              // words of one copy of a stage
@@ -351,7 +337,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
         const int d = dw0 + dd;
         if (d >= ndms)
             break;
-        int32_t *row = a.out + R.out_offset + int64_t(d) * R.nout;
+        int32_t *row = R.out + int64_t(d) * R.nout;
 #pragma unroll
         for (int k = 0; k < kNW; ++k) {
             const int64_t t = t0 + 2 * (lane + kWave * k);
@@ -363,6 +349,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     }
 }
 
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
+{
+    extern __shared__ uint32_t lds[];
+
+    // Workgroups with consecutive logical index run on one XCD, so the DM
+    // tiles of a time tile share that XCD's L2.
+    const int64_t b = blockIdx.x;
+    const int64_t L = (b % kXcds) * a.per_xcd + b / kXcds;
+    if (L >= a.nblocks)
+        return;
+    int r = 0;
+    for (int i = 1; i < a.nranges; ++i)
+        if (L >= a.r[i].block_start)
+            r = i;
+    dedisp_tile_u8(a.r[r], L - a.r[r].block_start, lds);
+}
 
 // ---------------------------------------------------------------------------
 // Float32 path.
@@ -666,11 +669,9 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
 {
     FwdArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.out = d_out;
     a.nblocks = p.blocks;
     a.per_xcd = (p.blocks + kXcds - 1) / kXcds;
     a.nranges = int32_t(p.ranges.size());
-    a.nchans = p.nchans;
     for (size_t i = 0; i < p.ranges.size(); ++i) {
         const RangeInfo &ri = p.ranges[i];
         const dd::BinLevel &lv = p.levels[ri.level];
@@ -679,8 +680,9 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
         R.pitch = lv.pitch;
         R.offT = t.offT + ri.off_offset;
         R.baseT = t.baseT + ri.base_offset;
+        R.out = d_out + ri.out_offset;
+        R.nchans = p.nchans;
         R.nout = ri.nout;
-        R.out_offset = ri.out_offset;
         R.block_start = ri.block_start;
         R.ndms = ri.ndms;
         R.ndms_pad = ri.ndms_pad;
