@@ -235,6 +235,44 @@ dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *
                      const float *d_weights, float *d_grad_in, float *d_grad_w, void *d_ws,
                      size_t ws_bytes, void *stream);
 
+/*
+ * Batches: many integer plans (beams of uneven channel counts, lengths and
+ * DM plans) summed by ONE persistent launch that takes its work items --
+ * (beam, range, time tile, DM tile), most expensive first -- from queues
+ * in the workspace.  The launch sequence allocates nothing and contains no
+ * memset, so it can be captured in a HIP graph (call dd_batch_prepare
+ * first).  Results equal dd_forward of each plan bit for bit.
+ *
+ * dd_batch_create   plans: [nbeams] DD_U8 plans (borrowed: they must
+ *                   outlive the batch).  Host-only.  Errors: DD_ERR_NULL,
+ *                   DD_ERR_INVALID (nbeams < 1), DD_ERR_DTYPE, DD_ERR_NOMEM.
+ * dd_batch_info     in_bytes: size of the batch input buffer (each beam's
+ *                   [nchans][nsamp] uint8 block at its in_offset);
+ *                   out_elems: int32 elements of the batch output (each
+ *                   beam's dd_forward layout at its out_offset); ws_bytes:
+ *                   workspace; work_items: items of the persistent launch.
+ *                   Any pointer may be NULL.
+ * dd_batch_beam     byte offset of beam b's input and element offset of its
+ *                   output (both 256-byte aligned).
+ * dd_batch_prepare  upload the batch's and its plans' device tables to the
+ *                   current device.
+ * dd_batch_forward  d_in: batch input (256-byte aligned); d_out: int32,
+ *                   out_capacity elements; d_ws: workspace (256-byte
+ *                   aligned, ws_bytes >= dd_batch_info's).  Calls that
+ *                   overlap in time need distinct workspaces.
+ */
+typedef struct dd_batch dd_batch;
+
+dd_status dd_batch_create(const dd_plan *const *plans, int32_t nbeams, dd_batch **out);
+void dd_batch_destroy(dd_batch *batch);
+dd_status dd_batch_info(const dd_batch *batch, int64_t *in_bytes, int64_t *out_elems,
+                        size_t *ws_bytes, int64_t *work_items);
+dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
+                        int64_t *out_offset);
+dd_status dd_batch_prepare(dd_batch *batch);
+dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
+                           int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Text of a status code (static storage). */
 const char *dd_status_str(dd_status status);
 

@@ -123,6 +123,81 @@ class Plan:
         self.close()
 
 
+class Batch:
+    """Many u8 plans summed by one persistent launch (dd_batch_*).  The
+    plans must stay alive as long as the batch."""
+
+    def __init__(self, plans):
+        L = lib()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        self._h = ctypes.c_void_p()
+        check(L.dd_batch_create(arr, len(self.plans), ctypes.byref(self._h)), "dd_batch_create")
+        ib, oe, wb, wi = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int64()
+        check(L.dd_batch_info(self._h, ctypes.byref(ib), ctypes.byref(oe), ctypes.byref(wb),
+                              ctypes.byref(wi)), "dd_batch_info")
+        self.in_bytes, self.out_elems = ib.value, oe.value
+        self.workspace_bytes, self.work_items = wb.value, wi.value
+        self.in_offsets, self.out_offsets = [], []
+        for b in range(len(self.plans)):
+            io, oo = ctypes.c_int64(), ctypes.c_int64()
+            check(L.dd_batch_beam(self._h, b, ctypes.byref(io), ctypes.byref(oo)), "dd_batch_beam")
+            self.in_offsets.append(io.value)
+            self.out_offsets.append(oo.value)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise DDError(-1, "batch has been closed")
+        return self._h
+
+    def prepare(self) -> None:
+        check(lib().dd_batch_prepare(self.handle), "dd_batch_prepare")
+
+    def pack(self, inputs, device=None):
+        """One batch input buffer holding every beam's [nchans, nsamp] uint8
+        block at its offset (inputs: numpy arrays or tensors)."""
+        import torch
+        buf = torch.zeros(max(1, self.in_bytes), dtype=torch.uint8, device=device or "cuda")
+        for p, off, x in zip(self.plans, self.in_offsets, inputs):
+            t = torch.as_tensor(x).reshape(-1)
+            if t.numel() != p.nchans * p.nsamp or t.dtype != torch.uint8:
+                raise ValueError("beam input has the wrong shape or dtype")
+            buf[off: off + t.numel()].copy_(t)
+        return buf
+
+    def split(self, out):
+        """Per-beam flat outputs (views)."""
+        return [out[o: o + p.out_elems] for p, o in zip(self.plans, self.out_offsets)]
+
+    def close(self) -> None:
+        if self._h:
+            lib().dd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dedisperse_batch(x, batch: Batch, out=None, ws=None, stream=None):
+    """Batched forward of every beam (dd_batch_forward); x is the packed
+    batch input.  Returns the flat int32 batch output."""
+    import torch
+    if x.dtype != torch.uint8 or not x.is_cuda or not x.is_contiguous() or \
+            x.numel() < batch.in_bytes:
+        raise ValueError("x must be the packed uint8 batch input on the device")
+    if out is None:
+        out = torch.empty(batch.out_elems, dtype=torch.int32, device=x.device)
+    if ws is None:
+        ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device=x.device)
+    check(lib().dd_batch_forward(batch.handle, _ptr(x), _ptr(out), out.numel(), _ptr(ws),
+                                 ws.numel(), _stream_ptr(stream)), "dd_batch_forward")
+    return out
+
+
 def _stream_ptr(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream

@@ -25,6 +25,12 @@ SIGNATURES = {
     "dd_forward_bin": (ctypes.c_int, [P, P, P, P, SZ, P]),
     "dd_forward_sum": (ctypes.c_int, [P, P, I64, P, SZ, P]),
     "dd_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, SZ, P]),
+    "dd_batch_create": (ctypes.c_int, [P, I32, P]),
+    "dd_batch_destroy": (None, [P]),
+    "dd_batch_info": (ctypes.c_int, [P, P, P, P, P]),
+    "dd_batch_beam": (ctypes.c_int, [P, I32, P, P]),
+    "dd_batch_prepare": (ctypes.c_int, [P]),
+    "dd_batch_forward": (ctypes.c_int, [P, P, P, I64, P, SZ, P]),
     "dd_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "dd_last_error": (ctypes.c_char_p, []),
 }

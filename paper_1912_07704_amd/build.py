@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdd_mi355x.so")
 
-HOST_SOURCES = ["plan.cpp", "capi.cpp"]
+HOST_SOURCES = ["plan.cpp", "capi.cpp", "batch.cpp"]
 HIP_SOURCES = ["dedisp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -164,6 +164,88 @@ dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes)
     return DD_OK;
 }
 
+dd_status dd_batch_create(const dd_plan *const *plans, int32_t nbeams, dd_batch **out)
+{
+    clear_error();
+    if (!out) {
+        set_error("out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *out = nullptr;
+    if (!plans) {
+        set_error("plans must not be NULL");
+        return DD_ERR_NULL;
+    }
+    dd_batch *bt = new (std::nothrow) dd_batch;
+    if (!bt) {
+        set_error("host allocation failed");
+        return DD_ERR_NOMEM;
+    }
+    std::vector<const dd::Plan *> ps;
+    dd_status st = DD_OK;
+    std::string err;
+    try {
+        for (int32_t i = 0; i < nbeams; ++i)
+            ps.push_back(plans[i] ? &plans[i]->p : nullptr);
+        st = dd::build_batch(ps.data(), nbeams, &bt->b, &err);
+        if (st == DD_OK) {
+            bt->b.device = dd::new_batch_device_state();
+            if (!bt->b.device) {
+                st = DD_ERR_NOMEM;
+                err = "host allocation failed";
+            }
+        }
+    } catch (...) {
+        st = DD_ERR_NOMEM;
+        err = "host allocation failed";
+    }
+    if (st != DD_OK) {
+        delete bt;
+        set_error(err);
+        return st;
+    }
+    *out = bt;
+    return DD_OK;
+}
+
+dd_status dd_batch_info(const dd_batch *batch, int64_t *in_bytes, int64_t *out_elems,
+                        size_t *ws_bytes, int64_t *work_items)
+{
+    clear_error();
+    if (!batch) {
+        set_error("batch must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (in_bytes)
+        *in_bytes = batch->b.in_bytes;
+    if (out_elems)
+        *out_elems = batch->b.out_elems;
+    if (ws_bytes)
+        *ws_bytes = batch->b.ws_bytes;
+    if (work_items)
+        *work_items = batch->b.nitems;
+    return DD_OK;
+}
+
+dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
+                        int64_t *out_offset)
+{
+    clear_error();
+    if (!batch) {
+        set_error("batch must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (beam < 0 || beam >= int32_t(batch->b.plans.size())) {
+        set_error("beam index out of bounds");
+        return DD_ERR_INVALID;
+    }
+    if (in_offset)
+        *in_offset = batch->b.in_off[beam];
+    if (out_offset)
+        *out_offset = batch->b.out_off[beam];
+    return DD_OK;
+}
+
 const char *dd_status_str(dd_status status)
 {
     switch (status) {

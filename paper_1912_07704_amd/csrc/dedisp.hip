@@ -628,6 +628,86 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float *__restrict__ p
         out[c] = red[0];
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched integer forward: one persistent launch over the work items of
+// many beams.  Item L of the cost-ordered list belongs to the descriptor
+// whose item_start is the largest not above L.  The list is cut into one
+// contiguous queue per XCD; a workgroup dealt to XCD x takes its next item
+// from queue x (a counter in the workspace, reset by k_reset_counters
+// before the launch), so the tiles of a time tile still share an L2.
+// ---------------------------------------------------------------------------
+
+struct BatchDesc {
+    const int32_t *offT;
+    const int32_t *baseT;
+    int64_t src_off;          // bytes into the workspace
+    int64_t out_off;          // elements into the batch output
+    int64_t pitch;
+    int64_t nout;
+    int64_t item_start;
+    int32_t nchans;
+    int32_t ndms;
+    int32_t ndms_pad;
+    int32_t ndm_tiles;
+    int32_t stage_chans;
+    int32_t row_words;
+    int32_t widen_every;
+    int32_t pad_;
+};
+
+__global__ void k_reset_counters(int32_t *counters, int n)
+{
+    if (int(threadIdx.x) < n)
+        counters[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
+                  int ndesc, int64_t nitems, int64_t per_queue, const char *ws, int32_t *out,
+                  int32_t *counters)
+{
+    extern __shared__ uint32_t lds[];
+    __shared__ int64_t s_item;
+    const int x = blockIdx.x % kXcds;
+    const int64_t q_begin = int64_t(x) * per_queue;
+    const int64_t q_end = min(nitems, q_begin + per_queue);
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = q_begin + atomicAdd(&counters[x], 1);
+        __syncthreads();
+        const int64_t L = s_item;
+        __syncthreads();
+        if (L >= q_end)
+            break;
+        int lo = 0, hi = ndesc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (starts[mid] <= L)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchDesc &D = descs[lo];
+        RangeArgs R;
+        R.src = reinterpret_cast<const uint16_t *>(ws + D.src_off);
+        R.offT = D.offT;
+        R.baseT = D.baseT;
+        R.out = out + D.out_off;
+        R.pitch = D.pitch;
+        R.nout = D.nout;
+        R.block_start = 0;
+        R.nchans = D.nchans;
+        R.ndms = D.ndms;
+        R.ndms_pad = D.ndms_pad;
+        R.ndm_tiles = D.ndm_tiles;
+        R.stage_chans = D.stage_chans;
+        R.row_words = D.row_words;
+        R.widen_every = D.widen_every;
+        dedisp_tile_u8(R, L - D.item_start, lds);
+    }
+}
+
 dd_status launch_check(const char *what)
 {
     if (fault_requested("launch")) {
@@ -844,6 +924,110 @@ dd_status forward_sum(const Plan &p, const DeviceTables &t, void *d_out, const c
     return sum_f32(p, t, static_cast<float *>(d_out), d_ws, stream);
 }
 
+
+// Device-side batch state: descriptor array and item starts, per device.
+struct BatchDevice {
+    BatchDesc *descs = nullptr;
+    int64_t *starts = nullptr;
+};
+
+struct BatchState {
+    std::mutex mu;
+    std::map<int, BatchDevice> per_device;
+};
+
+dd_status batch_device(const dd::Batch &b, BatchDevice **out)
+{
+    BatchState *st = static_cast<BatchState *>(b.device);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(st->mu);
+    auto it = st->per_device.find(dev);
+    if (it != st->per_device.end()) {
+        *out = &it->second;
+        return DD_OK;
+    }
+    std::vector<BatchDesc> hd(b.descs.size());
+    std::vector<int64_t> hs(b.descs.size());
+    for (size_t i = 0; i < b.descs.size(); ++i) {
+        const dd::BatchDescHost &d = b.descs[i];
+        const Plan &p = *b.plans[d.beam];
+        DeviceTables *t = nullptr;
+        dd_status s2 = device_tables(p, &t);
+        if (s2 != DD_OK)
+            return s2;
+        const RangeInfo &ri = p.ranges[d.range];
+        const dd::BinLevel &lv = p.levels[ri.level];
+        BatchDesc &D = hd[i];
+        std::memset(&D, 0, sizeof(D));
+        D.offT = t->offT + ri.off_offset;
+        D.baseT = t->baseT + ri.base_offset;
+        D.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
+        D.out_off = b.out_off[d.beam] + ri.out_offset;
+        D.pitch = lv.pitch;
+        D.nout = ri.nout;
+        D.item_start = d.item_start;
+        D.nchans = p.nchans;
+        D.ndms = ri.ndms;
+        D.ndms_pad = ri.ndms_pad;
+        D.ndm_tiles = ri.ndm_tiles;
+        D.stage_chans = ri.stage_chans;
+        D.row_words = ri.row_words;
+        D.widen_every = ri.widen_every;
+        hs[i] = d.item_start;
+    }
+    BatchDevice bd;
+    const size_t db = hd.size() * sizeof(BatchDesc), sb = hs.size() * sizeof(int64_t);
+    e = hipMalloc(&bd.descs, db + sb + 64);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        dd::set_error(std::string("hipMalloc of the batch descriptors: ") + hipGetErrorString(e));
+        return DD_ERR_NOMEM;
+    }
+    bd.starts = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(bd.descs) + db);
+    e = hipMemcpy(bd.descs, hd.data(), db, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(bd.starts, hs.data(), sb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(bd.descs);
+        return hip_fail(e, "hipMemcpy of the batch descriptors");
+    }
+    *out = &(st->per_device[dev] = bd);
+    return DD_OK;
+}
+
+// Persistent workgroups per XCD: two per CU of its 32.
+constexpr int kPersistPerXcd = 64;
+
+dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
+                        int32_t *d_out, char *d_ws, hipStream_t stream)
+{
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+        dd_status st = bin_u8(*b.plans[i], reinterpret_cast<const uint8_t *>(d_in + b.in_off[i]),
+                              d_ws + b.ws_off[i], stream);
+        if (st != DD_OK)
+            return st;
+    }
+    int32_t *counters = reinterpret_cast<int32_t *>(d_ws);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, counters, kXcds);
+    dd_status st = launch_check("k_reset_counters");
+    if (st != DD_OK)
+        return st;
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dd::kMaxLdsBytes - 64));
+    });
+    const int64_t per_queue = (b.nitems + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(k_dedisp_u8_batch, dim3(unsigned(kXcds * kPersistPerXcd)), dim3(kBlock),
+                       b.lds_bytes, stream, bd.descs, bd.starts, int(b.descs.size()), b.nitems,
+                       per_queue, d_ws, d_out, counters);
+    return launch_check("k_dedisp_u8_batch");
+}
+
 // Argument checks shared by the compute entry points (synchronous, before
 // any HIP call).
 dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float *d_weights,
@@ -883,6 +1067,7 @@ dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float 
 }  // namespace
 
 void *dd::new_device_state() { return new (std::nothrow) DeviceState; }
+void *dd::new_batch_device_state() { return new (std::nothrow) BatchState; }
 
 extern "C" {
 
@@ -903,6 +1088,66 @@ void dd_plan_destroy(dd_plan *plan)
         delete st;
     }
     delete plan;
+}
+
+void dd_batch_destroy(dd_batch *batch)
+{
+    if (!batch)
+        return;
+    BatchState *st = static_cast<BatchState *>(batch->b.device);
+    if (st) {
+        int cur = -1;
+        const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+        for (auto &kv : st->per_device)
+            if (hipSetDevice(kv.first) == hipSuccess)
+                (void)hipFree(kv.second.descs);
+        if (have_cur)
+            (void)hipSetDevice(cur);
+        delete st;
+    }
+    delete batch;
+}
+
+dd_status dd_batch_prepare(dd_batch *batch)
+{
+    dd::clear_error();
+    if (!batch) {
+        dd::set_error("batch must not be NULL");
+        return DD_ERR_NULL;
+    }
+    BatchDevice *bd = nullptr;
+    return batch_device(batch->b, &bd);
+}
+
+dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
+                           int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream)
+{
+    dd::clear_error();
+    if (!batch || !d_in || !d_out || !d_ws) {
+        dd::set_error("batch, d_in, d_out and d_ws must not be NULL");
+        return DD_ERR_NULL;
+    }
+    const dd::Batch &b = batch->b;
+    if (out_capacity < b.out_elems) {
+        dd::set_error("out_capacity " + std::to_string(out_capacity) + " < out_elems " +
+                      std::to_string(b.out_elems));
+        return DD_ERR_CAPACITY;
+    }
+    if (ws_bytes < b.ws_bytes || reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+        dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
+                      std::to_string(b.ws_bytes) + " or not 256-byte aligned");
+        return DD_ERR_WORKSPACE;
+    }
+    if (reinterpret_cast<uintptr_t>(d_in) % 256 != 0) {
+        dd::set_error("d_in must be 256-byte aligned");
+        return DD_ERR_INVALID;
+    }
+    BatchDevice *bd = nullptr;
+    dd_status st = batch_device(b, &bd);
+    if (st != DD_OK)
+        return st;
+    return batch_forward(b, *bd, static_cast<const char *>(d_in), static_cast<int32_t *>(d_out),
+                         static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
 }
 
 dd_status dd_plan_prepare(dd_plan *plan)

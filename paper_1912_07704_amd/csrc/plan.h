@@ -146,13 +146,45 @@ dd_status build_plan(const double *freqs_mhz, int32_t nchans, double tsamp_s, in
 // Device-side state of a plan (allocated by the HIP unit, freed by
 // dd_plan_destroy).
 void *new_device_state();
+void *new_batch_device_state();
 
 // Thread-local error text shared by every entry point.
 void set_error(const std::string &msg);
 void clear_error();
 
+// A batch of integer plans (beams) summed by one persistent launch.  Inputs
+// and outputs of all beams share one buffer each, at fixed offsets.
+struct BatchDescHost {
+    int32_t beam = 0;
+    int32_t range = 0;
+    int64_t item_start = 0;      // first work item of this (beam, range)
+    int64_t nitems = 0;          // time tiles x DM tiles
+};
+
+struct Batch {
+    std::vector<const Plan *> plans;       // not owned
+    std::vector<int64_t> in_off;           // bytes into the batch input
+    std::vector<int64_t> out_off;          // elements into the batch output
+    std::vector<size_t> ws_off;            // bytes into the workspace (beam's own part)
+    int64_t in_bytes = 0;
+    int64_t out_elems = 0;
+    size_t ws_bytes = 0;
+    std::vector<BatchDescHost> descs;      // most expensive items first
+    int64_t nitems = 0;
+    size_t lds_bytes = 0;
+    void *device = nullptr;
+};
+
+constexpr size_t kBatchCounterBytes = 256;     // queue counters at the start of the workspace
+
+dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::string *err);
+
 }  // namespace dd
 
 struct dd_plan {
     dd::Plan p;
+};
+
+struct dd_batch {
+    dd::Batch b;
 };

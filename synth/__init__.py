@@ -112,6 +112,36 @@ def filterbank_u8(seed: int, freqs: np.ndarray, tsamp: float, nsamp: int,
     return out
 
 
+def filterbank_u8_device(seed: int, freqs: np.ndarray, tsamp: float, nsamp: int, pulses=(),
+                         mean: float = 128.0, sd: float = 16.0, device="cuda"):
+    """The uint8 filterbank recipe of filterbank_u8 drawn on the GPU with
+    torch's seeded generator (a different noise stream than the numpy one,
+    for workloads too large to draw on the host): rint(N(mean, sd)) noise,
+    integer pulses added, one clip to [0, 255]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    nch = len(freqs)
+    out = torch.empty((nch, nsamp), dtype=torch.uint8, device=device)
+    step = max(1, (1 << 26) // max(1, nsamp))          # channels per chunk
+    rows_all = [(p, sky_delay_samples(p.dm, freqs, tsamp)) for p in pulses]
+    for c0 in range(0, nch, step):
+        c1 = min(nch, c0 + step)
+        z = torch.randn((c1 - c0, nsamp), generator=g, device=device, dtype=torch.float32)
+        v = torch.round(z * sd + mean).to(torch.int16)
+        for p, delays in rows_all:
+            amp = int(p.amp)
+            for k in range(p.width):
+                t = p.t0 + delays[c0:c1] + k
+                ok = np.nonzero(t < nsamp)[0]
+                if ok.size:
+                    ri = torch.from_numpy(ok).to(device)
+                    ti = torch.from_numpy(t[ok]).to(device)
+                    v[ri, ti] += amp
+        out[c0:c1] = v.clamp_(0, 255).to(torch.uint8)
+    return out
+
+
 def filterbank_f32(seed: int, nchans: int, nsamp: int,
                    threads: int | None = None) -> np.ndarray:
     """float32 filterbank [nchans][nsamp] of N(0, 1) samples."""
