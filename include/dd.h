@@ -236,6 +236,33 @@ dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *
                      size_t ws_bytes, void *stream);
 
 /*
+ * Boxcar loss of DD_F32 plans (the single-pulse search's boxcar filters,
+ * paper Introduction, recast as a differentiable loss):
+ *   L = sum_beams sum_r sum_d sum_{w = 1, 2, 4, ..., max_width}
+ *       sum_{t = 0}^{nout_r - w} ( sum_{k < w} out_r[d][t + k] )^2
+ * with out = dd_forward(x_beam, weights).  The dedispersed output is never
+ * stored: dd_boxcar_loss forms the windows inside each output tile, and
+ * dd_boxcar_backward recomputes each tile to form dL/dout (one beam at a
+ * time, in the workspace) and runs the adjoint, so
+ *   d_grad_in[beam] = dL/dx_beam    and    d_grad_w = sum_beams dL/dw.
+ *   d_in        [nbeams][nchans][nsamp] float32.
+ *   d_weights   [nchans] shared by all beams, or NULL (ones).
+ *   max_width   a power of two in [1, 32].
+ *   d_loss      one float32 on the device (overwritten).
+ *   d_grad_in   [nbeams][nchans][nsamp] float32 or NULL; d_grad_w [nchans]
+ *               float32 or NULL.
+ *   d_ws        the plan's workspace (dd_workspace_bytes).
+ * Sums are float32 in a fixed order.  Errors: DD_ERR_NULL, DD_ERR_DTYPE,
+ * DD_ERR_INVALID (nbeams < 1, max_width), DD_ERR_WORKSPACE, DD_ERR_HIP.
+ */
+dd_status dd_boxcar_loss(const dd_plan *plan, const float *d_in, int32_t nbeams,
+                         const float *d_weights, int32_t max_width, float *d_loss, void *d_ws,
+                         size_t ws_bytes, void *stream);
+dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbeams,
+                             const float *d_weights, int32_t max_width, float *d_grad_in,
+                             float *d_grad_w, void *d_ws, size_t ws_bytes, void *stream);
+
+/*
  * Batches: many integer plans (beams of uneven channel counts, lengths and
  * DM plans) summed by ONE persistent launch that takes its work items --
  * (beam, range, time tile, DM tile), most expensive first -- from queues

@@ -305,6 +305,48 @@ def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=Tru
     return dx, dw
 
 
+def _check_beams(x, plan):
+    import torch
+    if (x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous()
+            or x.shape[-2:] != (plan.nchans, plan.nsamp)):
+        raise ValueError(f"x must be a contiguous device float32 [..., {plan.nchans}, "
+                         f"{plan.nsamp}] tensor")
+    return x.numel() // (plan.nchans * plan.nsamp)
+
+
+def boxcar_loss(x, plan: Plan, weights=None, max_width: int = 32, ws=None, stream=None):
+    """Sum over beams, DMs, widths 1..max_width (powers of two) and valid
+    windows of squared boxcar sums of the dedispersed output, which is never
+    stored (dd_boxcar_loss).  x: [nbeams, nchans, nsamp] or [nchans, nsamp]."""
+    import torch
+    nb = _check_beams(x, plan)
+    _check_weights(weights, plan)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    if ws is None:
+        ws = workspace(plan, x.device)
+    check(lib().dd_boxcar_loss(plan.handle, _ptr(x), nb, _ptr(weights), int(max_width),
+                               _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+          "dd_boxcar_loss")
+    return loss[0]
+
+
+def boxcar_backward(x, plan: Plan, weights=None, max_width: int = 32, grad_in=True,
+                    grad_w=True, ws=None, stream=None):
+    """(dL/dx, dL/dw) of boxcar_loss, recomputing the dedispersed output
+    (dd_boxcar_backward)."""
+    import torch
+    nb = _check_beams(x, plan)
+    _check_weights(weights, plan)
+    dx = torch.empty_like(x) if grad_in else None
+    dw = torch.empty(plan.nchans, dtype=torch.float32, device=x.device) if grad_w else None
+    if ws is None:
+        ws = workspace(plan, x.device)
+    check(lib().dd_boxcar_backward(plan.handle, _ptr(x), nb, _ptr(weights), int(max_width),
+                                   _ptr(dx), _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+          "dd_boxcar_backward")
+    return dx, dw
+
+
 def _autograd_fn():
     import torch
 

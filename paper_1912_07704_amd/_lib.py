@@ -25,6 +25,8 @@ SIGNATURES = {
     "dd_forward_bin": (ctypes.c_int, [P, P, P, P, SZ, P]),
     "dd_forward_sum": (ctypes.c_int, [P, P, I64, P, SZ, P]),
     "dd_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, SZ, P]),
+    "dd_boxcar_loss": (ctypes.c_int, [P, P, I32, P, I32, P, P, SZ, P]),
+    "dd_boxcar_backward": (ctypes.c_int, [P, P, I32, P, I32, P, P, P, SZ, P]),
     "dd_batch_create": (ctypes.c_int, [P, I32, P]),
     "dd_batch_destroy": (None, [P]),
     "dd_batch_info": (ctypes.c_int, [P, P, P, P, P]),

@@ -466,7 +466,30 @@ __device__ __forceinline__ void stage_issue_f32(const SumArgs &R, int tile, int6
     }
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_shiftsum_f32(const SumBatch a)
+// Epilogues of the float32 shift-and-sum:
+//   kWrite    write the outputs;
+//   kBoxLoss  sum over valid windows of (boxcar_w(out))^2 for w = 1, 2, 4,
+//             ..., max_width, windows starting in the first t_stride samples
+//             of the tile; one partial per workgroup (fixed-order tree);
+//   kBoxGrad  dL/dout = 2 * sum_w sum_{j<w} B_w[t - j] (valid windows only)
+//             for the tile's samples [t_lead, t_lead + t_stride).
+// Boxcar sums are formed by doubling, B_2w[t] = B_w[t] + B_w[t + w], through
+// one LDS row per wave; the window sums of the gradient likewise.
+enum { kWrite = 0, kBoxLoss = 1, kBoxGrad = 2 };
+
+struct BoxArgs {
+    float *partial;           // kBoxLoss: one float per workgroup
+    int64_t t_stride;         // samples between consecutive time tiles
+    int64_t t_lead;           // the first tile starts at sample -t_lead
+    int32_t max_width;        // largest boxcar width (a power of two <= 32)
+    int32_t pad_;
+};
+
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
 {
     extern __shared__ float ldsf[];
     const int64_t bid = blockIdx.x;
@@ -481,7 +504,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     const int64_t lb = L - R.block_start;
     const int64_t tt = lb / R.nout_tiles;
     const int tile = int(lb - tt * R.nout_tiles);
-    const int64_t t0 = tt * kFTileT;
+    const int64_t t0 = tt * bx.t_stride - bx.t_lead;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -542,17 +565,105 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
             }
         }
     }
+
+    if constexpr (MODE == kWrite) {
 #pragma unroll
-    for (int dd = 0; dd < kFP; ++dd) {
-        const int ao = aw0 + dd;
-        if (ao >= R.nouts)
-            break;
-        float *row = R.dst + int64_t(ao) * R.dst_pitch;
+        for (int dd = 0; dd < kFP; ++dd) {
+            const int ao = aw0 + dd;
+            if (ao >= R.nouts)
+                break;
+            float *row = R.dst + int64_t(ao) * R.dst_pitch;
 #pragma unroll
-        for (int k = 0; k < kFW; ++k) {
-            const int64_t t = t0 + lane + kWave * k;
-            if (t < R.nt)
-                row[t] = acc[dd][k];
+            for (int k = 0; k < kFW; ++k) {
+                const int64_t t = t0 + lane + kWave * k;
+                if (t >= 0 && t < R.nt)
+                    row[t] = acc[dd][k];
+            }
+        }
+    } else {
+        lds_barrier();                          // staging rows are no longer read
+        float *rowR = ldsf + wave * (2 * kFTileT);
+        float *rowS = rowR + kFTileT;
+        const int64_t nt = R.nt;
+        float part = 0.0f;
+        for (int dd = 0; dd < kFP; ++dd) {
+            const int ao = aw0 + dd;
+            const bool dm_ok = ao < R.nouts;
+            float b[kFW], gsum[kFW];
+#pragma unroll
+            for (int k = 0; k < kFW; ++k) {
+                b[k] = acc[dd][k];
+                gsum[k] = 0.0f;
+            }
+            for (int w = 1; w <= bx.max_width; w *= 2) {
+                if constexpr (MODE == kBoxLoss) {
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k) {
+                        const int t = lane + kWave * k;
+                        const int64_t tg = t0 + t;
+                        if (dm_ok && t < bx.t_stride && tg >= 0 && tg + w <= nt)
+                            part += b[k] * b[k];
+                    }
+                } else {
+                    float c[kFW];
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k) {
+                        const int64_t tg = t0 + lane + kWave * k;
+                        c[k] = (dm_ok && tg >= 0 && tg + w <= nt) ? b[k] : 0.0f;
+                    }
+                    for (int h = 1; h < w; h *= 2) {
+#pragma unroll
+                        for (int k = 0; k < kFW; ++k)
+                            rowS[lane + kWave * k] = c[k];
+                        lds_wave_sync();
+#pragma unroll
+                        for (int k = 0; k < kFW; ++k) {
+                            const int t = lane + kWave * k;
+                            c[k] += t >= h ? rowS[t - h] : 0.0f;
+                        }
+                        lds_wave_sync();
+                    }
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k)
+                        gsum[k] += c[k];
+                }
+                if (w < bx.max_width) {
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k)
+                        rowR[lane + kWave * k] = b[k];
+                    lds_wave_sync();
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k) {
+                        const int t = lane + kWave * k;
+                        b[k] += t + w < kFTileT ? rowR[t + w] : 0.0f;
+                    }
+                    lds_wave_sync();
+                }
+            }
+            if constexpr (MODE == kBoxGrad) {
+                if (dm_ok) {
+                    float *row = R.dst + int64_t(ao) * R.dst_pitch;
+#pragma unroll
+                    for (int k = 0; k < kFW; ++k) {
+                        const int t = lane + kWave * k;
+                        const int64_t tg = t0 + t;
+                        if (t >= bx.t_lead && t < bx.t_lead + bx.t_stride && tg >= 0 && tg < nt)
+                            row[tg] = 2.0f * gsum[k];
+                    }
+                }
+            }
+        }
+        if constexpr (MODE == kBoxLoss) {
+            float *red = ldsf + kWavesPerBlock * 2 * kFTileT;
+            red[tid] = part;
+            __syncthreads();
+            for (int h = kBlock / 2; h > 0; h >>= 1) {
+                if (tid < h)
+                    red[tid] += red[tid + h];
+                __syncthreads();
+            }
+            if (tid == 0)
+                bx.partial[L] = red[0];
         }
     }
 }
@@ -786,7 +897,7 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
 dd_status bin_f32(const Plan &p, const float *d_in, const float *d_w, char *d_ws, hipStream_t stream)
 {
     for (const dd::BinLevel &lv : p.levels) {
-        float *dst = reinterpret_cast<float *>(d_ws + lv.ws_offset);
+        float *dst = reinterpret_cast<float *>(d_ws + lv.ws_offset) + lv.lead;
         const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 255) / 256, 1024)),
                         unsigned(std::min<int32_t>(p.nchans, 65535)));
         if (lv.src < 0) {
@@ -794,7 +905,7 @@ dd_status bin_f32(const Plan &p, const float *d_in, const float *d_w, char *d_ws
                                lv.pitch, lv.nbin, lv.factor, p.nchans);
         } else {
             const dd::BinLevel &sl = p.levels[lv.src];
-            const float *src = reinterpret_cast<const float *>(d_ws + sl.ws_offset);
+            const float *src = reinterpret_cast<const float *>(d_ws + sl.ws_offset) + sl.lead;
             hipLaunchKernelGGL(k_level_f32, grid, dim3(256), 0, stream, src, sl.pitch,
                                static_cast<const float *>(nullptr), dst, lv.pitch, lv.nbin,
                                lv.factor, p.nchans);
@@ -828,19 +939,29 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     return R;
 }
 
-dd_status launch_sum(SumBatch &a, int64_t blocks, size_t lds, hipStream_t stream)
+template <int MODE>
+dd_status launch_sum_mode(SumBatch &a, int64_t blocks, size_t lds, const BoxArgs &bx,
+                          hipStream_t stream)
 {
     a.nblocks = blocks;
     a.per_xcd = (blocks + kXcds - 1) / kXcds;
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_shiftsum_f32),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_shiftsum_f32<MODE>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(dd::kMaxLdsBytes));
     });
-    hipLaunchKernelGGL(k_shiftsum_f32, dim3(unsigned(a.per_xcd * kXcds)), dim3(kBlock), lds,
-                       stream, a);
+    hipLaunchKernelGGL(k_shiftsum_f32<MODE>, dim3(unsigned(a.per_xcd * kXcds)), dim3(kBlock), lds,
+                       stream, a, bx);
     return launch_check("k_shiftsum_f32");
+}
+
+dd_status launch_sum(SumBatch &a, int64_t blocks, size_t lds, hipStream_t stream)
+{
+    BoxArgs bx;
+    std::memset(&bx, 0, sizeof(bx));
+    bx.t_stride = kFTileT;
+    return launch_sum_mode<kWrite>(a, blocks, lds, bx, stream);
 }
 
 dd_status sum_f32(const Plan &p, const DeviceTables &t, float *d_out, const char *d_ws,
@@ -852,7 +973,7 @@ dd_status sum_f32(const Plan &p, const DeviceTables &t, float *d_out, const char
     for (size_t i = 0; i < p.ranges.size(); ++i) {
         const RangeInfo &ri = p.ranges[i];
         const dd::BinLevel &lv = p.levels[ri.level];
-        a.p[i] = sum_args(ri.fwd, t, reinterpret_cast<const float *>(d_ws + lv.ws_offset),
+        a.p[i] = sum_args(ri.fwd, t, reinterpret_cast<const float *>(d_ws + lv.ws_offset) + lv.lead,
                           lv.pitch, d_out + ri.out_offset, ri.nout);
     }
     return launch_sum(a, p.blocks, p.lds_bytes, stream);
@@ -906,6 +1027,110 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
     hipLaunchKernelGGL(k_reduce_rows, dim3(unsigned(p.nchans)), dim3(256), 0, stream, partial,
                        p.dw_chunks, d_dw);
     return launch_check("k_reduce_rows");
+}
+
+
+__global__ void k_accumulate(float *__restrict__ dst, const float *__restrict__ src, int n,
+                             int first)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        dst[i] = first ? src[i] : dst[i] + src[i];
+}
+
+// Forward problems of a plan relaunched with the boxcar tiling.
+int64_t box_batch(const Plan &p, const DeviceTables &t, const char *d_ws, float *dst,
+                  int64_t stride, SumBatch &a)
+{
+    std::memset(&a, 0, sizeof(a));
+    a.nprob = int32_t(p.ranges.size());
+    int64_t blocks = 0;
+    for (size_t i = 0; i < p.ranges.size(); ++i) {
+        const RangeInfo &ri = p.ranges[i];
+        const dd::BinLevel &lv = p.levels[ri.level];
+        a.p[i] = sum_args(ri.fwd, t, reinterpret_cast<const float *>(d_ws + lv.ws_offset) + lv.lead,
+                          lv.pitch, dst ? dst + ri.out_offset : nullptr, ri.nout);
+        a.p[i].block_start = blocks;
+        blocks += (ri.nout + stride - 1) / stride * ri.fwd.nout_tiles;
+    }
+    return blocks;
+}
+
+size_t box_lds(const Plan &p)
+{
+    return std::max(p.lds_bytes, size_t(kWavesPerBlock * 2 * kFTileT + kBlock) * sizeof(float));
+}
+
+dd_status boxcar_loss_f32(const Plan &p, const DeviceTables &t, const float *d_in, int32_t nbeams,
+                          const float *d_w, int32_t max_width, float *d_loss, char *d_ws,
+                          hipStream_t stream)
+{
+    float *partial = reinterpret_cast<float *>(d_ws + p.box_offset);
+    float *beam_loss = partial + p.box_partials;
+    for (int32_t b = 0; b < nbeams; ++b) {
+        const float *x = d_in + int64_t(b) * p.nchans * p.nsamp;
+        dd_status st = bin_f32(p, x, d_w, d_ws, stream);
+        if (st != DD_OK)
+            return st;
+        SumBatch a;
+        const int64_t blocks = box_batch(p, t, d_ws, nullptr, dd::kBoxLossStride, a);
+        BoxArgs bx;
+        std::memset(&bx, 0, sizeof(bx));
+        bx.partial = partial;
+        bx.t_stride = dd::kBoxLossStride;
+        bx.t_lead = 0;
+        bx.max_width = max_width;
+        st = launch_sum_mode<kBoxLoss>(a, blocks, box_lds(p), bx, stream);
+        if (st != DD_OK)
+            return st;
+        hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, stream, partial, int(blocks),
+                           beam_loss);
+        st = launch_check("k_reduce_rows");
+        if (st != DD_OK)
+            return st;
+        hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(64), 0, stream, d_loss, beam_loss, 1,
+                           int(b == 0));
+        st = launch_check("k_accumulate");
+        if (st != DD_OK)
+            return st;
+    }
+    return DD_OK;
+}
+
+dd_status boxcar_backward_f32(const Plan &p, const DeviceTables &t, const float *d_in,
+                              int32_t nbeams, const float *d_w, int32_t max_width, float *d_dx,
+                              float *d_dw, char *d_ws, hipStream_t stream)
+{
+    float *gout = reinterpret_cast<float *>(d_ws + p.gout_offset);
+    float *dwb = reinterpret_cast<float *>(d_ws + p.dwb_offset);
+    for (int32_t b = 0; b < nbeams; ++b) {
+        const int64_t xoff = int64_t(b) * p.nchans * p.nsamp;
+        dd_status st = bin_f32(p, d_in + xoff, d_w, d_ws, stream);
+        if (st != DD_OK)
+            return st;
+        SumBatch a;
+        const int64_t blocks = box_batch(p, t, d_ws, gout, dd::kBoxGradStride, a);
+        BoxArgs bx;
+        std::memset(&bx, 0, sizeof(bx));
+        bx.t_stride = dd::kBoxGradStride;
+        bx.t_lead = dd::kBoxLead;
+        bx.max_width = max_width;
+        st = launch_sum_mode<kBoxGrad>(a, blocks, box_lds(p), bx, stream);
+        if (st != DD_OK)
+            return st;
+        st = adjoint_f32(p, t, gout, d_in + xoff, d_w, d_dx ? d_dx + xoff : nullptr,
+                         d_dw ? dwb : nullptr, d_ws, stream);
+        if (st != DD_OK)
+            return st;
+        if (d_dw) {
+            hipLaunchKernelGGL(k_accumulate, dim3(unsigned((p.nchans + 255) / 256)), dim3(256), 0,
+                               stream, d_dw, dwb, p.nchans, int(b == 0));
+            st = launch_check("k_accumulate");
+            if (st != DD_OK)
+                return st;
+        }
+    }
+    return DD_OK;
 }
 
 dd_status forward_bin(const Plan &p, const void *d_in, const float *d_w, char *d_ws,
@@ -1233,6 +1458,67 @@ dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *
         return st;
     return adjoint_f32(p, *t, d_grad_out, d_in, d_weights, d_grad_in, d_grad_w,
                        static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
+}
+
+static dd_status check_box_args(const dd_plan *plan, const float *d_in, int32_t nbeams,
+                                int32_t max_width, const void *d_ws, size_t ws_bytes)
+{
+    if (!plan || !d_in) {
+        dd::set_error("plan and d_in must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (plan->p.dtype != DD_F32) {
+        dd::set_error("the boxcar loss is defined for DD_F32 plans");
+        return DD_ERR_DTYPE;
+    }
+    if (nbeams < 1 || max_width < 1 || max_width > dd::kBoxMaxWidth ||
+        (max_width & (max_width - 1)) != 0) {
+        dd::set_error("need nbeams >= 1 and max_width a power of two in [1, 32]");
+        return DD_ERR_INVALID;
+    }
+    if (ws_bytes < plan->p.ws_bytes || !d_ws || reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+        dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
+                      std::to_string(plan->p.ws_bytes) + " or not 256-byte aligned");
+        return DD_ERR_WORKSPACE;
+    }
+    return DD_OK;
+}
+
+dd_status dd_boxcar_loss(const dd_plan *plan, const float *d_in, int32_t nbeams,
+                         const float *d_weights, int32_t max_width, float *d_loss, void *d_ws,
+                         size_t ws_bytes, void *stream)
+{
+    dd::clear_error();
+    dd_status st = check_box_args(plan, d_in, nbeams, max_width, d_ws, ws_bytes);
+    if (st != DD_OK)
+        return st;
+    if (!d_loss) {
+        dd::set_error("d_loss must not be NULL");
+        return DD_ERR_NULL;
+    }
+    DeviceTables *t = nullptr;
+    st = device_tables(plan->p, &t);
+    if (st != DD_OK)
+        return st;
+    return boxcar_loss_f32(plan->p, *t, d_in, nbeams, d_weights, max_width, d_loss,
+                           static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
+}
+
+dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbeams,
+                             const float *d_weights, int32_t max_width, float *d_grad_in,
+                             float *d_grad_w, void *d_ws, size_t ws_bytes, void *stream)
+{
+    dd::clear_error();
+    dd_status st = check_box_args(plan, d_in, nbeams, max_width, d_ws, ws_bytes);
+    if (st != DD_OK)
+        return st;
+    DeviceTables *t = nullptr;
+    st = device_tables(plan->p, &t);
+    if (st != DD_OK)
+        return st;
+    return boxcar_backward_f32(plan->p, *t, d_in, nbeams, d_weights, max_width, d_grad_in,
+                               d_grad_w, static_cast<char *>(d_ws),
+                               static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -155,12 +155,14 @@ dd_status build_f32(Plan *p, std::string *err)
             }
         lv.nbin = nsamp / ds;
         lv.pitch = (lv.nbin + 8 + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+        lv.lead = kLevelAlign;
         int32_t reach = 0;
         for (const RangeInfo &ri : p->ranges)
             if (ri.ds == ds)
                 reach = std::max(reach, ri.fwd.row_words + 16);
         lv.ws_offset = ws;
-        lv.bytes = (size_t(nchans) * size_t(lv.pitch) + size_t(reach)) * sizeof(float);
+        lv.bytes = (size_t(lv.lead) + size_t(nchans) * size_t(lv.pitch) + size_t(reach)) *
+                   sizeof(float);
         ws = align_up(ws + lv.bytes, kWsAlign);
         p->levels.push_back(lv);
     }
@@ -182,6 +184,17 @@ dd_status build_f32(Plan *p, std::string *err)
     p->dw_chunks = int32_t((nsamp + p->dw_chunk_len - 1) / p->dw_chunk_len);
     p->dw_offset = ws;
     ws = align_up(ws + size_t(nchans) * size_t(p->dw_chunks) * sizeof(float), kWsAlign);
+    // boxcar loss buffers
+    p->gout_offset = ws;
+    ws = align_up(ws + size_t(p->out_elems) * sizeof(float), kWsAlign);
+    int64_t lp = 0;
+    for (const RangeInfo &ri : p->ranges)
+        lp += (ri.nout + kBoxLossStride - 1) / kBoxLossStride * ri.fwd.nout_tiles;
+    p->box_partials = lp;
+    p->box_offset = ws;
+    ws = align_up(ws + size_t(lp + 64) * sizeof(float), kWsAlign);
+    p->dwb_offset = ws;
+    ws = align_up(ws + size_t(nchans) * sizeof(float), kWsAlign);
     p->ws_bytes = ws;
     return DD_OK;
 }

@@ -38,6 +38,14 @@ constexpr int kF32PerWave = 4;
 constexpr int kF32TimeTile = 64 * kF32Words;
 constexpr int kF32OutTile = kWaves * kF32PerWave;
 constexpr int kF32MaxStage = 16;
+// Boxcar loss tiles: the loss tile counts windows starting in its first
+// kBoxLossStride samples; the gradient tile writes dL/dout for its samples
+// [kBoxLead, kBoxLead + kBoxGradStride).  Both keep the 31-sample reach of
+// the widest (32-sample) window inside the 512-sample tile.
+constexpr int kBoxMaxWidth = 32;
+constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 480
+constexpr int kBoxLead = kBoxMaxWidth;                                // 32
+constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 448
 
 struct SumProblem {
     int32_t nrows = 0;          // b: rows summed
@@ -64,6 +72,7 @@ struct BinLevel {
     int32_t factor = 1;      // ds / ds of the source
     int64_t nbin = 0;        // floor(nsamp / ds)
     int64_t pitch = 0;       // samples per row (multiple of kLevelAlign, > nbin)
+    int64_t lead = 0;        // samples before row 0 (reads at small negative times land here)
     size_t ws_offset = 0;    // byte offset in the workspace (256-byte aligned)
     size_t bytes = 0;
 };
@@ -134,6 +143,12 @@ struct Plan {
     int32_t dw_chunks = 0;                 // time chunks of the weight-gradient reduction
     int64_t dw_chunk_len = 0;
     size_t dw_offset = 0;                  // workspace bytes: partials [nchans][dw_chunks]
+    // boxcar loss (float32 plans): dL/dout of one beam, the loss partials of
+    // one launch, and one beam's weight gradient.
+    size_t gout_offset = 0;                // [out_elems] floats
+    size_t box_offset = 0;                 // [box_partials + 64] floats
+    int64_t box_partials = 0;
+    size_t dwb_offset = 0;                 // [nchans] floats
     void *device = nullptr;                // device-side state (owned by the HIP unit)
 };
 

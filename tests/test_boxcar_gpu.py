@@ -1,0 +1,125 @@
+"""Boxcar loss on the dedispersed output (never stored) and its gradient,
+which recomputes the output tiles, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cref
+from oracle import dedisp as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+dd = pytest.importorskip("paper_1912_07704_amd")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def oracle_loss_and_grads(xs, freqs, tsamp, ranges, w, widths):
+    L, gX, gw = 0.0, [], np.zeros(len(freqs))
+    for x in xs:
+        flat = cref.dedisperse_f32(x, freqs, tsamp, ranges, w)
+        plan = O.expand_plan(freqs, tsamp, x.shape[1], ranges)
+        outs, off = [], 0
+        for r in plan:
+            n = len(r.dms) * r.nout
+            outs.append(flat[off: off + n].reshape(len(r.dms), r.nout))
+            off += n
+        L += O.boxcar_loss(outs, widths)
+        g = O.concat(O.boxcar_loss_grad(outs, widths))
+        dX, dw = cref.adjoint_f32(x, freqs, tsamp, ranges, g, w)
+        gX.append(dX)
+        gw += dw
+    return L, gX, gw
+
+
+def normwise(got, want):
+    return float(np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-30))
+
+
+@pytest.mark.parametrize("seed,max_width", [(0, 32), (1, 8), (2, 1)])
+def test_small_plans_vs_oracle(seed, max_width):
+    rng = np.random.default_rng(900 + seed)
+    nch, nsamp, nb = int(rng.integers(3, 90)), int(rng.integers(1500, 5000)), 2
+    freqs = synth.band_freqs(1500.0, 1300.0, nch)
+    ranges = [(0.0, 20.0, 1.0, 1), (20.0, 30.0, 2.0, 2)]
+    tsamp = 2.56e-4
+    xs = rng.standard_normal((nb, nch, nsamp)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, nch).astype(np.float32)
+    widths = tuple(2 ** i for i in range(int(np.log2(max_width)) + 1))
+    say("boxcar small", seed, nch, nsamp, widths)
+    plan = dd.Plan(freqs, tsamp, nsamp, ranges, "f32")
+    xt, wt = torch.from_numpy(xs).cuda(), torch.from_numpy(w).cuda()
+    loss = float(dd.boxcar_loss(xt, plan, wt, max_width))
+    dx, dw = dd.boxcar_backward(xt, plan, wt, max_width)
+    torch.cuda.synchronize()
+    L, gX, gw = oracle_loss_and_grads(list(xs), freqs, tsamp, ranges, w, widths)
+    assert abs(loss - L) <= 1e-5 * L
+    for b in range(nb):
+        assert normwise(dx[b].cpu().numpy(), gX[b]) <= 2e-5
+    assert normwise(dw.cpu().numpy(), gw) <= 2e-5
+
+
+def test_differentiable_beam_plan_reduced_length_vs_oracle():
+    """The batched-differentiable plan (4096 channels, DM 0..999) on two
+    beams shortened to 2^14 samples, against the FP64 oracle."""
+    full = synth.batched_differentiable(2, nsamp=1 << 14)
+    w0 = full[0]
+    say("boxcar 4096ch reduced length")
+    xs = [synth.filterbank_f32(w.seed, w.nchans, w.nsamp) for w in full]
+    wts = (1.0 + 0.1 * synth.gaussian(7, (w0.nchans,), "weights")).astype(np.float32)
+    plan = dd.Plan(w0.freqs, w0.tsamp, w0.nsamp, w0.ranges, "f32")
+    xt = torch.from_numpy(np.stack(xs)).cuda()
+    wt = torch.from_numpy(wts).cuda()
+    loss = float(dd.boxcar_loss(xt, plan, wt))
+    dx, dw = dd.boxcar_backward(xt, plan, wt)
+    torch.cuda.synchronize()
+    L, gX, gw = oracle_loss_and_grads(xs, w0.freqs, w0.tsamp, w0.ranges, wts, O.BOXCAR_WIDTHS)
+    assert abs(loss - L) <= 1e-5 * L
+    for b in range(2):
+        assert normwise(dx[b].cpu().numpy(), gX[b]) <= 2e-5
+    assert normwise(dw.cpu().numpy(), gw) <= 2e-5
+
+
+def test_batched_differentiable_full_size():
+    """32 beams x 4096 channels x 2^17 float32, DM 0..999: the loss of the
+    batch is the sum of the beams' losses, the weight gradient adds over
+    beams, and (the loss being quadratic in the weights) central differences
+    match the weight gradient."""
+    wls = synth.batched_differentiable()
+    w0 = wls[0]
+    say("boxcar full size: inputs")
+    plan = dd.Plan(w0.freqs, w0.tsamp, w0.nsamp, w0.ranges, "f32")
+    x = torch.empty((len(wls), w0.nchans, w0.nsamp), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    for b, w in enumerate(wls):
+        gen.manual_seed(w.seed)
+        x[b].normal_(generator=gen)
+    wt = torch.ones(w0.nchans, dtype=torch.float32, device="cuda")
+    ws = dd.workspace(plan)
+    say("boxcar full size: loss + backward")
+    loss = float(dd.boxcar_loss(x, plan, wt, ws=ws))
+    dx, dw = dd.boxcar_backward(x, plan, wt, ws=ws)
+    torch.cuda.synchronize()
+    assert np.isfinite(loss) and loss > 0
+    assert torch.isfinite(dx).all() and torch.isfinite(dw).all()
+    per = [float(dd.boxcar_loss(x[b], plan, wt, ws=ws)) for b in range(len(wls))]
+    assert abs(loss - sum(per)) <= 1e-5 * loss
+    del dx
+    _, dw01 = dd.boxcar_backward(x[:2], plan, wt, ws=ws, grad_in=False)
+    _, dw0 = dd.boxcar_backward(x[:1], plan, wt, ws=ws, grad_in=False)
+    _, dw1 = dd.boxcar_backward(x[1:2], plan, wt, ws=ws, grad_in=False)
+    torch.cuda.synchronize()
+    assert torch.allclose(dw01, dw0 + dw1, rtol=1e-5, atol=1e-3 * float(dw01.abs().max()) * 1e-3)
+    # L(w) on one beam is a quadratic form in w: central differences are exact
+    # up to rounding; the float32 loss limits agreement to ~1e-3 relative.
+    h = 0.25
+    for c in (0, 2048, 4095):
+        e = torch.zeros_like(wt)
+        e[c] = h
+        lp = float(dd.boxcar_loss(x[0], plan, wt + e, ws=ws))
+        lm = float(dd.boxcar_loss(x[0], plan, wt - e, ws=ws))
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - float(dw0[c])) <= 2e-3 * abs(float(dw0[c])) + 1e-6 * lp, (c, fd, float(dw0[c]))
