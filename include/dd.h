@@ -110,6 +110,26 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
                          int64_t nsamp, const dd_range *ranges, int32_t nranges,
                          dd_dtype dtype, dd_plan **out);
 
+/*
+ * Strategy options for dd_plan_create_ex (paper, "Plan and strategy": the
+ * strategy is configured once, then immutable).  Zero means "library
+ * default" for every field.
+ *   variant      DD_U8 shift-and-sum kernel: 1 = re-read a channel's words
+ *                for every DM, 2 = re-read only when the DM's delay differs
+ *                from the previous DM's.
+ *   stage_chans  channels staged in LDS at once (rounded down to even,
+ *                clamped to what the LDS and, for DD_U8, the exact 16-bit
+ *                partial sums allow).
+ */
+typedef struct {
+    int32_t variant;
+    int32_t stage_chans;
+} dd_options;
+
+dd_status dd_plan_create_ex(const double *freqs_mhz, int32_t nchans, double tsamp_s,
+                            int64_t nsamp, const dd_range *ranges, int32_t nranges,
+                            dd_dtype dtype, const dd_options *options, dd_plan **out);
+
 /* Release the plan, its host tables and every device copy it made.
  * NULL-safe.  No call on the plan may be in flight on any stream. */
 void dd_plan_destroy(dd_plan *plan);
@@ -150,9 +170,10 @@ dd_status dd_plan_shifts(const dd_plan *plan, int32_t *shifts_out);
  *   dm_tile        trial DMs per workgroup
  *   chans_stage    largest number of channels staged in LDS at once
  *   workgroups     workgroups of one forward launch
+ *   variant        kernel variant (see dd_options)
  */
 dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_tile,
-                           int32_t *chans_stage, int64_t *workgroups);
+                           int32_t *chans_stage, int64_t *workgroups, int32_t *variant);
 
 /*
  * Device workspace a forward call needs, in bytes (paper, "Memory

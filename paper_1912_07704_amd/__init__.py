@@ -39,10 +39,16 @@ class RangeInfo:
     downsample: int
 
 
-class Plan:
-    """Immutable dedispersion plan (wraps dd_plan_create / dd_plan_destroy)."""
+class _Options(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("stage_chans", ctypes.c_int32)]
 
-    def __init__(self, freqs_mhz, tsamp_s: float, nsamp: int, ranges, dtype: str = "u8"):
+
+class Plan:
+    """Immutable dedispersion plan (wraps dd_plan_create_ex / dd_plan_destroy).
+    `variant` and `stage_chans` fix the strategy (0 = library default)."""
+
+    def __init__(self, freqs_mhz, tsamp_s: float, nsamp: int, ranges, dtype: str = "u8",
+                 variant: int = 0, stage_chans: int = 0):
         L = lib()
         f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         rg = (_Range * len(ranges))(*[_Range(float(a), float(b), float(c), int(d))
@@ -52,9 +58,11 @@ class Plan:
         self.nchans = int(f.size)
         self.nsamp = int(nsamp)
         self.tsamp = float(tsamp_s)
-        check(L.dd_plan_create(f.ctypes.data_as(ctypes.c_void_p), f.size, float(tsamp_s),
-                               int(nsamp), rg, len(ranges), _DTYPES[dtype],
-                               ctypes.byref(self._h)), "dd_plan_create")
+        opts = _Options(int(variant), int(stage_chans))
+        check(L.dd_plan_create_ex(f.ctypes.data_as(ctypes.c_void_p), f.size, float(tsamp_s),
+                                  int(nsamp), rg, len(ranges), _DTYPES[dtype], ctypes.byref(opts),
+                                  ctypes.byref(self._h)), "dd_plan_create_ex")
+        self.args = (f.copy(), float(tsamp_s), int(nsamp), [tuple(r) for r in ranges], dtype)
         nd, oe, ov = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
         check(L.dd_plan_info(self._h, ctypes.byref(nd), ctypes.byref(oe), ctypes.byref(ov)),
               "dd_plan_info")
@@ -71,11 +79,12 @@ class Plan:
         ws = ctypes.c_size_t()
         check(L.dd_workspace_bytes(self._h, ctypes.byref(ws)), "dd_workspace_bytes")
         self.workspace_bytes = ws.value
-        tt, dt, cs, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        tt, dt, cs, wg, va = (ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                              ctypes.c_int64(), ctypes.c_int32())
         check(L.dd_plan_strategy(self._h, ctypes.byref(tt), ctypes.byref(dt), ctypes.byref(cs),
-                                 ctypes.byref(wg)), "dd_plan_strategy")
+                                 ctypes.byref(wg), ctypes.byref(va)), "dd_plan_strategy")
         self.strategy = {"time_tile": tt.value, "dm_tile": dt.value,
-                         "chans_stage": cs.value, "workgroups": wg.value}
+                         "chans_stage": cs.value, "workgroups": wg.value, "variant": va.value}
 
     @property
     def handle(self):

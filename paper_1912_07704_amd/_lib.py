@@ -18,7 +18,8 @@ SIGNATURES = {
     "dd_plan_nranges": (ctypes.c_int, [P, P]),
     "dd_plan_dms": (ctypes.c_int, [P, P]),
     "dd_plan_shifts": (ctypes.c_int, [P, P]),
-    "dd_plan_strategy": (ctypes.c_int, [P, P, P, P, P]),
+    "dd_plan_create_ex": (ctypes.c_int, [P, I32, F64, I64, P, I32, ctypes.c_int, P, P]),
+    "dd_plan_strategy": (ctypes.c_int, [P, P, P, P, P, P]),
     "dd_workspace_bytes": (ctypes.c_int, [P, P]),
     "dd_plan_prepare": (ctypes.c_int, [P]),
     "dd_forward": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),

@@ -19,6 +19,14 @@ extern "C" {
 dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s, int64_t nsamp,
                          const dd_range *ranges, int32_t nranges, dd_dtype dtype, dd_plan **out)
 {
+    return dd_plan_create_ex(freqs_mhz, nchans, tsamp_s, nsamp, ranges, nranges, dtype, nullptr,
+                             out);
+}
+
+dd_status dd_plan_create_ex(const double *freqs_mhz, int32_t nchans, double tsamp_s,
+                            int64_t nsamp, const dd_range *ranges, int32_t nranges,
+                            dd_dtype dtype, const dd_options *options, dd_plan **out)
+{
     clear_error();
     if (!out) {
         set_error("out must not be NULL");
@@ -33,8 +41,8 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
     std::string err;
     dd_status st;
     try {
-        st = dd::build_plan(freqs_mhz, nchans, tsamp_s, nsamp, ranges, nranges, dtype, &pl->p,
-                            &err);
+        st = dd::build_plan(freqs_mhz, nchans, tsamp_s, nsamp, ranges, nranges, dtype, options,
+                            &pl->p, &err);
     } catch (...) {
         st = DD_ERR_NOMEM;
         err = "unexpected host failure while building the plan";
@@ -132,20 +140,25 @@ dd_status dd_plan_shifts(const dd_plan *plan, int32_t *shifts_out)
 }
 
 dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_tile,
-                           int32_t *chans_stage, int64_t *workgroups)
+                           int32_t *chans_stage, int64_t *workgroups, int32_t *variant)
 {
     clear_error();
     if (!plan) {
         set_error("plan must not be NULL");
         return DD_ERR_NULL;
     }
+    const bool f32 = plan->p.dtype == DD_F32;
     int32_t st = 0;
-    for (const dd::RangeInfo &ri : plan->p.ranges)
-        st = ri.stage_chans > st ? ri.stage_chans : st;
+    for (const dd::RangeInfo &ri : plan->p.ranges) {
+        const int32_t c = f32 ? ri.fwd.stage_rows : ri.stage_chans;
+        st = c > st ? c : st;
+    }
     if (time_tile)
-        *time_tile = dd::kTimeTile;
+        *time_tile = f32 ? dd::kF32TimeTile : dd::kTimeTile;
     if (dm_tile)
-        *dm_tile = dd::kDmTile;
+        *dm_tile = f32 ? dd::kF32OutTile : dd::kDmTile;
+    if (variant)
+        *variant = plan->p.dedup ? 2 : 1;
     if (chans_stage)
         *chans_stage = st;
     if (workgroups)

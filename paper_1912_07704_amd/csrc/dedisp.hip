@@ -227,6 +227,9 @@ __device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int 
 
 // One work item: range R, item index lb inside the range (time tile major,
 // DM tile minor).  `lds` holds two stages of two copies each.
+// DEDUP: a channel's words are re-read from LDS only when a DM's offset
+// differs from the previous DM's (consecutive DMs share a delay often).
+template <bool DEDUP>
 __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, uint32_t *lds)
 {
     const int64_t tt = lb / R.ndm_tiles;
@@ -302,13 +305,33 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
                 const int4 b1 = *reinterpret_cast<const int4 *>(ob + 4);
                 const int offb[kDW] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
                 const uint32_t *rowb = rowa + Wr;
+                if constexpr (DEDUP) {
+                    uint32_t va[kNW], vb[kNW];
 #pragma unroll
-                for (int dd = 0; dd < kDW; ++dd) {
-                    const uint32_t *pa = rowa + offa[dd];
-                    const uint32_t *pb = rowb + offb[dd];
+                    for (int dd = 0; dd < kDW; ++dd) {
+                        if (dd == 0 || offa[dd] != offa[dd - 1]) {
 #pragma unroll
-                    for (int k = 0; k < kNW; ++k)
-                        acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                            for (int k = 0; k < kNW; ++k)
+                                va[k] = rowa[offa[dd] + kWave * k];
+                        }
+                        if (dd == 0 || offb[dd] != offb[dd - 1]) {
+#pragma unroll
+                            for (int k = 0; k < kNW; ++k)
+                                vb[k] = rowb[offb[dd] + kWave * k];
+                        }
+#pragma unroll
+                        for (int k = 0; k < kNW; ++k)
+                            acc16[dd][k] += va[k] + vb[k];
+                    }
+                } else {
+#pragma unroll
+                    for (int dd = 0; dd < kDW; ++dd) {
+                        const uint32_t *pa = rowa + offa[dd];
+                        const uint32_t *pb = rowb + offb[dd];
+#pragma unroll
+                        for (int k = 0; k < kNW; ++k)
+                            acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                    }
                 }
             } else {
 #pragma unroll
@@ -350,6 +373,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
 }
 
 
+template <bool DEDUP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
 {
     extern __shared__ uint32_t lds[];
@@ -364,7 +388,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     for (int i = 1; i < a.nranges; ++i)
         if (L >= a.r[i].block_start)
             r = i;
-    dedisp_tile_u8(a.r[r], L - a.r[r].block_start, lds);
+    dedisp_tile_u8<DEDUP>(a.r[r], L - a.r[r].block_start, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -773,6 +797,7 @@ __global__ void k_reset_counters(int32_t *counters, int n)
         counters[threadIdx.x] = 0;
 }
 
+template <bool DEDUP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
                   int ndesc, int64_t nitems, int64_t per_queue, const char *ws, int32_t *out,
@@ -815,7 +840,7 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
         R.stage_chans = D.stage_chans;
         R.row_words = D.row_words;
         R.widen_every = D.widen_every;
-        dedisp_tile_u8(R, L - D.item_start, lds);
+        dedisp_tile_u8<DEDUP>(R, L - D.item_start, lds);
     }
 }
 
@@ -884,12 +909,20 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
     }
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8<false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dd::kMaxLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8<true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(dd::kMaxLdsBytes));
     });
     const int64_t grid = a.per_xcd * kXcds;
-    hipLaunchKernelGGL(k_dedisp_u8, dim3(unsigned(grid)), dim3(kBlock), p.lds_bytes, stream, a);
+    if (p.dedup)
+        hipLaunchKernelGGL(k_dedisp_u8<true>, dim3(unsigned(grid)), dim3(kBlock), p.lds_bytes,
+                           stream, a);
+    else
+        hipLaunchKernelGGL(k_dedisp_u8<false>, dim3(unsigned(grid)), dim3(kBlock), p.lds_bytes,
+                           stream, a);
     return launch_check("k_dedisp_u8");
 }
 
@@ -1242,14 +1275,23 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
         return st;
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch<true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dd::kMaxLdsBytes - 64));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch<false>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(dd::kMaxLdsBytes - 64));
     });
     const int64_t per_queue = (b.nitems + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(k_dedisp_u8_batch, dim3(unsigned(kXcds * kPersistPerXcd)), dim3(kBlock),
-                       b.lds_bytes, stream, bd.descs, bd.starts, int(b.descs.size()), b.nitems,
-                       per_queue, d_ws, d_out, counters);
+    const dim3 grid(unsigned(kXcds * kPersistPerXcd));
+    if (b.dedup)
+        hipLaunchKernelGGL(k_dedisp_u8_batch<true>, grid, dim3(kBlock), b.lds_bytes, stream,
+                           bd.descs, bd.starts, int(b.descs.size()), b.nitems, per_queue, d_ws,
+                           d_out, counters);
+    else
+        hipLaunchKernelGGL(k_dedisp_u8_batch<false>, grid, dim3(kBlock), b.lds_bytes, stream,
+                           bd.descs, bd.starts, int(b.descs.size()), b.nitems, per_queue, d_ws,
+                           d_out, counters);
     return launch_check("k_dedisp_u8_batch");
 }
 

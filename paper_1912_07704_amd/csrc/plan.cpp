@@ -38,7 +38,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 template <typename SFn>
 dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S,
                             std::vector<int32_t> &offF, std::vector<int32_t> &baseF,
-                            int64_t *blocks, size_t *lds, std::string *err, const char *what)
+                            int64_t *blocks, size_t *lds, std::string *err, const char *what,
+                            int32_t want_stage)
 {
     sp.nrows = nrows;
     sp.nouts = nouts;
@@ -64,7 +65,9 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
     }
     sp.span = span;
     sp.row_words = (kF32TimeTile + 3 + span + 4 + 3) / 4 * 4;
-    int32_t stage = kF32MaxStage;
+    int32_t stage = want_stage > 0 ? std::max(1, std::min(want_stage, kF32MaxStage)) : kF32MaxStage;
+    if (stage > 1)
+        stage &= ~1;
     auto bytes_for = [&](int32_t st) { return size_t(8) * size_t(st) * size_t(sp.row_words); };
     while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
         stage = stage > 2 ? stage - 2 : 1;
@@ -103,7 +106,7 @@ const char *last_error() { return g_last_error.c_str(); }
 
 // Float32 plans: weighted 32-bit level copies, forward and adjoint problems
 // of the generic shift-and-sum, and the adjoint's workspace buffers.
-dd_status build_f32(Plan *p, std::string *err)
+dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
 {
     const int32_t nchans = p->nchans;
     const int64_t nsamp = p->nsamp;
@@ -124,7 +127,7 @@ dd_status build_f32(Plan *p, std::string *err)
         const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
         auto Sf = [&](int32_t a, int32_t b) { return sh[size_t(a) * nchans + b]; };
         dd_status st = build_sum_problem(ri.fwd, nchans, ri.ndms, ri.nout, Sf, p->offF, p->baseF,
-                                         &blocks, &lds, err, "forward");
+                                         &blocks, &lds, err, "forward", want_stage);
         if (st != DD_OK)
             return st;
     }
@@ -134,7 +137,7 @@ dd_status build_f32(Plan *p, std::string *err)
         const int32_t P = ri.max_shift;
         auto Sa = [&](int32_t a, int32_t b) { return P - sh[size_t(b) * nchans + a]; };
         dd_status st = build_sum_problem(ri.adj, ri.ndms, nchans, ri.nbin, Sa, p->offF, p->baseF,
-                                         &ablocks, &alds, err, "adjoint");
+                                         &ablocks, &alds, err, "adjoint", want_stage);
         if (st != DD_OK)
             return st;
     }
@@ -200,9 +203,15 @@ dd_status build_f32(Plan *p, std::string *err)
 }
 
 dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t nsamp,
-                     const dd_range *ranges, int32_t nranges, dd_dtype dtype, Plan *p,
-                     std::string *err)
+                     const dd_range *ranges, int32_t nranges, dd_dtype dtype,
+                     const dd_options *opts, Plan *p, std::string *err)
 {
+    const int32_t want_variant = opts ? opts->variant : 0;
+    const int32_t want_stage = opts ? opts->stage_chans : 0;
+    if (want_variant < 0 || want_variant > 2 || want_stage < 0) {
+        *err = "options: variant must be 0, 1 or 2 and stage_chans >= 0";
+        return DD_ERR_INVALID;
+    }
     if (!freqs || !ranges || !p) {
         *err = "freqs_mhz, ranges and out must not be NULL";
         return DD_ERR_NULL;
@@ -327,8 +336,9 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         }
         p->out_elems = out_off;
 
+        p->dedup = want_variant != 1;
         if (dtype == DD_F32)
-            return build_f32(p, err);
+            return build_f32(p, want_stage, err);
 
         // Tile strategy: a time tile of kTimeTile samples by a DM tile of
         // kDmTile trials per workgroup.  Channels are staged in LDS in groups
@@ -350,7 +360,7 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             const int32_t imax = 64 * kWaveWords + 2 + ((span + 1) >> 1);
             ri.row_words = (imax + 2 + 3) / 4 * 4;
             const int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
-            int32_t stage = std::max(1, std::min(kMaxStageChans, cap));
+            int32_t stage = std::max(1, std::min(want_stage > 0 ? want_stage : kMaxStageChans, cap));
             if (stage > 1)
                 stage &= ~1;
             auto bytes_for = [&](int32_t st) {

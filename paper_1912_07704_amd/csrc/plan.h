@@ -134,6 +134,7 @@ struct Plan {
     size_t ws_bytes = 0;
     int64_t blocks = 0;                    // workgroups of one forward launch
     size_t lds_bytes = 0;                  // dynamic LDS of the forward kernel
+    bool dedup = true;                     // integer kernel variant (see dd_plan_set_variant)
     // float32 plans: tables of the generic shift-and-sum (forward problems
     // then adjoint problems), and the adjoint's reduction buffer.
     std::vector<int32_t> offF;
@@ -155,8 +156,8 @@ struct Plan {
 // Host core (plan.cpp).  On failure returns a negative status and writes a
 // message into *err.
 dd_status build_plan(const double *freqs_mhz, int32_t nchans, double tsamp_s, int64_t nsamp,
-                     const dd_range *ranges, int32_t nranges, dd_dtype dtype, Plan *p,
-                     std::string *err);
+                     const dd_range *ranges, int32_t nranges, dd_dtype dtype,
+                     const dd_options *opts, Plan *p, std::string *err);
 
 // Device-side state of a plan (allocated by the HIP unit, freed by
 // dd_plan_destroy).
@@ -187,6 +188,7 @@ struct Batch {
     std::vector<BatchDescHost> descs;      // most expensive items first
     int64_t nitems = 0;
     size_t lds_bytes = 0;
+    bool dedup = true;
     void *device = nullptr;
 };
 
