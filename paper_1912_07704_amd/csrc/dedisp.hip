@@ -1299,9 +1299,9 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
 // any HIP call).
 dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float *d_weights,
                              const void *d_out, int64_t out_capacity, const void *d_ws,
-                             size_t ws_bytes, bool need_out)
+                             size_t ws_bytes, bool need_out, bool need_in = true)
 {
-    if (!plan || !d_in || (need_out && !d_out)) {
+    if (!plan || (need_in && !d_in) || (need_out && !d_out)) {
         dd::set_error("plan, d_in and d_out must not be NULL");
         return DD_ERR_NULL;
     }
@@ -1310,7 +1310,7 @@ dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float 
         dd::set_error("per-channel weights apply to DD_F32 plans only");
         return DD_ERR_DTYPE;
     }
-    if (reinterpret_cast<uintptr_t>(d_in) % 4 != 0) {
+    if (need_in && reinterpret_cast<uintptr_t>(d_in) % 4 != 0) {
         dd::set_error("d_in must be 4-byte aligned");
         return DD_ERR_INVALID;
     }
@@ -1443,9 +1443,8 @@ dd_status dd_forward_sum(const dd_plan *plan, void *d_out, int64_t out_capacity,
                          size_t ws_bytes, void *stream)
 {
     dd::clear_error();
-    static const char dummy = 0;
-    dd_status st = check_forward_args(plan, &dummy, nullptr, d_out, out_capacity, d_ws, ws_bytes,
-                                      true);
+    dd_status st = check_forward_args(plan, nullptr, nullptr, d_out, out_capacity, d_ws, ws_bytes,
+                                      true, false);
     if (st != DD_OK)
         return st;
     DeviceTables *t = nullptr;
