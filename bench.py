@@ -87,6 +87,98 @@ def cpu_baseline(w, x, target_s: float):
                        f"oracle, OpenMP over DM trials")}
 
 
+def _time(torch, fn, n):
+    ts = []
+    for _ in range(n):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+def leg_fwdbwd(dd, synth, torch, plain_value):
+    """Differentiable workload (1024 ch float32, 2^16 samples, DM 0..511):
+    forward with weights, then the hand-written adjoint (dX and dw)."""
+    w = synth.differentiable()
+    log("leg fwd+bwd:", w.name)
+    x = torch.from_numpy(w.make_input()).cuda()
+    wt = torch.ones(w.nchans, device="cuda")
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32")
+    ws = dd.workspace(plan)
+    out = dd.dedisperse(x, plan, weights=wt, ws=ws)
+    g = torch.randn(plan.out_elems, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(w.seed))
+    dd.adjoint(g, plan, x=x, weights=wt, ws=ws)
+    torch.cuda.synchronize()
+    f_ms = _time(torch, lambda: dd.dedisperse(x, plan, out=out, weights=wt, ws=ws), 5)
+    b_ms = _time(torch, lambda: dd.adjoint(g, plan, x=x, weights=wt, ws=ws), 5)
+    samples = plan.out_elems
+    v = samples / ((f_ms + b_ms) / 1e3)
+    return {"workload": w.name, "fwd_ms": f_ms, "bwd_ms": b_ms,
+            "fwd_dm_trial_samples_per_s": samples / (f_ms / 1e3),
+            "fwd_bwd_dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
+            "note": "float32; plain = the uint8 single-beam value of this line"}
+
+
+def leg_batched(dd, synth, torch, plain_value, opts):
+    """64 uint8 beams of uneven shape in one persistent launch (inputs drawn
+    on the GPU, excluded from timing)."""
+    wls = synth.batched_beams()
+    log("leg batched:", len(wls), "beams")
+    o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile")}
+    plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **o) for w in wls]
+    batch = dd.Batch(plans)
+    batch.prepare()
+    xin = torch.empty(batch.in_bytes, dtype=torch.uint8, device="cuda")
+    for w, p, off in zip(wls, plans, batch.in_offsets):
+        xin[off: off + p.nchans * p.nsamp] = synth.filterbank_u8_device(
+            w.seed, w.freqs, w.tsamp, w.nsamp, w.pulses).reshape(-1)
+    out = torch.empty(batch.out_elems, dtype=torch.int32, device="cuda")
+    ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
+    dd.dedisperse_batch(xin, batch, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ms = _time(torch, lambda: dd.dedisperse_batch(xin, batch, out=out, ws=ws), 3)
+    samples = sum(p.out_elems for p in plans)
+    v = samples / (ms / 1e3)
+    res = {"workload": f"{len(wls)} uint8 beams, 1024-4096 ch, 2^16-2^18 samples, DM max "
+                       "500/1000/2000", "ms": ms, "dm_trial_samples": samples,
+           "dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
+           "work_items": batch.work_items, "launches": "bins per beam + 1 persistent"}
+    del xin, out, ws
+    batch.close()
+    return res
+
+
+def leg_boxcar(dd, synth, torch):
+    """32 float32 beams x 4096 ch x 2^17, DM 0..999: boxcar loss (out never
+    stored) and its backward (out recomputed, adjoint)."""
+    wls = synth.batched_differentiable()
+    w0 = wls[0]
+    log("leg boxcar:", len(wls), "beams")
+    plan = dd.Plan(w0.freqs, w0.tsamp, w0.nsamp, w0.ranges, "f32")
+    x = torch.empty((len(wls), w0.nchans, w0.nsamp), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    for b, w in enumerate(wls):
+        gen.manual_seed(w.seed)
+        x[b].normal_(generator=gen)
+    wt = torch.ones(w0.nchans, device="cuda")
+    ws = dd.workspace(plan)
+    dd.boxcar_loss(x, plan, wt, ws=ws)
+    torch.cuda.synchronize()
+    l_ms = _time(torch, lambda: dd.boxcar_loss(x, plan, wt, ws=ws), 1)
+    dx, dw = dd.boxcar_backward(x, plan, wt, ws=ws)
+    torch.cuda.synchronize()
+    b_ms = _time(torch, lambda: dd.boxcar_backward(x, plan, wt, ws=ws), 1)
+    samples = plan.out_elems * len(wls)
+    return {"workload": f"{len(wls)} float32 beams x 4096 ch x 2^17, DM 0..999, boxcar 1..32",
+            "loss_ms": l_ms, "backward_ms": b_ms,
+            "fwd_dm_trial_samples_per_s": samples / (l_ms / 1e3),
+            "fwd_bwd_dm_trial_samples_per_s": samples / ((l_ms + b_ms) / 1e3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +186,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the default strategy")
+    ap.add_argument("--legs", default="fwdbwd,batched,boxcar",
+                    help="extra legs after the main one: fwdbwd,batched,boxcar (or none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -114,8 +209,17 @@ def main() -> int:
     torch.cuda.set_device(dev)
     xt = torch.from_numpy(x).to(dev)
 
+    tune_info = None
+    opts = {}
+    if not args.no_tune:
+        from paper_1912_07704_amd import tune as tuner
+        t = time.perf_counter()
+        opts, timings = tuner.tune(w.freqs, w.tsamp, w.nsamp, w.ranges, x=xt, use_cache=False)
+        tune_info = {"best": opts, "seconds": round(time.perf_counter() - t, 2),
+                     "candidates_sum_ms": [[o, round(m, 3)] for o, m in timings]}
+        log("tuned strategy", opts)
     t = time.perf_counter()
-    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges)
+    plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **opts)
     t_plan = time.perf_counter() - t
     t = time.perf_counter()
     plan.prepare()
@@ -198,7 +302,21 @@ def main() -> int:
                                           if traffic else None)},
         "steps_ms": {"bin": ms_bin, "sum": ms_sum, "plan_create_s": t_plan,
                      "table_upload_s": t_upload, "wall_s": wall},
+        "strategy": plan.strategy,
+        "tuning": tune_info,
     }
+    del out, ws
+    torch.cuda.empty_cache()
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    if "fwdbwd" in legs:
+        res["fwd_bwd"] = leg_fwdbwd(dd, synth, torch, value)
+    if "batched" in legs:
+        del xt
+        torch.cuda.empty_cache()
+        res["batched"] = leg_batched(dd, synth, torch, value, opts)
+    if "boxcar" in legs:
+        torch.cuda.empty_cache()
+        res["boxcar"] = leg_boxcar(dd, synth, torch)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, x, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -120,10 +120,12 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *   stage_chans  channels staged in LDS at once (rounded down to even,
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
  *                partial sums allow).
+ *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8).
  */
 typedef struct {
     int32_t variant;
     int32_t stage_chans;
+    int32_t dm_tile;
 } dd_options;
 
 dd_status dd_plan_create_ex(const double *freqs_mhz, int32_t nchans, double tsamp_s,

@@ -40,7 +40,8 @@ class RangeInfo:
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("variant", ctypes.c_int32), ("stage_chans", ctypes.c_int32)]
+    _fields_ = [("variant", ctypes.c_int32), ("stage_chans", ctypes.c_int32),
+                ("dm_tile", ctypes.c_int32)]
 
 
 class Plan:
@@ -48,7 +49,7 @@ class Plan:
     `variant` and `stage_chans` fix the strategy (0 = library default)."""
 
     def __init__(self, freqs_mhz, tsamp_s: float, nsamp: int, ranges, dtype: str = "u8",
-                 variant: int = 0, stage_chans: int = 0):
+                 variant: int = 0, stage_chans: int = 0, dm_tile: int = 0):
         L = lib()
         f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         rg = (_Range * len(ranges))(*[_Range(float(a), float(b), float(c), int(d))
@@ -58,7 +59,7 @@ class Plan:
         self.nchans = int(f.size)
         self.nsamp = int(nsamp)
         self.tsamp = float(tsamp_s)
-        opts = _Options(int(variant), int(stage_chans))
+        opts = _Options(int(variant), int(stage_chans), int(dm_tile))
         check(L.dd_plan_create_ex(f.ctypes.data_as(ctypes.c_void_p), f.size, float(tsamp_s),
                                   int(nsamp), rg, len(ranges), _DTYPES[dtype], ctypes.byref(opts),
                                   ctypes.byref(self._h)), "dd_plan_create_ex")

@@ -45,8 +45,13 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
             b->ws_off[i] = ws;
             ws = align_up(ws + p->ws_bytes, 256);
             lds = std::max(lds, p->lds_bytes);
-            if (i == 0)
+            if (i == 0) {
                 b->dedup = p->dedup;
+                b->waves = p->waves;
+            } else if (p->waves != b->waves) {
+                *err = "all plans of a batch need the same DM tile";
+                return DD_ERR_INVALID;
+            }
         }
         b->in_bytes = int64_t(in);
         b->out_elems = int64_t(out);

@@ -156,7 +156,7 @@ dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_
     if (time_tile)
         *time_tile = f32 ? dd::kF32TimeTile : dd::kTimeTile;
     if (dm_tile)
-        *dm_tile = f32 ? dd::kF32OutTile : dd::kDmTile;
+        *dm_tile = f32 ? dd::kF32OutTile : plan->p.dm_tile;
     if (variant)
         *variant = plan->p.dedup ? 2 : 1;
     if (chans_stage)

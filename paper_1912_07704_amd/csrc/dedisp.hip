@@ -206,13 +206,14 @@ __device__ __forceinline__ void wait_loads()
 // Start the direct-to-LDS loads of the windows of channels [cs, cs + cn)
 // into the A copy at `buf` (row j at buf + j*Wr).  One wave instruction
 // moves 64 lanes x 16 bytes of one row.
+template <int WAVES>
 __device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int tile, int64_t t0,
                                             int cs, int cn, uint32_t *buf, int wave, int lane)
 {
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
     const int ipr = (chunks + kWave - 1) / kWave;
-    for (int i = wave; i < cn * ipr; i += kWavesPerBlock) {
+    for (int i = wave; i < cn * ipr; i += WAVES) {
         const int j = i / ipr;
         const int part = i - j * ipr;
         const int q = part * kWave + lane;
@@ -229,12 +230,14 @@ __device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int 
 // DM tile minor).  `lds` holds two stages of two copies each.
 // DEDUP: a channel's words are re-read from LDS only when a DM's offset
 // differs from the previous DM's (consecutive DMs share a delay often).
-template <bool DEDUP>
+template <bool DEDUP, int WAVES>
 __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, uint32_t *lds)
 {
+    constexpr int kTileDW = WAVES * kDW;
+    constexpr int kBlockW = WAVES * kWave;
     const int64_t tt = lb / R.ndm_tiles;
     const int tile = int(lb - tt * R.ndm_tiles);
-    const int d0 = tile * kTileD;
+    const int d0 = tile * kTileDW;
     const int64_t t0 = tt * kTileT;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -259,7 +262,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
             acc32[dd][k][1] = 0;
         }
 
-    stage_issue(R, nchans, tile, t0, 0, min(C, nchans), lds, wave, lane);
+    stage_issue<WAVES>(R, nchans, tile, t0, 0, min(C, nchans), lds, wave, lane);
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
         const int cn = min(C, nchans - c0);
@@ -271,7 +274,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         // Odd-aligned copy: B[j][m] = (A[j][m] >> 16) | (A[j][m+1] << 16),
         // four words per thread and step.
         const int quads = Wr >> 2;
-        for (int g = tid; g < cn * quads; g += kBlock) {
+        for (int g = tid; g < cn * quads; g += kBlockW) {
             const int j = g / quads;
             const int m = (g - j * quads) * 4;
             const uint32_t *src = A + j * Wr + m;
@@ -286,7 +289,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         }
         if (st + 1 < nst) {
             const int cs = c0 + C;
-            stage_issue(R, nchans, tile, t0, cs, min(C, nchans - cs),
+            stage_issue<WAVES>(R, nchans, tile, t0, cs, min(C, nchans - cs),
                         lds + ((st + 1) & 1) * (2 * CW), wave, lane);
         }
         lds_barrier();
@@ -373,8 +376,8 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
 }
 
 
-template <bool DEDUP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
+template <bool DEDUP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
 {
     extern __shared__ uint32_t lds[];
 
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     for (int i = 1; i < a.nranges; ++i)
         if (L >= a.r[i].block_start)
             r = i;
-    dedisp_tile_u8<DEDUP>(a.r[r], L - a.r[r].block_start, lds);
+    dedisp_tile_u8<DEDUP, WAVES>(a.r[r], L - a.r[r].block_start, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -797,8 +800,8 @@ __global__ void k_reset_counters(int32_t *counters, int n)
         counters[threadIdx.x] = 0;
 }
 
-template <bool DEDUP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+template <bool DEDUP, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
                   int ndesc, int64_t nitems, int64_t per_queue, const char *ws, int32_t *out,
                   int32_t *counters)
@@ -840,7 +843,7 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
         R.stage_chans = D.stage_chans;
         R.row_words = D.row_words;
         R.widen_every = D.widen_every;
-        dedisp_tile_u8<DEDUP>(R, L - D.item_start, lds);
+        dedisp_tile_u8<DEDUP, WAVES>(R, L - D.item_start, lds);
     }
 }
 
@@ -907,22 +910,21 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
         R.row_words = ri.row_words;
         R.widen_every = ri.widen_every;
     }
-    static std::once_flag attr_once;
-    std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dd::kMaxLdsBytes));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dd::kMaxLdsBytes));
-    });
     const int64_t grid = a.per_xcd * kXcds;
-    if (p.dedup)
-        hipLaunchKernelGGL(k_dedisp_u8<true>, dim3(unsigned(grid)), dim3(kBlock), p.lds_bytes,
-                           stream, a);
+    const void *fn = nullptr;
+    if (p.waves == 4)
+        fn = p.dedup ? reinterpret_cast<const void *>(k_dedisp_u8<true, 4>)
+                     : reinterpret_cast<const void *>(k_dedisp_u8<false, 4>);
     else
-        hipLaunchKernelGGL(k_dedisp_u8<false>, dim3(unsigned(grid)), dim3(kBlock), p.lds_bytes,
-                           stream, a);
+        fn = p.dedup ? reinterpret_cast<const void *>(k_dedisp_u8<true, 8>)
+                     : reinterpret_cast<const void *>(k_dedisp_u8<false, 8>);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(dd::kMaxLdsBytes));
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(p.waves * kWave)), args,
+                                   p.lds_bytes, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "k_dedisp_u8");
     return launch_check("k_dedisp_u8");
 }
 
@@ -1273,25 +1275,29 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
     dd_status st = launch_check("k_reset_counters");
     if (st != DD_OK)
         return st;
-    static std::once_flag attr_once;
-    std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch<true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dd::kMaxLdsBytes - 64));
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_dedisp_u8_batch<false>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dd::kMaxLdsBytes - 64));
-    });
     const int64_t per_queue = (b.nitems + kXcds - 1) / kXcds;
-    const dim3 grid(unsigned(kXcds * kPersistPerXcd));
-    if (b.dedup)
-        hipLaunchKernelGGL(k_dedisp_u8_batch<true>, grid, dim3(kBlock), b.lds_bytes, stream,
-                           bd.descs, bd.starts, int(b.descs.size()), b.nitems, per_queue, d_ws,
-                           d_out, counters);
+    const void *fn = nullptr;
+    if (b.waves == 4)
+        fn = b.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4>)
+                     : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4>);
     else
-        hipLaunchKernelGGL(k_dedisp_u8_batch<false>, grid, dim3(kBlock), b.lds_bytes, stream,
-                           bd.descs, bd.starts, int(b.descs.size()), b.nitems, per_queue, d_ws,
-                           d_out, counters);
+        fn = b.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8>)
+                     : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8>);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(dd::kMaxLdsBytes - 64));
+    const BatchDesc *descs = bd.descs;
+    const int64_t *starts = bd.starts;
+    int ndesc = int(b.descs.size());
+    int64_t nitems = b.nitems;
+    const char *ws = d_ws;
+    void *args[] = {&descs, &starts, &ndesc, &nitems, const_cast<int64_t *>(&per_queue), &ws,
+                    &d_out, &counters};
+    // Persistent workgroups per XCD: two 8-wave (or four 4-wave) per CU of its 32.
+    const unsigned per_xcd = unsigned(kPersistPerXcd * (8 / b.waves));
+    hipError_t e = hipLaunchKernel(fn, dim3(kXcds * per_xcd), dim3(unsigned(b.waves * kWave)),
+                                   args, b.lds_bytes, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "k_dedisp_u8_batch");
     return launch_check("k_dedisp_u8_batch");
 }
 

@@ -208,8 +208,10 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
 {
     const int32_t want_variant = opts ? opts->variant : 0;
     const int32_t want_stage = opts ? opts->stage_chans : 0;
-    if (want_variant < 0 || want_variant > 2 || want_stage < 0) {
-        *err = "options: variant must be 0, 1 or 2 and stage_chans >= 0";
+    const int32_t want_dm_tile = opts ? opts->dm_tile : 0;
+    if (want_variant < 0 || want_variant > 2 || want_stage < 0 ||
+        (want_dm_tile != 0 && want_dm_tile != 32 && want_dm_tile != 64)) {
+        *err = "options: variant must be 0, 1 or 2, stage_chans >= 0, dm_tile 0, 32 or 64";
         return DD_ERR_INVALID;
     }
     if (!freqs || !ranges || !p) {
@@ -337,6 +339,9 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         p->out_elems = out_off;
 
         p->dedup = want_variant != 1;
+        p->dm_tile = want_dm_tile ? want_dm_tile : kDmTile;
+        p->waves = p->dm_tile / kDmPerWave;
+        const int32_t dmt = p->dm_tile;
         if (dtype == DD_F32)
             return build_f32(p, want_stage, err);
 
@@ -349,8 +354,8 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         for (int32_t r = 0; r < nranges; ++r) {
             RangeInfo &ri = p->ranges[r];
             int32_t span = 0;
-            for (int32_t d0 = 0; d0 < ri.ndms; d0 += kDmTile) {
-                const int32_t d1 = std::min(ri.ndms, d0 + kDmTile) - 1;
+            for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
+                const int32_t d1 = std::min(ri.ndms, d0 + dmt) - 1;
                 const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
                 const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d1) * nchans];
                 for (int32_t c = 0; c < nchans; ++c)
@@ -366,7 +371,9 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             auto bytes_for = [&](int32_t st) {
                 return size_t(16) * size_t(st) * size_t(ri.row_words);
             };
-            while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
+            // LDS per workgroup that still lets 16 wavefronts share a CU.
+            const size_t lds_target = kMaxLdsBytes * size_t(p->waves) / 16 - 1024;
+            while (stage > 1 && bytes_for(stage) > lds_target)
                 stage = stage > 2 ? stage - 2 : 1;
             if (bytes_for(stage) > kMaxLdsBytes) {
                 *err = fmt("range ", r, ": delay spread ", span,
@@ -378,8 +385,8 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             ri.widen_every = std::max(1, cap / stage);
             lds = std::max(lds, bytes_for(stage));
             ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
-            ri.ndm_tiles = (ri.ndms + kDmTile - 1) / kDmTile;
-            ri.ndms_pad = ri.ndm_tiles * kDmTile;
+            ri.ndm_tiles = (ri.ndms + dmt - 1) / dmt;
+            ri.ndms_pad = ri.ndm_tiles * dmt;
             ri.block_start = blocks;
             blocks += ri.ntime_tiles * ri.ndm_tiles;
         }
@@ -442,11 +449,11 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             for (int32_t c = 0; c < nchans; ++c) {
                 int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
                 for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile) {
-                    const int32_t b = p->shifts[size_t(ri.dm_index + tile * kDmTile) * nchans + c];
+                    const int32_t b = p->shifts[size_t(ri.dm_index + tile * dmt) * nchans + c];
                     const int32_t par = b & 1;
                     const int32_t e = ((b - par) / 2) & 3;
                     p->baseT[ri.base_offset + size_t(tile) * nchans + c] = (b - par) / 2 - e;
-                    for (int32_t d = tile * kDmTile; d < (tile + 1) * kDmTile; ++d) {
+                    for (int32_t d = tile * dmt; d < (tile + 1) * dmt; ++d) {
                         const int32_t dv = std::min(d, ri.ndms - 1);
                         const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] - b;
                         off[d] = ((o + par) & 1) * copy_words + e + ((o + par) >> 1);

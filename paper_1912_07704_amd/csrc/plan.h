@@ -13,13 +13,13 @@ namespace dd {
 
 // Tile geometry of the integer forward kernel: each wavefront covers
 // kWaveWords 32-bit words per lane (two samples per word) of one time tile,
-// for kDmPerWave trial DMs; a workgroup holds kWaves wavefronts, one DM
-// group each.
-constexpr int kWaves = 8;
+// for kDmPerWave trial DMs; a workgroup holds 4 or 8 wavefronts (a plan
+// option), one DM group each.
+constexpr int kWaves = 8;                        // default; the float32 kernels always use 8
 constexpr int kWaveWords = 4;                    // words per lane
 constexpr int kDmPerWave = 8;
 constexpr int kTimeTile = 128 * kWaveWords;      // samples per workgroup
-constexpr int kDmTile = kWaves * kDmPerWave;     // DMs per workgroup
+constexpr int kDmTile = kWaves * kDmPerWave;     // default DMs per workgroup
 constexpr int kMaxStageChans = 16;               // channels staged at once
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr size_t kLdsTwoBlocks = 80 * 1024;      // LDS that still fits two workgroups per CU
@@ -134,7 +134,9 @@ struct Plan {
     size_t ws_bytes = 0;
     int64_t blocks = 0;                    // workgroups of one forward launch
     size_t lds_bytes = 0;                  // dynamic LDS of the forward kernel
-    bool dedup = true;                     // integer kernel variant (see dd_plan_set_variant)
+    bool dedup = true;                     // integer kernel variant (dd_options.variant)
+    int32_t waves = kWaves;                // integer kernel: wavefronts per workgroup (4 or 8)
+    int32_t dm_tile = kDmTile;             // integer kernel: DMs per workgroup
     // float32 plans: tables of the generic shift-and-sum (forward problems
     // then adjoint problems), and the adjoint's reduction buffer.
     std::vector<int32_t> offF;
@@ -189,6 +191,7 @@ struct Batch {
     int64_t nitems = 0;
     size_t lds_bytes = 0;
     bool dedup = true;
+    int32_t waves = kWaves;
     void *device = nullptr;
 };
 

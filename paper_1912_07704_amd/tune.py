@@ -1,0 +1,124 @@
+"""Autotuner of the integer forward's strategy (paper, "Design of the API":
+the strategy decides how input data are split and processed on the GPU).
+
+For one plan signature it times the shift-and-sum step of every candidate
+strategy -- kernel variant x DM tile x channels per LDS stage -- on the
+current device, checks that every candidate's output is bit-identical to
+the first one's, and keeps the fastest.  Results are cached per (plan
+signature, device) in a JSON file (``DD_TUNE_CACHE``, default
+``~/.cache/paper_1912_07704_amd/tune.json``).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import statistics
+
+from . import Plan, dedisperse, workspace
+
+VARIANTS = (1, 2)
+DM_TILES = (64, 32)
+STAGES = (16, 8, 4)
+
+
+def candidates():
+    return [{"variant": v, "dm_tile": d, "stage_chans": s}
+            for v in VARIANTS for d in DM_TILES for s in STAGES]
+
+
+def _cache_path() -> str:
+    return os.environ.get("DD_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1912_07704_amd",
+                                       "tune.json"))
+
+
+def signature(freqs, tsamp, nsamp, ranges, dtype="u8") -> str:
+    import numpy as np
+    import torch
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    key = json.dumps({"freqs": hashlib.sha1(f.tobytes()).hexdigest(), "nchans": int(f.size),
+                      "tsamp": float(tsamp), "nsamp": int(nsamp),
+                      "ranges": [[float(a), float(b), float(c), int(d)] for a, b, c, d in ranges],
+                      "dtype": dtype, "device": dev}, sort_keys=True)
+    return hashlib.sha1(key.encode()).hexdigest()
+
+
+def _load() -> dict:
+    try:
+        with open(_cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache: dict) -> None:
+    path = _cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def tune(freqs, tsamp, nsamp, ranges, x=None, reps: int = 3, cands=None, use_cache=True):
+    """Time each candidate strategy on the device and return (best options,
+    [(options, median ms of the shift-and-sum step), ...]).  `x` is a device
+    uint8 [nchans, nsamp] input; a seeded uniform one is drawn if None."""
+    import torch
+    sig = signature(freqs, tsamp, nsamp, ranges)
+    cache = _load() if use_cache else {}
+    if use_cache and sig in cache:
+        return cache[sig]["best"], [tuple(t) for t in cache[sig]["timings"]]
+    if x is None:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        x = torch.randint(0, 256, (len(freqs), nsamp), generator=g, device="cuda",
+                          dtype=torch.int32).to(torch.uint8)
+    timings, ref, best = [], None, None
+    for opts in (cands or candidates()):
+        try:
+            plan = Plan(freqs, tsamp, nsamp, ranges, "u8", **opts)
+        except Exception:            # an LDS-infeasible candidate for this plan
+            continue
+        ws = workspace(plan, x.device)
+        out = torch.empty(plan.out_elems, dtype=torch.int32, device=x.device)
+        dedisperse(x, plan, out=out, ws=ws)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"strategy {opts} changed the integer result")
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            dedisperse(x, plan, out=out, ws=ws, step="sum")
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        med = statistics.median(ms)
+        timings.append((dict(opts), med))
+        if best is None or med < best[1]:
+            best = (dict(opts), med)
+        plan.close()
+        del ws, out
+    if best is None:
+        raise RuntimeError("no feasible strategy")
+    if use_cache:
+        cache = _load()
+        cache[sig] = {"best": best[0], "timings": timings}
+        _store(cache)
+    return best[0], timings
+
+
+def tuned_plan(freqs, tsamp, nsamp, ranges, x=None, **kw) -> Plan:
+    """A u8 plan with the fastest strategy for this device (tuned once,
+    then read from the cache)."""
+    best, _ = tune(freqs, tsamp, nsamp, ranges, x=x, **kw)
+    return Plan(freqs, tsamp, nsamp, ranges, "u8", **best)
