@@ -323,6 +323,52 @@ dd_status dd_batch_prepare(dd_batch *batch);
 dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
                            int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream);
 
+/*
+ * Streaming (paper, "Pipeline": the pipeline walks the input in chunks and
+ * reports a status per iteration).  A stream processes a long series in
+ * chunks of the plan's nsamp samples that start `step` samples apart, where
+ * step is the largest multiple of every range's downsample not above any
+ * range's ds_r * nout_r (so nsamp - step is the plan's largest delay,
+ * rounded up to that multiple).  The first step/ds_r output samples of each
+ * DM row of chunk k are the one-shot output samples k*step/ds_r + [0,
+ * step/ds_r) of the whole series: concatenated, the chunks reproduce a
+ * single forward over the series exactly (bit for bit for DD_U8).
+ *
+ * dd_stream_create  plan: borrowed, must outlive the stream.  time_major: 0
+ *                   when pushed blocks are channel-major [nchans][samples],
+ *                   1 when they are time-major [samples][nchans] (SIGPROC
+ *                   filterbank order; transposed on the device).  Host-only.
+ *                   DD_ERR_INVALID when step < nsamp/2.
+ * dd_stream_info    first: samples the first push must supply (nsamp);
+ *                   step: samples every later push supplies.
+ * dd_stream_push    d_block: the next `samples` samples of the series in the
+ *                   stream's layout (device, read only).  d_chunk: the
+ *                   caller-owned chunk buffer [nchans][nsamp] of the plan's
+ *                   input type, kept between pushes (it carries the
+ *                   overlap).  Then runs dd_forward on the chunk into d_out
+ *                   (d_weights, d_ws as for dd_forward).  *chunk_index (may
+ *                   be NULL) receives the chunk's index.  DD_ERR_INVALID if
+ *                   samples is not `first` (first push) or `step` (later).
+ * dd_stream_reset   the next push is a first push again.
+ */
+typedef struct dd_stream dd_stream;
+
+dd_status dd_stream_create(const dd_plan *plan, int32_t time_major, dd_stream **out);
+void dd_stream_destroy(dd_stream *stream);
+dd_status dd_stream_info(const dd_stream *stream, int64_t *first, int64_t *step);
+dd_status dd_stream_reset(dd_stream *stream);
+dd_status dd_stream_push(dd_stream *stream, const void *d_block, int64_t samples, void *d_chunk,
+                         const float *d_weights, void *d_out, int64_t out_capacity, void *d_ws,
+                         size_t ws_bytes, int64_t *chunk_index, void *hip_stream);
+
+/*
+ * Corner turn: out[c][t] = in[t][c] for t < nsamp, c < nchans (uint8 for
+ * DD_U8, float32 for DD_F32), through LDS tiles.  d_out rows are out_pitch
+ * elements apart.  Errors: DD_ERR_NULL, DD_ERR_INVALID, DD_ERR_HIP.
+ */
+dd_status dd_corner_turn(dd_dtype dtype, const void *d_in, int64_t nsamp, int32_t nchans,
+                         void *d_out, int64_t out_pitch, void *stream);
+
 /* Text of a status code (static storage). */
 const char *dd_status_str(dd_status status);
 

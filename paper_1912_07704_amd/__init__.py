@@ -208,6 +208,73 @@ def dedisperse_batch(x, batch: Batch, out=None, ws=None, stream=None):
     return out
 
 
+class Stream:
+    """Chunked processing of a long series with the plan's largest delay as
+    overlap (dd_stream_*).  push() returns the chunk's flat output; the first
+    `step // ds_r` samples of each DM row of range r are its share of the
+    one-shot output (emitted() slices them)."""
+
+    def __init__(self, plan: Plan, time_major: bool = False):
+        import torch
+        self.plan = plan
+        self.time_major = bool(time_major)
+        self._h = ctypes.c_void_p()
+        check(lib().dd_stream_create(plan.handle, int(self.time_major), ctypes.byref(self._h)),
+              "dd_stream_create")
+        first, step = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().dd_stream_info(self._h, ctypes.byref(first), ctypes.byref(step)),
+              "dd_stream_info")
+        self.first, self.step = first.value, step.value
+        dt = torch.uint8 if plan.dtype == "u8" else torch.float32
+        self.chunk = torch.empty((plan.nchans, plan.nsamp), dtype=dt, device="cuda")
+        self.ws = workspace(plan)
+        self.out = _out_tensor(plan, None, "cuda")
+
+    def push(self, block, weights=None, stream=None):
+        """Feed the next block ([nchans, n] channel-major or [n, nchans]
+        time-major device tensor, n = first for the first push, then step).
+        Returns (chunk index, flat output of the chunk)."""
+        samples = block.shape[0] if self.time_major else block.shape[1]
+        idx = ctypes.c_int64()
+        check(lib().dd_stream_push(self._h, _ptr(block.contiguous()), int(samples), _ptr(self.chunk),
+                                   _ptr(weights), _ptr(self.out), self.out.numel(), _ptr(self.ws),
+                                   self.ws.numel(), ctypes.byref(idx), _stream_ptr(stream)),
+              "dd_stream_push")
+        return idx.value, self.out
+
+    def emitted(self, out):
+        """Per-range [ndms_r, step // ds_r] slices a chunk contributes."""
+        return [o[:, : self.step // r.downsample] for o, r in zip(self.plan.split(out),
+                                                                  self.plan.ranges)]
+
+    def reset(self):
+        check(lib().dd_stream_reset(self._h), "dd_stream_reset")
+
+    def close(self):
+        if self._h:
+            lib().dd_stream_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def corner_turn(x, stream=None):
+    """[nsamp, nchans] time-major device tensor -> [nchans, nsamp] (dd_corner_turn)."""
+    import torch
+    if x.dim() != 2 or x.dtype not in (torch.uint8, torch.float32) or not x.is_cuda:
+        raise ValueError("x must be a 2-D uint8 or float32 device tensor")
+    x = x.contiguous()
+    n, c = x.shape
+    out = torch.empty((c, n), dtype=x.dtype, device=x.device)
+    check(lib().dd_corner_turn(DD_U8 if x.dtype == torch.uint8 else DD_F32, _ptr(x), n, c,
+                               _ptr(out), n, _stream_ptr(stream)), "dd_corner_turn")
+    return out
+
+
 def _stream_ptr(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream

@@ -34,6 +34,12 @@ SIGNATURES = {
     "dd_batch_beam": (ctypes.c_int, [P, I32, P, P]),
     "dd_batch_prepare": (ctypes.c_int, [P]),
     "dd_batch_forward": (ctypes.c_int, [P, P, P, I64, P, SZ, P]),
+    "dd_stream_create": (ctypes.c_int, [P, I32, P]),
+    "dd_stream_destroy": (None, [P]),
+    "dd_stream_info": (ctypes.c_int, [P, P, P]),
+    "dd_stream_reset": (ctypes.c_int, [P]),
+    "dd_stream_push": (ctypes.c_int, [P, P, I64, P, P, P, I64, P, SZ, P, P]),
+    "dd_corner_turn": (ctypes.c_int, [ctypes.c_int, P, I64, I32, P, I64, P]),
     "dd_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "dd_last_error": (ctypes.c_char_p, []),
 }

@@ -85,4 +85,39 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
     return DD_OK;
 }
 
+dd_status build_stream(const Plan *plan, int32_t time_major, Stream *s, std::string *err)
+{
+    if (!plan) {
+        *err = "plan must not be NULL";
+        return DD_ERR_NULL;
+    }
+    if (time_major != 0 && time_major != 1) {
+        *err = "time_major must be 0 or 1";
+        return DD_ERR_INVALID;
+    }
+    int64_t lcm = 1;
+    int64_t limit = plan->nsamp;
+    for (const RangeInfo &ri : plan->ranges) {
+        int64_t a = lcm, b = ri.ds;
+        while (b) {
+            const int64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        lcm = lcm / a * ri.ds;
+        limit = std::min(limit, int64_t(ri.ds) * ri.nout);
+    }
+    const int64_t step = limit / lcm * lcm;
+    if (step <= 0 || 2 * step < plan->nsamp) {
+        *err = "chunk too short for streaming: need a step >= nsamp/2 that every downsample divides";
+        return DD_ERR_INVALID;
+    }
+    s->plan = plan;
+    s->time_major = time_major;
+    s->step = step;
+    s->overlap = plan->nsamp - step;
+    s->chunks = 0;
+    return DD_OK;
+}
+
 }  // namespace dd

@@ -259,6 +259,58 @@ dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
     return DD_OK;
 }
 
+dd_status dd_stream_create(const dd_plan *plan, int32_t time_major, dd_stream **out)
+{
+    clear_error();
+    if (!out || !plan) {
+        set_error("plan and out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *out = nullptr;
+    dd_stream *st = new (std::nothrow) dd_stream;
+    if (!st) {
+        set_error("host allocation failed");
+        return DD_ERR_NOMEM;
+    }
+    std::string err;
+    const dd_status rc = dd::build_stream(&plan->p, time_major, &st->s, &err);
+    st->s.handle = plan;
+    if (rc != DD_OK) {
+        delete st;
+        set_error(err);
+        return rc;
+    }
+    *out = st;
+    return DD_OK;
+}
+
+void dd_stream_destroy(dd_stream *stream) { delete stream; }
+
+dd_status dd_stream_info(const dd_stream *stream, int64_t *first, int64_t *step)
+{
+    clear_error();
+    if (!stream) {
+        set_error("stream must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (first)
+        *first = stream->s.plan->nsamp;
+    if (step)
+        *step = stream->s.step;
+    return DD_OK;
+}
+
+dd_status dd_stream_reset(dd_stream *stream)
+{
+    clear_error();
+    if (!stream) {
+        set_error("stream must not be NULL");
+        return DD_ERR_NULL;
+    }
+    stream->s.chunks = 0;
+    return DD_OK;
+}
+
 const char *dd_status_str(dd_status status)
 {
     switch (status) {

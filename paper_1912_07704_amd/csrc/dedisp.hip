@@ -1168,6 +1168,91 @@ dd_status boxcar_backward_f32(const Plan &p, const DeviceTables &t, const float 
     return DD_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Streaming helpers: corner turn of a time-major block into channel-major
+// rows (32 x 32 tiles through LDS, coalesced on both sides), a pitched row
+// copy, and the move of a chunk's last `overlap` samples to its front.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_corner_turn(const T *__restrict__ in, int64_t nsamp,
+                                                     int nchans, T *__restrict__ out,
+                                                     int64_t out_pitch, int64_t out_off)
+{
+    __shared__ T tile[32][33];
+    const int64_t t0 = int64_t(blockIdx.x) * 32;
+    const int c0 = int(blockIdx.y) * 32;
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int64_t t = t0 + j;
+        const int c = c0 + int(threadIdx.x);
+        if (t < nsamp && c < nchans)
+            tile[j][threadIdx.x] = in[t * nchans + c];
+    }
+    __syncthreads();
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int c = c0 + j;
+        const int64_t t = t0 + threadIdx.x;
+        if (t < nsamp && c < nchans)
+            out[int64_t(c) * out_pitch + out_off + t] = tile[threadIdx.x][j];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_rows(const T *__restrict__ in, int64_t n,
+                                                   int nchans, T *__restrict__ out,
+                                                   int64_t out_pitch, int64_t out_off)
+{
+    for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y)
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+             i += int64_t(gridDim.x) * blockDim.x)
+            out[c * out_pitch + out_off + i] = in[c * n + i];
+}
+
+// buf[c][i] = buf[c][i + step] for i < overlap (step >= overlap: no overlap
+// between what is read and what is written).
+template <typename T>
+__global__ __launch_bounds__(256) void k_shift_rows(T *buf, int64_t pitch, int64_t step,
+                                                    int64_t overlap, int nchans)
+{
+    for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y)
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < overlap;
+             i += int64_t(gridDim.x) * blockDim.x)
+            buf[c * pitch + i] = buf[c * pitch + i + step];
+}
+
+template <typename T>
+dd_status corner_turn_t(const T *in, int64_t nsamp, int nchans, T *out, int64_t pitch,
+                        int64_t off, hipStream_t stream)
+{
+    const dim3 grid(unsigned((nsamp + 31) / 32), unsigned((nchans + 31) / 32));
+    hipLaunchKernelGGL(k_corner_turn<T>, grid, dim3(32, 8), 0, stream, in, nsamp, nchans, out,
+                       pitch, off);
+    return launch_check("k_corner_turn");
+}
+
+template <typename T>
+dd_status stream_fill(const dd::Stream &S, const T *block, int64_t samples, T *chunk,
+                      hipStream_t stream)
+{
+    const Plan &p = *S.plan;
+    const int64_t off = S.chunks == 0 ? 0 : S.overlap;
+    const dim3 rows(unsigned(std::min<int64_t>((p.nsamp + 255) / 256, 1024)),
+                    unsigned(std::min<int32_t>(p.nchans, 65535)));
+    if (S.chunks > 0) {
+        hipLaunchKernelGGL(k_shift_rows<T>, rows, dim3(256), 0, stream, chunk, p.nsamp, S.step,
+                           S.overlap, p.nchans);
+        dd_status st = launch_check("k_shift_rows");
+        if (st != DD_OK)
+            return st;
+    }
+    if (S.time_major)
+        return corner_turn_t(block, samples, p.nchans, chunk, p.nsamp, off, stream);
+    hipLaunchKernelGGL(k_copy_rows<T>, rows, dim3(256), 0, stream, block, samples, p.nchans, chunk,
+                       p.nsamp, off);
+    return launch_check("k_copy_rows");
+}
+
 dd_status forward_bin(const Plan &p, const void *d_in, const float *d_w, char *d_ws,
                       hipStream_t stream)
 {
@@ -1566,6 +1651,72 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
     return boxcar_backward_f32(plan->p, *t, d_in, nbeams, d_weights, max_width, d_grad_in,
                                d_grad_w, static_cast<char *>(d_ws),
                                static_cast<hipStream_t>(stream));
+}
+
+
+dd_status dd_corner_turn(dd_dtype dtype, const void *d_in, int64_t nsamp, int32_t nchans,
+                         void *d_out, int64_t out_pitch, void *stream)
+{
+    dd::clear_error();
+    if (!d_in || !d_out) {
+        dd::set_error("d_in and d_out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (nsamp <= 0 || nchans <= 0 || out_pitch < nsamp || (dtype != DD_U8 && dtype != DD_F32) ||
+        (nchans + 31) / 32 > 65535) {
+        dd::set_error("need nsamp > 0, 0 < nchans <= 2096640, out_pitch >= nsamp, a known dtype");
+        return DD_ERR_INVALID;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == DD_U8)
+        return corner_turn_t(static_cast<const uint8_t *>(d_in), nsamp, nchans,
+                             static_cast<uint8_t *>(d_out), out_pitch, 0, s);
+    return corner_turn_t(static_cast<const float *>(d_in), nsamp, nchans,
+                         static_cast<float *>(d_out), out_pitch, 0, s);
+}
+
+dd_status dd_stream_push(dd_stream *stream, const void *d_block, int64_t samples, void *d_chunk,
+                         const float *d_weights, void *d_out, int64_t out_capacity, void *d_ws,
+                         size_t ws_bytes, int64_t *chunk_index, void *hip_stream)
+{
+    dd::clear_error();
+    if (!stream || !d_block || !d_chunk || !d_out) {
+        dd::set_error("stream, d_block, d_chunk and d_out must not be NULL");
+        return DD_ERR_NULL;
+    }
+    dd::Stream &S = stream->s;
+    const Plan &p = *S.plan;
+    const int64_t want = S.chunks == 0 ? p.nsamp : S.step;
+    if (samples != want) {
+        dd::set_error("this push needs " + std::to_string(want) + " samples, got " +
+                      std::to_string(samples));
+        return DD_ERR_INVALID;
+    }
+    if ((p.nchans + 31) / 32 > 65535) {
+        dd::set_error("too many channels for the corner turn");
+        return DD_ERR_INVALID;
+    }
+    // The forward's own checks run before anything is enqueued.
+    dd_status st = check_forward_args(S.handle, d_chunk, d_weights, d_out, out_capacity, d_ws,
+                                      ws_bytes, true);
+    if (st != DD_OK)
+        return st;
+    const hipStream_t hs = static_cast<hipStream_t>(hip_stream);
+    if (p.dtype == DD_U8)
+        st = stream_fill(S, static_cast<const uint8_t *>(d_block), samples,
+                         static_cast<uint8_t *>(d_chunk), hs);
+    else
+        st = stream_fill(S, static_cast<const float *>(d_block), samples,
+                         static_cast<float *>(d_chunk), hs);
+    if (st != DD_OK)
+        return st;
+    st = dd_forward(S.handle, d_chunk, d_weights, d_out, out_capacity, d_ws, ws_bytes, hip_stream);
+    if (st != DD_OK)
+        return st;
+    if (chunk_index)
+        *chunk_index = S.chunks;
+    ++S.chunks;
+    return DD_OK;
 }
 
 }  // extern "C"

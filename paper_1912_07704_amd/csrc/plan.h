@@ -197,6 +197,21 @@ struct Batch {
 
 constexpr size_t kBatchCounterBytes = 256;     // queue counters at the start of the workspace
 
+// Streaming over a long series in chunks of the plan's nsamp samples.
+// Consecutive chunks start `step` samples apart; step is the largest
+// multiple of every range's downsample with step <= ds_r * nout_r for all r,
+// so the first step/ds_r outputs of each chunk row tile the one-shot output.
+struct Stream {
+    const dd_plan *handle = nullptr;  // borrowed
+    const Plan *plan = nullptr;       // the same plan
+    int32_t time_major = 0;       // input blocks are [samples][nchans] (SIGPROC order)
+    int64_t step = 0;
+    int64_t overlap = 0;          // nsamp - step
+    int64_t chunks = 0;           // chunks produced so far
+};
+
+dd_status build_stream(const Plan *plan, int32_t time_major, Stream *s, std::string *err);
+
 dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::string *err);
 
 }  // namespace dd
@@ -207,4 +222,8 @@ struct dd_plan {
 
 struct dd_batch {
     dd::Batch b;
+};
+
+struct dd_stream {
+    dd::Stream s;
 };

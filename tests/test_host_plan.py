@@ -183,3 +183,19 @@ def test_strategy_is_queryable():
     assert s["time_tile"] > 0 and s["dm_tile"] > 0 and s["chans_stage"] >= 1
     r = p.ranges[0]
     assert s["workgroups"] == -(-r.nout // s["time_tile"]) * -(-r.ndms // s["dm_tile"])
+
+
+def test_stream_step_of_the_ska_plan():
+    """The chunk step of the SKA-like plan is nsamp minus its largest delay
+    in native samples (22560), a multiple of every downsample."""
+    p = plan_of(synth.ska_single_beam())
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.dd_stream_create(p.handle, 0, ctypes.byref(h)) == 0
+    first, step = ctypes.c_int64(), ctypes.c_int64()
+    assert L.dd_stream_info(h, ctypes.byref(first), ctypes.byref(step)) == 0
+    assert first.value == 262144 and step.value == 262144 - 22560
+    L.dd_stream_destroy(h)
+    assert L.dd_stream_create(p.handle, 2, ctypes.byref(h)) == -2
+    short = dd.Plan(synth.band_freqs(1670.0, 1370.0, 64), 64e-6, 3000, [(0.0, 150.0, 1.0, 1)])
+    assert L.dd_stream_create(short.handle, 0, ctypes.byref(h)) == -2   # step < nsamp/2
