@@ -187,6 +187,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default strategy")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also run one device-to-device copy of this many GiB (a counter "
+                         "calibration reference for profiles)")
     ap.add_argument("--legs", default="fwdbwd,batched,boxcar",
                     help="extra legs after the main one: fwdbwd,batched,boxcar (or none)")
     args = ap.parse_args()
@@ -317,6 +320,14 @@ def main() -> int:
     if "boxcar" in legs:
         torch.cuda.empty_cache()
         res["boxcar"] = leg_boxcar(dd, synth, torch)
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30))
+        src = torch.empty(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_reference_bytes"] = n
+        del src, dst
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, x, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -114,9 +114,9 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  * Strategy options for dd_plan_create_ex (paper, "Plan and strategy": the
  * strategy is configured once, then immutable).  Zero means "library
  * default" for every field.
- *   variant      DD_U8 shift-and-sum kernel: 1 = re-read a channel's words
- *                for every DM, 2 = re-read only when the DM's delay differs
- *                from the previous DM's.
+ *   variant      DD_U8 shift-and-sum kernel: 1 (default) = read a
+ *                channel's words for every DM, 2 = re-read them only when
+ *                the DM's delay differs from the previous DM's.
  *   stage_chans  channels staged in LDS at once (rounded down to even,
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
  *                partial sums allow).

@@ -338,7 +338,7 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         }
         p->out_elems = out_off;
 
-        p->dedup = want_variant != 1;
+        p->dedup = want_variant == 2;
         p->dm_tile = want_dm_tile ? want_dm_tile : kDmTile;
         p->waves = p->dm_tile / kDmPerWave;
         const int32_t dmt = p->dm_tile;
