@@ -32,6 +32,35 @@ constexpr int kTileT = dd::kTimeTile;
 constexpr int kTileD = dd::kDmTile;
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round-robin
 
+// Plan tables are read-only for the whole launch and read at wave-uniform
+// addresses.  The compiler would use vector loads for them after the
+// direct-to-LDS loads (which it treats as possible writes), and every such
+// load's wait would also drain the in-flight staging loads; so eight table
+// entries are fetched with one scalar load instead.
+typedef int sgpr8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ sgpr8 table8(const int32_t *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    const uint64_t addr = (uint64_t(hi) << 32) | lo;
+    sgpr8 v;
+    asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(addr));
+    return v;
+}
+
+__device__ __forceinline__ int32_t table1(const int32_t *p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    const uint64_t addr = (uint64_t(hi) << 32) | lo;
+    int32_t v;
+    asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(addr));
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Device-side plan state: the channel-major shift table, one copy per device.
 // ---------------------------------------------------------------------------
@@ -218,7 +247,7 @@ __device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int 
         const int part = i - j * ipr;
         const int q = part * kWave + lane;
         const int64_t c = cs + j;
-        const int32_t w0 = R.baseT[int64_t(tile) * nchans + c];
+        const int32_t w0 = table1(R.baseT + int64_t(tile) * nchans + c);
         if (q < chunks) {
             const uint16_t *g = R.src + c * R.pitch + t0 + 2 * int64_t(w0) + 8 * q;
             __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
@@ -297,16 +326,14 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         for (int jp = 0; jp < cn; jp += 2) {
             // Offsets of this wave's DMs in the two staged channels; the
             // table is padded so the 8 entries are aligned and in bounds.
+            static_assert(kDW == 8, "offsets are loaded as one scalar octet per row");
             const int32_t *oa = R.offT + int64_t(c0 + jp) * dpad + dw0;
-            const int4 a0 = *reinterpret_cast<const int4 *>(oa);
-            const int4 a1 = *reinterpret_cast<const int4 *>(oa + 4);
-            const int offa[kDW] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const sgpr8 av = table8(oa);
+            const int offa[kDW] = {av[0], av[1], av[2], av[3], av[4], av[5], av[6], av[7]};
             const uint32_t *rowa = A + jp * Wr + lane;
             if (jp + 1 < cn) {
-                const int32_t *ob = oa + dpad;
-                const int4 b0 = *reinterpret_cast<const int4 *>(ob);
-                const int4 b1 = *reinterpret_cast<const int4 *>(ob + 4);
-                const int offb[kDW] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                const sgpr8 bv = table8(oa + dpad);
+                const int offb[kDW] = {bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]};
                 const uint32_t *rowb = rowa + Wr;
                 if constexpr (DEDUP) {
                     uint32_t va[kNW], vb[kNW];
