@@ -406,7 +406,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
 template <bool DEDUP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
 {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
 
     // Workgroups with consecutive logical index run on one XCD, so the DM
     // tiles of a time tile share that XCD's L2.
@@ -545,7 +545,7 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
 {
-    extern __shared__ float ldsf[];
+    extern __shared__ __attribute__((aligned(16))) float ldsf[];
     const int64_t bid = blockIdx.x;
     const int64_t L = (bid % kXcds) * a.per_xcd + bid / kXcds;
     if (L >= a.nblocks)
@@ -833,7 +833,10 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
                   int ndesc, int64_t nitems, int64_t per_queue, const char *ws, int32_t *out,
                   int32_t *counters)
 {
-    extern __shared__ uint32_t lds[];
+    // 16-byte rows: the staging loads and the odd-copy build move 16 bytes
+    // per lane, so the dynamic region must not start at the static s_item's
+    // 8-byte end.
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ int64_t s_item;
     const int x = blockIdx.x % kXcds;
     const int64_t q_begin = int64_t(x) * per_queue;

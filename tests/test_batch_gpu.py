@@ -56,6 +56,10 @@ def test_batch_graph_replay():
     xin = batch.pack([b[0] for b in beams])
     ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
     eager = dd.dedisperse_batch(xin, batch, ws=ws).clone()
+    torch.cuda.synchronize()
+    want = [cref.dedisperse_u8(x, f, t, r) for (x, f, t, r) in beams]
+    assert [int((o.cpu().numpy() != w).sum()) for o, w in zip(batch.split(eager), want)] == \
+        [0] * len(beams), "eager batch differs from the oracle"
     out = torch.zeros(batch.out_elems, dtype=torch.int32, device="cuda")
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -72,7 +76,10 @@ def test_batch_graph_replay():
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        assert torch.equal(out, eager), f"replay {i}"
+        if not torch.equal(out, eager):
+            bad = [(int((o != e).sum()), int(((o != e) & (o == 0)).sum()))
+                   for o, e in zip(batch.split(out), batch.split(eager))]
+            raise AssertionError(f"replay {i}: (mismatches, of them zeros) per beam {bad}")
         other = dd.dedisperse(torch.from_numpy(beams[0][0]).cuda(), plans[0])   # eager work between
         torch.cuda.synchronize()
         assert torch.equal(other, batch.split(eager)[0])
