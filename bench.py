@@ -187,6 +187,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default strategy")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every candidate strategy instead of using the cached or "
+                         "shipped strategy table")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="also run one device-to-device copy of this many GiB (a counter "
                          "calibration reference for profiles)")
@@ -217,10 +220,19 @@ def main() -> int:
     if not args.no_tune:
         from paper_1912_07704_amd import tune as tuner
         t = time.perf_counter()
-        opts, timings = tuner.tune(w.freqs, w.tsamp, w.nsamp, w.ranges, x=xt, use_cache=False)
-        tune_info = {"best": opts, "seconds": round(time.perf_counter() - t, 2),
+        sig = tuner.signature(w.freqs, w.tsamp, w.nsamp, w.ranges)
+        hit = None if args.retune else tuner.lookup(sig)
+        if hit:
+            opts, timings, source = hit
+        else:
+            opts, timings = tuner.tune(w.freqs, w.tsamp, w.nsamp, w.ranges, x=xt,
+                                       use_cache=False)
+            source = "measured"
+        tune_info = {"best": opts, "source": source, "signature": sig,
+                     "device": torch.cuda.get_device_name(dev),
+                     "seconds": round(time.perf_counter() - t, 2),
                      "candidates_sum_ms": [[o, round(m, 3)] for o, m in timings]}
-        log("tuned strategy", opts)
+        log("strategy", opts, "from", source)
     t = time.perf_counter()
     plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **opts)
     t_plan = time.perf_counter() - t

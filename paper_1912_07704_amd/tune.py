@@ -6,7 +6,10 @@ strategy -- kernel variant x DM tile x channels per LDS stage -- on the
 current device, checks that every candidate's output is bit-identical to
 the first one's, and keeps the fastest.  Results are cached per (plan
 signature, device) in a JSON file (``DD_TUNE_CACHE``, default
-``~/.cache/paper_1912_07704_amd/tune.json``).
+``~/.cache/paper_1912_07704_amd/tune.json``).  A table of strategies
+measured on MI355X for the standard workloads ships with the package
+(``strategies.json``) and is consulted after the user cache, so a fresh
+machine does not re-time known plans.
 """
 from __future__ import annotations
 
@@ -45,12 +48,25 @@ def signature(freqs, tsamp, nsamp, ranges, dtype="u8") -> str:
     return hashlib.sha1(key.encode()).hexdigest()
 
 
-def _load() -> dict:
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "strategies.json")
+
+
+def _load(path=None) -> dict:
     try:
-        with open(_cache_path()) as fh:
+        with open(path or _cache_path()) as fh:
             return json.load(fh)
     except (OSError, ValueError):
         return {}
+
+
+def lookup(sig: str):
+    """(best options, timings, source) from the user cache or the shipped
+    table, or None."""
+    for source, path in (("cache", None), ("shipped", SHIPPED)):
+        entry = _load(path).get(sig)
+        if entry:
+            return entry["best"], [tuple(t) for t in entry["timings"]], source
+    return None
 
 
 def _store(cache: dict) -> None:
@@ -71,9 +87,10 @@ def tune(freqs, tsamp, nsamp, ranges, x=None, reps: int = 3, cands=None, use_cac
     uint8 [nchans, nsamp] input; a seeded uniform one is drawn if None."""
     import torch
     sig = signature(freqs, tsamp, nsamp, ranges)
-    cache = _load() if use_cache else {}
-    if use_cache and sig in cache:
-        return cache[sig]["best"], [tuple(t) for t in cache[sig]["timings"]]
+    if use_cache:
+        hit = lookup(sig)
+        if hit:
+            return hit[0], hit[1]
     if x is None:
         g = torch.Generator(device="cuda")
         g.manual_seed(0)
