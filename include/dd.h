@@ -116,11 +116,20 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  * default" for every field.
  *   variant      DD_U8 shift-and-sum kernel: 1 (default) = read a
  *                channel's words for every DM, 2 = re-read them only when
- *                the DM's delay differs from the previous DM's.
+ *                the DM's delay differs from the previous DM's, 3 = exact
+ *                sub-band reuse: DMs of a DM tile whose delays over a
+ *                sub-band of 8 channels differ from their smallest by the
+ *                same pattern share that sub-band's partial sum (the same
+ *                integer result; DD_ERR_INVALID when the patterns of a
+ *                plan do not fit the LDS).  Not for batches.
  *   stage_chans  channels staged in LDS at once (rounded down to even,
+ *                or to a multiple of the sub-band for variant 3, and
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
  *                partial sums allow).
- *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8).
+ *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8)
+ *                for variants 1 and 2; for variant 3, 128 (the default: 16
+ *                wavefronts, 256-sample time tiles) or 96 or 64 (8
+ *                wavefronts, 512-sample time tiles).
  */
 typedef struct {
     int32_t variant;

@@ -38,6 +38,10 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                 *err = "batches hold DD_U8 plans only";
                 return DD_ERR_DTYPE;
             }
+            if (p->subband) {
+                *err = "batches hold variant 1 or 2 plans (variant 3 runs per plan)";
+                return DD_ERR_INVALID;
+            }
             b->in_off[i] = int64_t(in);
             in = align_up(in + size_t(p->nchans) * size_t(p->nsamp), 256);
             b->out_off[i] = int64_t(out);

@@ -154,11 +154,11 @@ dd_status dd_plan_strategy(const dd_plan *plan, int32_t *time_tile, int32_t *dm_
         st = c > st ? c : st;
     }
     if (time_tile)
-        *time_tile = f32 ? dd::kF32TimeTile : dd::kTimeTile;
+        *time_tile = f32 ? dd::kF32TimeTile : plan->p.time_tile;
     if (dm_tile)
         *dm_tile = f32 ? dd::kF32OutTile : plan->p.dm_tile;
     if (variant)
-        *variant = plan->p.dedup ? 2 : 1;
+        *variant = plan->p.subband ? 3 : plan->p.dedup ? 2 : 1;
     if (chans_stage)
         *chans_stage = st;
     if (workgroups)

@@ -66,8 +66,11 @@ __device__ __forceinline__ int32_t table1(const int32_t *p)
 // ---------------------------------------------------------------------------
 
 struct DeviceTables {
-    int32_t *offT = nullptr;
+    int32_t *offT = nullptr;     // start of the one allocation holding every table
     int32_t *baseT = nullptr;
+    int32_t *qcnt = nullptr;     // integer variant 3 only
+    int32_t *qoff = nullptr;
+    int32_t *offC = nullptr;
 };
 
 struct DeviceState {
@@ -108,25 +111,39 @@ dd_status device_tables(const Plan &p, DeviceTables **out)
         return DD_ERR_NOMEM;
     }
     DeviceTables t;
-    // integer plans use offT/baseT, float plans offF/baseF
-    const std::vector<int32_t> &hoff = p.dtype == DD_U8 ? p.offT : p.offF;
-    const std::vector<int32_t> &hbase = p.dtype == DD_U8 ? p.baseT : p.baseF;
-    const size_t ob = hoff.size() * sizeof(int32_t);
-    const size_t bb = hbase.size() * sizeof(int32_t);
-    e = hipMalloc(&t.offT, ob + bb + 16);
+    // integer plans use offT/baseT (variant 3: baseT, qcntT, qoffT, offCT),
+    // float plans offF/baseF; one allocation, each table 256-byte aligned
+    const std::vector<int32_t> empty;
+    const bool u8 = p.dtype == DD_U8;
+    const std::vector<int32_t> *parts[5] = {u8 ? &p.offT : &p.offF, u8 ? &p.baseT : &p.baseF,
+                                            p.subband ? &p.qcntT : &empty,
+                                            p.subband ? &p.qoffT : &empty,
+                                            p.subband ? &p.offCT : &empty};
+    size_t at[5], total = 0;
+    for (int i = 0; i < 5; ++i) {
+        at[i] = total;
+        total += (parts[i]->size() * sizeof(int32_t) + 255) / 256 * 256;
+    }
+    char *mem = nullptr;
+    e = hipMalloc(&mem, total + 256);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         dd::set_error(std::string("hipMalloc of the delay tables: ") + hipGetErrorString(e));
         return DD_ERR_NOMEM;
     }
-    t.baseT = t.offT + hoff.size();
-    e = hipMemcpy(t.offT, hoff.data(), ob, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(t.baseT, hbase.data(), bb, hipMemcpyHostToDevice);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i)
+        if (!parts[i]->empty())
+            e = hipMemcpy(mem + at[i], parts[i]->data(), parts[i]->size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(t.offT);
+        (void)hipFree(mem);
         return hip_fail(e, "hipMemcpy of the delay tables");
     }
+    t.offT = reinterpret_cast<int32_t *>(mem + at[0]);
+    t.baseT = reinterpret_cast<int32_t *>(mem + at[1]);
+    t.qcnt = reinterpret_cast<int32_t *>(mem + at[2]);
+    t.qoff = reinterpret_cast<int32_t *>(mem + at[3]);
+    t.offC = reinterpret_cast<int32_t *>(mem + at[4]);
     *out = &(st->per_device[dev] = t);
     return DD_OK;
 }
@@ -235,8 +252,8 @@ __device__ __forceinline__ void wait_loads()
 // Start the direct-to-LDS loads of the windows of channels [cs, cs + cn)
 // into the A copy at `buf` (row j at buf + j*Wr).  One wave instruction
 // moves 64 lanes x 16 bytes of one row.
-template <int WAVES>
-__device__ __forceinline__ void stage_issue(const RangeArgs &R, int nchans, int tile, int64_t t0,
+template <int WAVES, class RA>
+__device__ __forceinline__ void stage_issue(const RA &R, int nchans, int tile, int64_t t0,
                                             int cs, int cn, uint32_t *buf, int wave, int lane)
 {
     const int Wr = R.row_words;
@@ -419,6 +436,333 @@ __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4
         if (L >= a.r[i].block_start)
             r = i;
     dedisp_tile_u8<DEDUP, WAVES>(a.r[r], L - a.r[r].block_start, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Integer variant 3: exact sub-band reuse.
+//
+// Inside one DM tile, DMs whose delays over a sub-band of kSubband channels
+// exceed their own smallest delay over that sub-band by the same pattern
+// need the same partial sum of the sub-band, only read at different
+// delays:
+//   out[d][t] = sum_b Q_{b,j(d)}[t + a[d][b] - amin_j],
+//   Q_{b,j}[u] = sum_{c in b} x[c][u + amin_j + v_j[c]].
+// Per stage (stage_chans channels, one or two sub-bands) a workgroup stages
+// the channel windows as the direct kernel does (even and odd copies), then
+// builds the even copy of every pattern row Q of its sub-bands, then their
+// odd copies, and finally adds one row word per DM, sub-band and sample
+// pair -- the same integer sums in another grouping, so exact.
+// ---------------------------------------------------------------------------
+
+struct SbRange {
+    const uint16_t *src;      // 16-bit rows of this range's level
+    const int32_t *baseT;     // [ndm_tiles][nchans] first word of each staged window
+    const int32_t *qcnt;      // [ndm_tiles][nsub] patterns per sub-band
+    const int32_t *qoff;      // [ndm_tiles][nsub][jmax][kSubband] pattern row starts
+    const int32_t *offC;      // [ndm_tiles][nsub][dm_tile] per-DM row and delay
+    int32_t *out;             // [ndms][nout] output rows of this range
+    int64_t pitch;
+    int64_t nout;
+    int64_t block_start;
+    int32_t nchans;
+    int32_t ndms;
+    int32_t ndm_tiles;
+    int32_t stage_chans;
+    int32_t row_words;
+    int32_t widen_every;
+    int32_t sb_chans;
+    int32_t nsub;
+    int32_t jmax;
+    int32_t qwords;
+    int32_t nslot;            // sub-bands per stage
+    int32_t tb_words;         // ints per stage-table buffer
+};
+
+struct SbArgs {
+    SbRange r[DD_MAX_RANGES];
+    int64_t nblocks;
+    int64_t per_xcd;
+    int32_t nranges;
+};
+
+__device__ __forceinline__ void dma4(const void *g, void *l)
+{
+    __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+}
+
+__device__ __forceinline__ void dma16(const void *g, void *l)
+{
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+}
+
+// Per-stage tables, staged in LDS one stage ahead by direct loads (ints):
+//   [0, 4)             patterns of the stage's sub-bands
+//   [4, tb_offc)       first staged word of the next stage's channel windows
+//   [tb_offc, tb_qoff) per-DM row and delay, nslot x dm_tile
+//   [tb_qoff, ...)     pattern row starts, nslot x jmax x kSubband
+__device__ __forceinline__ int tb_offc(const SbRange &R) { return 4 + ((R.stage_chans + 3) & ~3); }
+
+template <int WAVES, int DT>
+__device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st, int32_t *T,
+                                             int wave, int lane)
+{
+    const int C = R.stage_chans, K = R.sb_chans, nch = R.nchans;
+    const int c0 = st * C;
+    const int cn = min(C, nch - c0);
+    const int sb0 = c0 / K;
+    const int nsb = (cn + K - 1) / K;
+    const int64_t gsb = int64_t(tile) * R.nsub + sb0;
+    const int offc = tb_offc(R);
+    if (wave == WAVES - 1) {
+        if (lane < nsb)
+            dma4(R.qcnt + gsb + lane, T);
+        const int c1 = c0 + C;
+        const int cn1 = min(C, nch - c1);
+        if (lane < cn1)
+            dma4(R.baseT + int64_t(tile) * nch + c1 + lane, T + 4);
+    } else if (wave == WAVES - 2) {
+        static_assert(2 * DT / 4 <= kWave, "one load instruction per stage for the DM offsets");
+        if (lane < nsb * DT / 4)
+            dma16(R.offC + gsb * DT + 4 * lane, T + offc);
+    } else if (wave == WAVES - 3) {
+        const int n4 = nsb * R.jmax * dd::kSubband / 4;
+        const int32_t *g = R.qoff + gsb * R.jmax * dd::kSubband;
+        int32_t *l = T + offc + R.nslot * DT;
+        for (int b = 0; b < n4; b += kWave)
+            if (b + lane < n4)
+                dma16(g + 4 * (b + lane), l + 4 * b);
+    }
+}
+
+// Direct loads of the channel windows this wavefront owns (rows j with
+// j % WAVES == wave) of one stage; the window starts come from `base`
+// (global or LDS stage tables).
+template <int WAVES, bool SCALAR_BASE>
+__device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base, int64_t t0,
+                                           int cs, int cn, uint32_t *buf, int wave, int lane)
+{
+    const int Wr = R.row_words;
+    const int chunks = Wr >> 2;
+    for (int j = wave; j < cn; j += WAVES) {
+        const int32_t w0 = SCALAR_BASE ? table1(base + j) : __builtin_amdgcn_readfirstlane(base[j]);
+        const uint16_t *g = R.src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
+        for (int part = 0; part * kWave < chunks; ++part) {
+            const int q = part * kWave + lane;
+            if (q < chunks)
+                dma16(g + 8 * q, buf + j * Wr + part * (4 * kWave));
+        }
+    }
+}
+
+__device__ __forceinline__ int lds_uniform(const int32_t *p)
+{
+    return __builtin_amdgcn_readfirstlane(*p);
+}
+
+template <int WAVES, int DPW, int NW>
+__device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uint32_t *lds)
+{
+    constexpr int DT = WAVES * DPW;
+    const int64_t tt = lb / R.ndm_tiles;
+    const int tile = int(lb - tt * R.ndm_tiles);
+    const int64_t t0 = tt * (2 * kWave * NW);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int ndms = R.ndms;
+    const int dw0 = tile * DT + wave * DPW;
+    const int nchans = R.nchans;
+    const int C = R.stage_chans;
+    const int Wr = R.row_words;
+    const int CW = C * Wr;
+    const int K = R.sb_chans;
+    const int Wq = R.qwords;
+    const int jmax = R.jmax;
+    const int nst = (nchans + C - 1) / C;
+    uint32_t *Q = lds + 4 * CW;
+    int32_t *Tb = reinterpret_cast<int32_t *>(Q + R.nslot * jmax * 2 * Wq + 4);
+    const int offc = tb_offc(R);
+    const int qoffs = offc + R.nslot * DT;
+
+    uint32_t acc16[DPW][NW];
+    int32_t acc32[DPW][NW][2];
+#pragma unroll
+    for (int dd = 0; dd < DPW; ++dd)
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            acc16[dd][k] = 0u;
+            acc32[dd][k][0] = 0;
+            acc32[dd][k][1] = 0;
+        }
+
+    rows_issue<WAVES, true>(R, R.baseT + int64_t(tile) * nchans, t0, 0, min(C, nchans), lds,
+                            wave, lane);
+    tables_issue<WAVES, DT>(R, tile, 0, Tb, wave, lane);
+    for (int st = 0; st < nst; ++st) {
+        const int c0 = st * C;
+        const int cn = min(C, nchans - c0);
+        const int nsb = (cn + K - 1) / K;
+        uint32_t *A = lds + (st & 1) * (2 * CW);
+        uint32_t *B = A + CW;
+        const int32_t *T = Tb + (st & 1) * R.tb_words;
+
+        // This wavefront's windows have landed: form their odd-aligned copies.
+        wait_loads();
+        for (int j = wave; j < cn; j += WAVES)
+            for (int m = 4 * lane; m < Wr; m += 4 * kWave) {
+                const uint32_t *src = A + j * Wr + m;
+                const uint4 v = *reinterpret_cast<const uint4 *>(src);
+                const uint32_t nx = src[4];
+                uint4 o;
+                o.x = __builtin_amdgcn_alignbyte(v.y, v.x, 2);
+                o.y = __builtin_amdgcn_alignbyte(v.z, v.y, 2);
+                o.z = __builtin_amdgcn_alignbyte(v.w, v.z, 2);
+                o.w = __builtin_amdgcn_alignbyte(nx, v.w, 2);
+                *reinterpret_cast<uint4 *>(B + j * Wr + m) = o;
+            }
+        lds_barrier();
+        // Every window, both copies and this stage's tables are in LDS; the
+        // previous stage's sums are done.  Start the next stage's loads.
+        if (st + 1 < nst) {
+            const int cs = c0 + C;
+            rows_issue<WAVES, false>(R, T + 4, t0, cs, min(C, nchans - cs),
+                                     lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+            tables_issue<WAVES, DT>(R, tile, st + 1, Tb + ((st + 1) & 1) * R.tb_words, wave,
+                                    lane);
+        }
+
+        // Pattern rows, one per wavefront at a time: even copy (word w = sum
+        // of the sub-band's channels at the pattern's delays), then the odd
+        // copy from the even one (same wavefront: LDS keeps its order).
+        const int J0 = lds_uniform(T);
+        const int J1 = nsb > 1 ? lds_uniform(T + 1) : 0;
+        for (int row = wave; row < J0 + J1; row += WAVES) {
+            const int s = row >= J0 ? 1 : 0;
+            const int j = row - s * J0;
+            const int kb = min(K, nchans - (c0 + s * K));
+            const int32_t *qo = T + qoffs + (s * jmax + j) * dd::kSubband;
+            int ov[dd::kSubband];
+#pragma unroll
+            for (int k = 0; k < dd::kSubband; ++k)
+                ov[k] = k < kb ? lds_uniform(qo + k) : 0;
+            uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
+            if (kb == dd::kSubband) {
+                // two words per lane per pass (read in pairs 64 words apart)
+                for (int w0 = 0; w0 < Wq; w0 += 2 * kWave) {
+                    const int w = w0 + lane;
+                    uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+                    for (int k = 0; k < dd::kSubband; ++k) {
+                        s0 += A[ov[k] + w];
+                        s1 += A[ov[k] + w + kWave];
+                    }
+                    if (w < Wq)
+                        qe[w] = s0;
+                    if (w + kWave < Wq)
+                        qe[w + kWave] = s1;
+                }
+            } else {
+                for (int w = lane; w < Wq; w += kWave) {
+                    uint32_t sum = A[ov[0] + w];
+#pragma unroll
+                    for (int k = 1; k < dd::kSubband; ++k)
+                        if (k < kb)
+                            sum += A[ov[k] + w];
+                    qe[w] = sum;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int w0 = 0; w0 + 1 < Wq; w0 += 2 * kWave) {
+                const int w = w0 + lane;
+                const uint32_t a0 = qe[w], a1 = qe[w + 1];
+                const uint32_t b0 = qe[w + kWave], b1 = qe[w + kWave + 1];
+                if (w + 1 < Wq)
+                    qe[Wq + w] = __builtin_amdgcn_alignbyte(a1, a0, 2);
+                if (w + kWave + 1 < Wq)
+                    qe[Wq + w + kWave] = __builtin_amdgcn_alignbyte(b1, b0, 2);
+            }
+        }
+        lds_barrier();
+
+        // One pattern-row word per DM, sub-band and sample pair.
+        const uint32_t *rowq = Q + lane;
+        const int32_t *oc = T + offc + wave * DPW;
+        int offa[DPW];
+#pragma unroll
+        for (int dd = 0; dd < DPW; ++dd)
+            offa[dd] = lds_uniform(oc + dd);
+        if (nsb > 1) {
+            int offb[DPW];
+#pragma unroll
+            for (int dd = 0; dd < DPW; ++dd)
+                offb[dd] = lds_uniform(oc + DT + dd);
+            // groups of 4 DMs bound the loads in flight (and the VGPRs they hold)
+#pragma unroll
+            for (int dd = 0; dd < DPW; ++dd) {
+                const uint32_t *pa = rowq + offa[dd];
+                const uint32_t *pb = rowq + offb[dd];
+#pragma unroll
+                for (int k = 0; k < NW; ++k)
+                    acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                if (dd % 4 == 3 && dd + 1 < DPW)
+                    __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int dd = 0; dd < DPW; ++dd) {
+                const uint32_t *pa = rowq + offa[dd];
+#pragma unroll
+                for (int k = 0; k < NW; ++k)
+                    acc16[dd][k] += pa[kWave * k];
+                if (dd % 4 == 3 && dd + 1 < DPW)
+                    __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if ((st + 1) % R.widen_every == 0 || st + 1 == nst) {
+#pragma unroll
+            for (int dd = 0; dd < DPW; ++dd)
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    acc32[dd][k][0] += int32_t(acc16[dd][k] & 0xffffu);
+                    acc32[dd][k][1] += int32_t(acc16[dd][k] >> 16);
+                    acc16[dd][k] = 0u;
+                }
+        }
+    }
+
+#pragma unroll
+    for (int dd = 0; dd < DPW; ++dd) {
+        const int d = dw0 + dd;
+        if (d >= ndms)
+            break;
+        int32_t *row = R.out + int64_t(d) * R.nout;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int64_t t = t0 + 2 * (lane + kWave * k);
+            if (t < R.nout)
+                row[t] = acc32[dd][k][0];
+            if (t + 1 < R.nout)
+                row[t + 1] = acc32[dd][k][1];
+        }
+    }
+}
+
+// One workgroup per CU: WAVES/4 wavefronts per SIMD, whose VGPRs hold the
+// packed and the widened sums of DPW DMs x NW words without spilling.
+template <int WAVES, int DPW, int NW>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
+k_dedisp_u8_sb(const SbArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const int64_t b = blockIdx.x;
+    const int64_t L = (b % kXcds) * a.per_xcd + b / kXcds;
+    if (L >= a.nblocks)
+        return;
+    int r = 0;
+    for (int i = 1; i < a.nranges; ++i)
+        if (L >= a.r[i].block_start)
+            r = i;
+    dedisp_tile_sb<WAVES, DPW, NW>(a.r[r], L - a.r[r].block_start, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,9 +1257,61 @@ dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t str
     return DD_OK;
 }
 
+dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const char *d_ws,
+                    hipStream_t stream)
+{
+    SbArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nblocks = p.blocks;
+    a.per_xcd = (p.blocks + kXcds - 1) / kXcds;
+    a.nranges = int32_t(p.ranges.size());
+    for (size_t i = 0; i < p.ranges.size(); ++i) {
+        const RangeInfo &ri = p.ranges[i];
+        const dd::BinLevel &lv = p.levels[ri.level];
+        SbRange &R = a.r[i];
+        R.src = reinterpret_cast<const uint16_t *>(d_ws + lv.ws_offset);
+        R.pitch = lv.pitch;
+        R.baseT = t.baseT + ri.base_offset;
+        R.qcnt = t.qcnt + ri.sb_n_offset;
+        R.qoff = t.qoff + ri.sb_q_offset;
+        R.offC = t.offC + ri.sb_c_offset;
+        R.out = d_out + ri.out_offset;
+        R.nout = ri.nout;
+        R.block_start = ri.block_start;
+        R.nchans = p.nchans;
+        R.ndms = ri.ndms;
+        R.ndm_tiles = ri.ndm_tiles;
+        R.stage_chans = ri.stage_chans;
+        R.row_words = ri.row_words;
+        R.widen_every = ri.widen_every;
+        R.sb_chans = ri.sb_chans;
+        R.nsub = ri.sb_nsub;
+        R.jmax = ri.sb_jmax;
+        R.qwords = ri.sb_qwords;
+        R.nslot = ri.sb_nslot;
+        R.tb_words = ri.sb_tb_words;
+    }
+    const int64_t grid = a.per_xcd * kXcds;
+    // dm_tile 128: 16 wavefronts of 8 DMs x 2 words; 96 and 64: 8 wavefronts
+    // of 12 or 8 DMs x 4 words (the plan's time tile matches)
+    const void *fn = p.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 8, 2>)
+                     : p.dm_tile == 96 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 12, 4>)
+                                       : reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 8, 4>);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(dd::kMaxLdsBytes));
+    void *args[] = {&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(p.waves * kWave)),
+                                   args, p.lds_bytes, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "k_dedisp_u8_sb");
+    return launch_check("k_dedisp_u8_sb");
+}
+
 dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const char *d_ws,
                  hipStream_t stream)
 {
+    if (p.subband)
+        return sum_u8_sb(p, t, d_out, d_ws, stream);
     FwdArgs a;
     std::memset(&a, 0, sizeof(a));
     a.nblocks = p.blocks;

@@ -202,6 +202,251 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     return DD_OK;
 }
 
+// 16-bit copies of the input for the integer kernels: one per distinct
+// downsample (1 included), each binned from the largest earlier level
+// (ds > 1) that divides it, or from the raw input.  Each level's tail covers
+// what the staging loads of its ranges may read past the last row.
+void build_levels(Plan *p)
+{
+    std::vector<int32_t> dss;
+    for (const RangeInfo &ri : p->ranges)
+        dss.push_back(ri.ds);
+    std::sort(dss.begin(), dss.end());
+    dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
+    p->levels.clear();
+    size_t ws = 0;
+    for (int32_t ds : dss) {
+        BinLevel lv;
+        lv.ds = ds;
+        lv.src = -1;
+        lv.factor = ds;
+        for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
+            if (p->levels[j].ds > 1 && ds % p->levels[j].ds == 0) {
+                lv.src = j;
+                lv.factor = ds / p->levels[j].ds;
+                break;
+            }
+        lv.nbin = p->nsamp / ds;
+        lv.pitch = (lv.nbin + 8 + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
+        int32_t reach = 0;     // samples the staging may read past a row start + nbin
+        for (const RangeInfo &ri : p->ranges)
+            if (ri.ds == ds)
+                reach = std::max(reach, 2 * ri.row_words + 16);
+        lv.ws_offset = ws;
+        lv.bytes = (size_t(p->nchans) * size_t(lv.pitch) + size_t(reach)) * sizeof(uint16_t);
+        ws = align_up(ws + lv.bytes, kWsAlign);
+        p->levels.push_back(lv);
+    }
+    for (RangeInfo &ri : p->ranges) {
+        ri.level = -1;
+        for (size_t j = 0; j < p->levels.size(); ++j)
+            if (p->levels[j].ds == ri.ds)
+                ri.level = int32_t(j);
+    }
+    p->ws_bytes = ws;
+}
+
+// Delay patterns of one sub-band (channels [c0, c0 + kb)) over the DMs
+// [d0, d0 + nd) of a range.  a[i] is DM i's smallest delay over the
+// sub-band; two DMs share a pattern when their delays minus a[i] agree on
+// every channel of the sub-band, and then share one partial sum.
+struct SbPatterns {
+    int32_t J = 0;
+    std::vector<int32_t> a, idx;          // per DM
+    std::vector<int32_t> amin, amax, rep; // per pattern (rep: one of its DMs)
+};
+
+void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int32_t c0,
+                 int32_t kb, SbPatterns &t, std::vector<int32_t> &order)
+{
+    const int32_t nch = p.nchans;
+    const int32_t *s = &p.shifts[size_t(ri.dm_index + d0) * nch + c0];
+    t.a.resize(size_t(nd));
+    t.idx.resize(size_t(nd));
+    order.resize(size_t(nd));
+    for (int32_t i = 0; i < nd; ++i) {
+        const int32_t *si = s + size_t(i) * nch;
+        int32_t m = si[0];
+        for (int32_t k = 1; k < kb; ++k)
+            m = std::min(m, si[k]);
+        t.a[i] = m;
+        order[i] = i;
+    }
+    auto cmp = [&](int32_t x, int32_t y) {
+        const int32_t *sx = s + size_t(x) * nch, *sy = s + size_t(y) * nch;
+        for (int32_t k = 0; k < kb; ++k) {
+            const int32_t u = sx[k] - t.a[x], v = sy[k] - t.a[y];
+            if (u != v)
+                return u < v ? -1 : 1;
+        }
+        return 0;
+    };
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int c = cmp(x, y);
+        return c != 0 ? c < 0 : x < y;
+    });
+    t.J = 0;
+    t.amin.clear();
+    t.amax.clear();
+    t.rep.clear();
+    for (int32_t n = 0; n < nd; ++n) {
+        const int32_t i = order[n];
+        if (n == 0 || cmp(order[n - 1], i) != 0) {
+            t.amin.push_back(t.a[i]);
+            t.amax.push_back(t.a[i]);
+            t.rep.push_back(i);
+            ++t.J;
+        }
+        const int32_t j = t.J - 1;
+        t.idx[i] = j;
+        t.amin[j] = std::min(t.amin[j], t.a[i]);
+        t.amax[j] = std::max(t.amax[j], t.a[i]);
+    }
+}
+
+// Integer variant 3: exact sub-band reuse.  Per range: the channel windows
+// of a DM tile (as in the direct kernel), the most patterns of one
+// sub-band in one DM tile, the rows' sizes, the stage width that fits the
+// LDS, then the tables documented in plan.h.
+dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
+{
+    const int32_t nchans = p->nchans;
+    const int32_t dmt = p->dm_tile;
+    // dm_tile 128: 16 wavefronts of 8 DMs, 2 words (4 samples) per lane;
+    // 64 and 96: 8 wavefronts of 8 or 12 DMs, 4 words per lane.
+    const int32_t T = dmt == 128 ? kTimeTile / 2 : kTimeTile;
+    p->time_tile = T;
+    p->waves = dmt == 128 ? 2 * kWaves : kWaves;
+    int64_t blocks = 0;
+    size_t lds = 0;
+    SbPatterns pt;
+    std::vector<int32_t> order;
+    for (size_t r = 0; r < p->ranges.size(); ++r) {
+        RangeInfo &ri = p->ranges[r];
+        const int32_t cap = int32_t(65535 / (255 * ri.ds));
+        const int32_t K = std::max(1, std::min(kSubband, cap));
+        const int32_t nsub = (nchans + K - 1) / K;
+        int32_t span = 0, jmax = 0, spanJ = 0;
+        for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
+            const int32_t nd = std::min(dmt, ri.ndms - d0);
+            const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
+            const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d0 + nd - 1) * nchans];
+            for (int32_t c = 0; c < nchans; ++c)
+                span = std::max(span, s1[c] - s0[c]);
+            for (int32_t b = 0; b < nsub; ++b) {
+                sb_patterns(*p, ri, d0, nd, b * K, std::min(K, nchans - b * K), pt, order);
+                jmax = std::max(jmax, pt.J);
+                for (int32_t j = 0; j < pt.J; ++j)
+                    spanJ = std::max(spanJ, pt.amax[j] - pt.amin[j]);
+            }
+        }
+        const int32_t Wq = ((spanJ >> 1) + T / 2 + 1 + 3) / 4 * 4;
+        const int32_t Wr = (((span + 7) >> 1) + Wq + 1 + 3) / 4 * 4;
+        // LDS: two stages of channel windows (even and odd copies), the
+        // pattern rows of one stage (even and odd), and two buffers of
+        // stage tables; one workgroup per CU.
+        auto slots_for = [&](int32_t st) { return (std::min(st, nchans) + K - 1) / K; };
+        auto tb_words = [&](int32_t st) {
+            const int32_t n = 4 + (st + 3) / 4 * 4 + slots_for(st) * (dmt + jmax * kSubband);
+            return (n + 3) / 4 * 4;
+        };
+        auto bytes_for = [&](int32_t st) {
+            return size_t(4) * (size_t(4) * st * Wr + size_t(slots_for(st)) * jmax * 2 * Wq + 4 +
+                                size_t(2) * tb_words(st));
+        };
+        int32_t stage = std::min(cap >= 2 * K ? 2 * K : K, std::max(K, nchans));
+        if (want_stage > 0)
+            stage = std::max(K, std::min(stage, want_stage / K * K));
+        const size_t target = kMaxLdsBytes - 1024;
+        if (stage > K && bytes_for(stage) > target)
+            stage = K;
+        if (bytes_for(stage) > target) {
+            *err = fmt("variant 3, range ", r, ": ", jmax, " delay patterns per sub-band and a ",
+                       span, "-sample delay spread per DM tile need ", bytes_for(stage),
+                       " bytes of LDS");
+            return DD_ERR_INVALID;
+        }
+        ri.sb_chans = K;
+        ri.sb_nsub = nsub;
+        ri.sb_jmax = jmax;
+        ri.sb_span = spanJ;
+        ri.sb_qwords = Wq;
+        ri.sb_nslot = slots_for(stage);
+        ri.sb_tb_words = tb_words(stage);
+        ri.span = span;
+        ri.row_words = Wr;
+        ri.stage_chans = stage;
+        ri.widen_every = std::max(1, cap / stage);
+        lds = std::max(lds, bytes_for(stage));
+        ri.ntime_tiles = (ri.nout + T - 1) / T;
+        ri.ndm_tiles = (ri.ndms + dmt - 1) / dmt;
+        ri.ndms_pad = ri.ndm_tiles * dmt;
+        ri.block_start = blocks;
+        blocks += ri.ntime_tiles * ri.ndm_tiles;
+    }
+    p->blocks = blocks;
+    p->lds_bytes = lds;
+    build_levels(p);
+
+    size_t nbase = 0, nq = 0, nn = 0, nc = 0;
+    for (RangeInfo &ri : p->ranges) {
+        ri.base_offset = nbase;
+        ri.sb_n_offset = nn;
+        ri.sb_q_offset = nq;
+        ri.sb_c_offset = nc;
+        nbase += size_t(nchans) * ri.ndm_tiles;
+        nn += size_t(ri.ndm_tiles) * ri.sb_nsub;
+        nq += size_t(ri.ndm_tiles) * ri.sb_nsub * ri.sb_jmax * kSubband;
+        nc += size_t(ri.ndm_tiles) * ri.sb_nsub * dmt;
+    }
+    p->offT.clear();
+    p->baseT.assign(nbase, 0);
+    p->qcntT.assign(nn, 0);
+    p->qoffT.assign(nq, 0);
+    p->offCT.assign(nc, 0);
+    for (RangeInfo &ri : p->ranges) {
+        const int32_t K = ri.sb_chans, S = ri.stage_chans, Wr = ri.row_words, Wq = ri.sb_qwords;
+        const int32_t jmax = ri.sb_jmax;
+        for (int32_t g = 0; g < ri.ndm_tiles; ++g) {
+            const int32_t d0 = g * dmt;
+            const int32_t nd = std::min(dmt, ri.ndms - d0);
+            int32_t *base = &p->baseT[ri.base_offset + size_t(g) * nchans];
+            for (int32_t c = 0; c < nchans; ++c) {
+                const int32_t b = p->shifts[size_t(ri.dm_index + d0) * nchans + c];
+                base[c] = (b >> 1) - ((b >> 1) & 3);
+            }
+            for (int32_t sb = 0; sb < ri.sb_nsub; ++sb) {
+                const int32_t c0 = sb * K, kb = std::min(K, nchans - c0);
+                const int32_t cs = c0 / S * S;            // first channel of the stage
+                const int32_t slot = (c0 - cs) / K;
+                sb_patterns(*p, ri, d0, nd, c0, kb, pt, order);
+                const size_t gb = size_t(g) * ri.sb_nsub + sb;
+                p->qcntT[ri.sb_n_offset + gb] = pt.J;
+                int32_t *q = &p->qoffT[ri.sb_q_offset + gb * jmax * kSubband];
+                for (int32_t j = 0; j < pt.J; ++j) {
+                    const int32_t *srep =
+                        &p->shifts[size_t(ri.dm_index + d0 + pt.rep[j]) * nchans + c0];
+                    for (int32_t k = 0; k < kb; ++k) {
+                        // first sample of pattern j's row in channel c0 + k,
+                        // relative to the channel's staged window
+                        const int32_t local = pt.amin[j] + (srep[k] - pt.a[pt.rep[j]]) -
+                                              2 * base[c0 + k];
+                        q[j * kSubband + k] = (local & 1) * S * Wr + (c0 + k - cs) * Wr +
+                                              (local >> 1);
+                    }
+                }
+                int32_t *oc = &p->offCT[ri.sb_c_offset + gb * dmt];
+                for (int32_t d = 0; d < dmt; ++d) {
+                    const int32_t j = d < nd ? pt.idx[d] : 0;
+                    const int32_t o = d < nd ? pt.a[d] - pt.amin[j] : 0;
+                    oc[d] = ((slot * jmax + j) * 2 + (o & 1)) * Wq + (o >> 1);
+                }
+            }
+        }
+    }
+    return DD_OK;
+}
+
 dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t nsamp,
                      const dd_range *ranges, int32_t nranges, dd_dtype dtype,
                      const dd_options *opts, Plan *p, std::string *err)
@@ -209,9 +454,20 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
     const int32_t want_variant = opts ? opts->variant : 0;
     const int32_t want_stage = opts ? opts->stage_chans : 0;
     const int32_t want_dm_tile = opts ? opts->dm_tile : 0;
-    if (want_variant < 0 || want_variant > 2 || want_stage < 0 ||
-        (want_dm_tile != 0 && want_dm_tile != 32 && want_dm_tile != 64)) {
-        *err = "options: variant must be 0, 1 or 2, stage_chans >= 0, dm_tile 0, 32 or 64";
+    if (want_variant < 0 || want_variant > 3 || want_stage < 0) {
+        *err = "options: variant must be 0 to 3 and stage_chans >= 0";
+        return DD_ERR_INVALID;
+    }
+    const bool tile_ok = want_dm_tile == 0 ||
+                         (want_variant == 3 ? (want_dm_tile == 64 || want_dm_tile == 96 ||
+                                               want_dm_tile == 128)
+                                            : (want_dm_tile == 32 || want_dm_tile == 64));
+    if (!tile_ok) {
+        *err = "options: dm_tile must be 32 or 64 (variants 1, 2) or 64, 96 or 128 (variant 3)";
+        return DD_ERR_INVALID;
+    }
+    if (want_variant == 3 && dtype != DD_U8) {
+        *err = "options: variant 3 is an integer (DD_U8) strategy";
         return DD_ERR_INVALID;
     }
     if (!freqs || !ranges || !p) {
@@ -339,11 +595,15 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         p->out_elems = out_off;
 
         p->dedup = want_variant == 2;
-        p->dm_tile = want_dm_tile ? want_dm_tile : kDmTile;
+        p->subband = want_variant == 3;
+        p->dm_tile = want_dm_tile ? want_dm_tile : (p->subband ? 2 * kDmTile : kDmTile);
         p->waves = p->dm_tile / kDmPerWave;
+        p->time_tile = kTimeTile;
         const int32_t dmt = p->dm_tile;
         if (dtype == DD_F32)
             return build_f32(p, want_stage, err);
+        if (p->subband)
+            return build_subband(p, want_stage, err);
 
         // Tile strategy: a time tile of kTimeTile samples by a DM tile of
         // kDmTile trials per workgroup.  Channels are staged in LDS in groups
@@ -393,46 +653,7 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         p->blocks = blocks;
         p->lds_bytes = lds;
 
-        // 16-bit copies of the input: one per distinct downsample (1 included),
-        // each binned from the largest earlier level (ds > 1) that divides it,
-        // or from the raw input.
-        const size_t elem = dtype == DD_U8 ? sizeof(uint16_t) : sizeof(float);
-        std::vector<int32_t> dss;
-        for (const RangeInfo &ri : p->ranges)
-            dss.push_back(ri.ds);
-        std::sort(dss.begin(), dss.end());
-        dss.erase(std::unique(dss.begin(), dss.end()), dss.end());
-        p->levels.clear();
-        size_t ws = 0;
-        for (int32_t ds : dss) {
-            BinLevel lv;
-            lv.ds = ds;
-            lv.src = -1;
-            lv.factor = ds;
-            for (int32_t j = int32_t(p->levels.size()) - 1; j >= 0; --j)
-                if (p->levels[j].ds > 1 && ds % p->levels[j].ds == 0) {
-                    lv.src = j;
-                    lv.factor = ds / p->levels[j].ds;
-                    break;
-                }
-            lv.nbin = nsamp / ds;
-            lv.pitch = (lv.nbin + 8 + kLevelAlign - 1) / kLevelAlign * kLevelAlign;
-            int32_t reach = 0;     // samples the staging may read past a row start + nbin
-            for (const RangeInfo &ri : p->ranges)
-                if (ri.ds == ds)
-                    reach = std::max(reach, 2 * ri.row_words + 16);
-            lv.ws_offset = ws;
-            lv.bytes = (size_t(nchans) * size_t(lv.pitch) + size_t(reach)) * elem;
-            ws = align_up(ws + lv.bytes, kWsAlign);
-            p->levels.push_back(lv);
-        }
-        for (RangeInfo &ri : p->ranges) {
-            ri.level = -1;
-            for (size_t j = 0; j < p->levels.size(); ++j)
-                if (p->levels[j].ds == ri.ds)
-                    ri.level = int32_t(j);
-        }
-        p->ws_bytes = ws;
+        build_levels(p);
 
         // Device tables of the integer kernel (see plan.h).
         size_t noff = 0, nbase = 0;

@@ -24,6 +24,12 @@ constexpr int kMaxStageChans = 16;               // channels staged at once
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr size_t kLdsTwoBlocks = 80 * 1024;      // LDS that still fits two workgroups per CU
 constexpr int kLevelAlign = 64;                  // samples; row pitch granule of a level
+// Exact sub-band reuse (integer variant 3).  Channels are grouped into
+// sub-bands of up to kSubband consecutive channels.  Inside one DM tile the
+// DMs whose delays over a sub-band differ from the sub-band's smallest delay
+// by the same pattern share one partial sum of that sub-band, built once in
+// LDS and added at each DM's own smallest delay.
+constexpr int kSubband = 8;
 constexpr size_t kWsAlign = 256;
 
 // Float32 path: one generic shift-and-sum over rows staged in LDS,
@@ -98,6 +104,17 @@ struct RangeInfo {
     int32_t ndms_pad = 0;        // ndms rounded up to a multiple of kDmTile
     size_t off_offset = 0;       // element offset of this range in offT
     size_t base_offset = 0;      // element offset of this range in baseT
+    // integer variant 3 (exact sub-band reuse)
+    int32_t sb_chans = 0;        // channels per sub-band (kSubband, fewer at large ds)
+    int32_t sb_nsub = 0;         // sub-bands
+    int32_t sb_jmax = 0;         // most delay patterns of one sub-band in one DM tile
+    int32_t sb_span = 0;         // largest spread of one pattern's smallest delays
+    int32_t sb_qwords = 0;       // words per copy of a partial-sum row (multiple of 4)
+    int32_t sb_nslot = 0;        // sub-bands per stage
+    int32_t sb_tb_words = 0;     // ints per LDS buffer of one stage's tables
+    size_t sb_q_offset = 0;      // element offset of this range in qoffT
+    size_t sb_n_offset = 0;      // element offset of this range in qcntT
+    size_t sb_c_offset = 0;      // element offset of this range in offCT
     // float32 plans
     SumProblem fwd;              // forward of this range
     SumProblem adj;              // adjoint of this range (rows = DMs, outputs = channels)
@@ -127,6 +144,22 @@ struct Plan {
     //                  copy.  DMs past the last (up to ndms_pad) repeat the last.
     std::vector<int32_t> baseT;
     std::vector<int32_t> offT;
+    // Variant 3 tables (offT unused; baseT as above).  For DM tile g,
+    // sub-band b and delay pattern j of that tile and sub-band:
+    //  qcntT[g][b]         number of patterns J;
+    //  qoffT[g][b][j][k]   word offset, from the start of the stage's even
+    //                      copy, of the staged window of the sub-band's k-th
+    //                      channel at which pattern j's row starts (copy
+    //                      select folded in, as in offT);
+    //  offCT[g][b][d]      word offset, from the start of the partial-sum
+    //                      region, of DM d's (d < dm_tile) row and delay:
+    //                      ((s*jmax + j)*2 + (o & 1))*qwords + (o >> 1), with
+    //                      s the sub-band's slot in its stage and o the DM's
+    //                      smallest delay minus the pattern's smallest.
+    std::vector<int32_t> qcntT;
+    std::vector<int32_t> qoffT;
+    std::vector<int32_t> offCT;
+    bool subband = false;                  // integer variant 3
     std::vector<RangeInfo> ranges;
     std::vector<BinLevel> levels;
     int64_t out_elems = 0;
@@ -137,6 +170,7 @@ struct Plan {
     bool dedup = true;                     // integer kernel variant (dd_options.variant)
     int32_t waves = kWaves;                // integer kernel: wavefronts per workgroup (4 or 8)
     int32_t dm_tile = kDmTile;             // integer kernel: DMs per workgroup
+    int32_t time_tile = kTimeTile;         // integer kernel: samples per workgroup
     // float32 plans: tables of the generic shift-and-sum (forward problems
     // then adjoint problems), and the adjoint's reduction buffer.
     std::vector<int32_t> offF;

@@ -23,11 +23,16 @@ from . import Plan, dedisperse, workspace
 VARIANTS = (1, 2)
 DM_TILES = (64, 32)
 STAGES = (16, 8, 4)
+# variant 3 (exact sub-band reuse): its own DM tiles; stages of one or two
+# 8-channel sub-bands
+SUBBAND = [(128, 16), (128, 8), (96, 16), (96, 8), (64, 16)]
 
 
 def candidates():
-    return [{"variant": v, "dm_tile": d, "stage_chans": s}
-            for v in VARIANTS for d in DM_TILES for s in STAGES]
+    c = [{"variant": v, "dm_tile": d, "stage_chans": s}
+         for v in VARIANTS for d in DM_TILES for s in STAGES]
+    c += [{"variant": 3, "dm_tile": d, "stage_chans": s} for d, s in SUBBAND]
+    return c
 
 
 def _cache_path() -> str:

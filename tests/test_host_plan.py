@@ -199,3 +199,49 @@ def test_stream_step_of_the_ska_plan():
     assert L.dd_stream_create(p.handle, 2, ctypes.byref(h)) == -2
     short = dd.Plan(synth.band_freqs(1670.0, 1370.0, 64), 64e-6, 3000, [(0.0, 150.0, 1.0, 1)])
     assert L.dd_stream_create(short.handle, 0, ctypes.byref(h)) == -2   # step < nsamp/2
+
+
+def test_subband_variant_strategy():
+    """Variant 3 (exact sub-band reuse) on the SKA-like plan: 128-DM tiles
+    of 256 samples with 16-channel stages by default, 512-sample tiles at
+    dm_tile 96 and 64; the workgroup count follows the tiles."""
+    w = synth.ska_single_beam()
+    for dm_tile, tt in ((0, 256), (128, 256), (96, 512), (64, 512)):
+        p = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3, dm_tile=dm_tile)
+        s = p.strategy
+        assert s["variant"] == 3 and s["time_tile"] == tt
+        assert s["dm_tile"] == (dm_tile or 128)
+        assert s["chans_stage"] % 8 == 0
+        assert s["workgroups"] == sum(-(-r.nout // tt) * -(-r.ndms // s["dm_tile"])
+                                      for r in p.ranges)
+        assert p.out_elems == 536529400
+        p.close()
+
+
+@pytest.mark.parametrize("opts", [dict(variant=3, dm_tile=32), dict(variant=1, dm_tile=128),
+                                  dict(variant=2, dm_tile=96), dict(variant=4)])
+def test_subband_option_errors(opts):
+    w = synth.tiny()
+    with pytest.raises(dd.DDError) as e:
+        dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", **opts)
+    assert e.value.status == -2
+
+
+def test_subband_variant_is_integer_only_and_not_batched():
+    w = synth.tiny()
+    with pytest.raises(dd.DDError) as e:
+        dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
+    assert e.value.status == -2
+    p3 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3)
+    with pytest.raises(dd.DDError) as e:
+        dd.Batch([p3])
+    assert e.value.status == -2
+
+
+def test_subband_variant_rejects_plans_beyond_the_lds():
+    """A DM tile whose delays spread over thousands of samples needs more
+    LDS than a workgroup has: DD_ERR_INVALID at creation, naming the LDS."""
+    freqs = synth.band_freqs(500.0, 300.0, 64)
+    with pytest.raises(dd.DDError) as e:
+        dd.Plan(freqs, 1e-3, 20000, [(0.0, 400.0, 12.5, 1)], "u8", variant=3)
+    assert e.value.status == -2 and "LDS" in str(e.value)
