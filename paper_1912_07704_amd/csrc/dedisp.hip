@@ -621,21 +621,12 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
                 *reinterpret_cast<uint4 *>(B + j * Wr + m) = o;
             }
         lds_barrier();
-        // Every window, both copies and this stage's tables are in LDS; the
-        // previous stage's sums are done.  Start the next stage's loads.
-        if (st + 1 < nst) {
-            const int cs = c0 + C;
-            rows_issue<WAVES, false>(R, T + 4, t0, cs, min(C, nchans - cs),
-                                     lds + ((st + 1) & 1) * (2 * CW), wave, lane);
-            tables_issue<WAVES, DT>(R, tile, st + 1, Tb + ((st + 1) & 1) * R.tb_words, wave,
-                                    lane);
-        }
 
+        const int J0 = lds_uniform(T);
+        const int J1 = nsb > 1 ? lds_uniform(T + 1) : 0;
         // Pattern rows, one per wavefront at a time: even copy (word w = sum
         // of the sub-band's channels at the pattern's delays), then the odd
         // copy from the even one (same wavefront: LDS keeps its order).
-        const int J0 = lds_uniform(T);
-        const int J1 = nsb > 1 ? lds_uniform(T + 1) : 0;
         for (int row = wave; row < J0 + J1; row += WAVES) {
             const int s = row >= J0 ? 1 : 0;
             const int j = row - s * J0;
@@ -646,7 +637,21 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
             for (int k = 0; k < dd::kSubband; ++k)
                 ov[k] = k < kb ? lds_uniform(qo + k) : 0;
             uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
-            if (kb == dd::kSubband) {
+            if (kb == dd::kSubband && Wq <= 4 * kWave) {
+                // rows of up to 256 words: two passes of two words per lane,
+                // every read issued before the first sum (words past the row
+                // read other LDS data and are not stored)
+                uint32_t sv[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < dd::kSubband; ++k)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        sv[i] += A[ov[k] + lane + kWave * i];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (lane + kWave * i < Wq)
+                        qe[lane + kWave * i] = sv[i];
+            } else if (kb == dd::kSubband) {
                 // two words per lane per pass (read in pairs 64 words apart)
                 for (int w0 = 0; w0 < Wq; w0 += 2 * kWave) {
                     const int w = w0 + lane;
@@ -681,6 +686,16 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
                 if (w + kWave + 1 < Wq)
                     qe[Wq + w + kWave] = __builtin_amdgcn_alignbyte(b1, b0, 2);
             }
+        }
+        // Every window, both copies and this stage's tables are in LDS (the
+        // previous stage's sums finished before this stage's first
+        // barrier): start the next stage's loads.
+        if (st + 1 < nst) {
+            const int cs = c0 + C;
+            rows_issue<WAVES, false>(R, T + 4, t0, cs, min(C, nchans - cs),
+                                     lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+            tables_issue<WAVES, DT>(R, tile, st + 1, Tb + ((st + 1) & 1) * R.tb_words, wave,
+                                    lane);
         }
         lds_barrier();
 
