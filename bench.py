@@ -30,7 +30,8 @@ UNIT = "DM-trial·samples/s"
 # (one v_add3_u32), i.e. 78.6 T adds/s.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dedisp_u8_ska-4096ch_traffic.json")
+# rocprofv3 FETCH_SIZE/WRITE_SIZE summary of the shift-and-sum kernel, per kernel
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_ska-4096ch_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_07704_amd", "csrc", f)
                   for f in ("dedisp.hip", "plan.h", "plan.cpp")]
 
@@ -47,12 +48,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def kernel_name(strategy) -> str:
+    """The shift-and-sum kernel a strategy launches."""
+    return "k_dedisp_u8_sb" if strategy["variant"] == 3 else "k_dedisp_u8"
+
+
+def measured_traffic(kernel):
     """HBM bytes per launch of the shift-and-sum kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the
     current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(kernel=kernel)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -71,7 +77,8 @@ def cpu_baseline(w, x, target_s: float):
     plan = O.expand_plan(w.freqs, w.tsamp, w.nsamp, [rg])
     nout = plan[0].nout
     threads = cref.max_threads()
-    n = 4
+    cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, 1, nout)      # thread pool warm-up
+    n = 2 * threads               # the probe keeps every thread busy (OpenMP over DM trials)
     t = time.perf_counter()
     cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n, nout)
     dt = time.perf_counter() - t
@@ -128,7 +135,10 @@ def leg_batched(dd, synth, torch, plain_value, opts):
     on the GPU, excluded from timing)."""
     wls = synth.batched_beams()
     log("leg batched:", len(wls), "beams")
+    # batches run the direct kernels (variants 1 and 2)
     o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile")}
+    if o.get("variant") == 3:
+        o = {}
     plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **o) for w in wls]
     batch = dd.Batch(plans)
     batch.prepare()
@@ -146,6 +156,7 @@ def leg_batched(dd, synth, torch, plain_value, opts):
     res = {"workload": f"{len(wls)} uint8 beams, 1024-4096 ch, 2^16-2^18 samples, DM max "
                        "500/1000/2000", "ms": ms, "dm_trial_samples": samples,
            "dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
+           "strategy": plans[0].strategy,
            "work_items": batch.work_items, "launches": "bins per beam + 1 persistent"}
     del xin, out, ws
     batch.close()
@@ -229,7 +240,7 @@ def main() -> int:
                                        use_cache=False)
             source = "measured"
         tune_info = {"best": opts, "source": source, "signature": sig,
-                     "device": torch.cuda.get_device_name(dev),
+                     "device": torch.cuda.get_device_name(dev), "arch": tuner.device_arch(),
                      "seconds": round(time.perf_counter() - t, 2),
                      "candidates_sum_ms": [[o, round(m, 3)] for o, m in timings]}
         log("strategy", opts, "from", source)
@@ -285,7 +296,8 @@ def main() -> int:
     value = samples / (ms_step / 1e3)
     adds = sum(r.ndms * r.nout for r in plan.ranges) * w.nchans
     achieved = adds / (ms_sum / 1e3) / 1e12
-    traffic = measured_traffic()
+    kernel = kernel_name(plan.strategy)
+    traffic = measured_traffic(kernel)
     alg_bytes = w.nchans * w.nsamp + samples * 4          # one input read + the output
     realtime = (w.nsamp - plan.overlap) * w.tsamp / (ms_step / 1e3)
 
@@ -310,7 +322,7 @@ def main() -> int:
         "x_realtime_full_chunk": w.nsamp * w.tsamp / (ms_step / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "k_dedisp_u8", "kernel_ms": ms_sum,
+                     "kernel": kernel, "kernel_ms": ms_sum,
                      "adds_per_launch": adds, "algorithmic_bytes_per_launch": alg_bytes,
                      "algorithmic_hbm_gbs": alg_bytes / (ms_sum / 1e3) / 1e9,
                      "hbm_frac_of_peak": (traffic / (ms_sum / 1e3) / 1e9 / HBM_PEAK_GBS

@@ -41,10 +41,18 @@ def _cache_path() -> str:
                                        "tune.json"))
 
 
-def signature(freqs, tsamp, nsamp, ranges, dtype="u8") -> str:
-    import numpy as np
+def device_arch() -> str:
+    """The current device's architecture (e.g. "gfx950"): strategies are
+    kept per architecture, not per marketing name."""
     import torch
-    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    if not torch.cuda.is_available():
+        return "cpu"
+    return torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+
+
+def signature(freqs, tsamp, nsamp, ranges, dtype="u8", device=None) -> str:
+    import numpy as np
+    dev = device or device_arch()
     f = np.ascontiguousarray(freqs, dtype=np.float64)
     key = json.dumps({"freqs": hashlib.sha1(f.tobytes()).hexdigest(), "nchans": int(f.size),
                       "tsamp": float(tsamp), "nsamp": int(nsamp),
