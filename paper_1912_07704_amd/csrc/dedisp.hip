@@ -559,6 +559,28 @@ __device__ __forceinline__ int lds_uniform(const int32_t *p)
     return __builtin_amdgcn_readfirstlane(*p);
 }
 
+// Even copy of one pattern row of up to NQ*64 words: every read issued
+// before the first sum (words past the row read other LDS data and are not
+// stored).
+template <int NQ>
+__device__ __forceinline__ void qrow_even(const uint32_t *A, const int *ov, uint32_t *qe, int Wq,
+                                          int lane)
+{
+    uint32_t sv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        sv[i] = 0;
+#pragma unroll
+    for (int k = 0; k < dd::kSubband; ++k)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            sv[i] += A[ov[k] + lane + kWave * i];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        if (lane + kWave * i < Wq)
+            qe[lane + kWave * i] = sv[i];
+}
+
 template <int WAVES, int DPW, int NW>
 __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uint32_t *lds)
 {
@@ -637,20 +659,10 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
             for (int k = 0; k < dd::kSubband; ++k)
                 ov[k] = k < kb ? lds_uniform(qo + k) : 0;
             uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
-            if (kb == dd::kSubband && Wq <= 4 * kWave) {
-                // rows of up to 256 words: two passes of two words per lane,
-                // every read issued before the first sum (words past the row
-                // read other LDS data and are not stored)
-                uint32_t sv[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < dd::kSubband; ++k)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        sv[i] += A[ov[k] + lane + kWave * i];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (lane + kWave * i < Wq)
-                        qe[lane + kWave * i] = sv[i];
+            if (kb == dd::kSubband && Wq <= 3 * kWave) {
+                qrow_even<3>(A, ov, qe, Wq, lane);
+            } else if (kb == dd::kSubband && Wq <= 4 * kWave) {
+                qrow_even<4>(A, ov, qe, Wq, lane);
             } else if (kb == dd::kSubband) {
                 // two words per lane per pass (read in pairs 64 words apart)
                 for (int w0 = 0; w0 < Wq; w0 += 2 * kWave) {

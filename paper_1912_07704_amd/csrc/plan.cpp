@@ -257,7 +257,7 @@ struct SbPatterns {
 };
 
 void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int32_t c0,
-                 int32_t kb, SbPatterns &t, std::vector<int32_t> &order)
+                 int32_t kb, int32_t max_spread, SbPatterns &t, std::vector<int32_t> &order)
 {
     const int32_t nch = p.nchans;
     const int32_t *s = &p.shifts[size_t(ri.dm_index + d0) * nch + c0];
@@ -289,9 +289,12 @@ void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int
     t.amin.clear();
     t.amax.clear();
     t.rep.clear();
+    // DMs of one pattern come in increasing DM order, so increasing a; a
+    // pattern whose smallest delays would spread over more than max_spread
+    // samples continues as a new pattern (a longer row costs every row).
     for (int32_t n = 0; n < nd; ++n) {
         const int32_t i = order[n];
-        if (n == 0 || cmp(order[n - 1], i) != 0) {
+        if (n == 0 || cmp(order[n - 1], i) != 0 || t.a[i] - t.amin[t.J - 1] > max_spread) {
             t.amin.push_back(t.a[i]);
             t.amax.push_back(t.a[i]);
             t.rep.push_back(i);
@@ -303,6 +306,8 @@ void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int
         t.amax[j] = std::max(t.amax[j], t.a[i]);
     }
 }
+
+constexpr int32_t kWave64 = 64;    // lanes per wavefront
 
 // Integer variant 3: exact sub-band reuse.  Per range: the channel windows
 // of a DM tile (as in the direct kernel), the most patterns of one
@@ -327,6 +332,9 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         const int32_t K = std::max(1, std::min(kSubband, cap));
         const int32_t nsub = (nchans + K - 1) / K;
         int32_t span = 0, jmax = 0, spanJ = 0;
+        // pattern rows of at most 64*NW + 64 words: 3 words per lane at
+        // 256-sample tiles, 5 at 512
+        const int32_t max_spread = 2 * (kWave64 - 1);
         for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
             const int32_t nd = std::min(dmt, ri.ndms - d0);
             const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
@@ -334,7 +342,8 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
             for (int32_t c = 0; c < nchans; ++c)
                 span = std::max(span, s1[c] - s0[c]);
             for (int32_t b = 0; b < nsub; ++b) {
-                sb_patterns(*p, ri, d0, nd, b * K, std::min(K, nchans - b * K), pt, order);
+                sb_patterns(*p, ri, d0, nd, b * K, std::min(K, nchans - b * K), max_spread, pt,
+                            order);
                 jmax = std::max(jmax, pt.J);
                 for (int32_t j = 0; j < pt.J; ++j)
                     spanJ = std::max(spanJ, pt.amax[j] - pt.amin[j]);
@@ -419,7 +428,7 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
                 const int32_t c0 = sb * K, kb = std::min(K, nchans - c0);
                 const int32_t cs = c0 / S * S;            // first channel of the stage
                 const int32_t slot = (c0 - cs) / K;
-                sb_patterns(*p, ri, d0, nd, c0, kb, pt, order);
+                sb_patterns(*p, ri, d0, nd, c0, kb, 2 * (kWave64 - 1), pt, order);
                 const size_t gb = size_t(g) * ri.sb_nsub + sb;
                 p->qcntT[ri.sb_n_offset + gb] = pt.J;
                 int32_t *q = &p->qoffT[ri.sb_q_offset + gb * jmax * kSubband];
