@@ -309,6 +309,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         }
 
     stage_issue<WAVES>(R, nchans, tile, t0, 0, min(C, nchans), lds, wave, lane);
+    int widen_left = R.widen_every;
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
         const int cn = min(C, nchans - c0);
@@ -390,7 +391,8 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
                 }
             }
         }
-        if ((st + 1) % R.widen_every == 0 || st + 1 == nst) {
+        if (--widen_left == 0 || st + 1 == nst) {
+            widen_left = R.widen_every;
 #pragma unroll
             for (int dd = 0; dd < kDW; ++dd)
 #pragma unroll
@@ -502,16 +504,14 @@ __device__ __forceinline__ void dma16(const void *g, void *l)
 //   [tb_qoff, ...)     pattern row starts, nslot x jmax x kSubband
 __device__ __forceinline__ int tb_offc(const SbRange &R) { return 4 + ((R.stage_chans + 3) & ~3); }
 
+// Direct loads of stage st's tables (its nsb sub-bands start at st*nslot).
 template <int WAVES, int DT>
-__device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st, int32_t *T,
-                                             int wave, int lane)
+__device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st, int nsb,
+                                             int32_t *T, int wave, int lane)
 {
-    const int C = R.stage_chans, K = R.sb_chans, nch = R.nchans;
+    const int C = R.stage_chans, nch = R.nchans;
     const int c0 = st * C;
-    const int cn = min(C, nch - c0);
-    const int sb0 = c0 / K;
-    const int nsb = (cn + K - 1) / K;
-    const int64_t gsb = int64_t(tile) * R.nsub + sb0;
+    const int64_t gsb = int64_t(tile) * R.nsub + st * R.nslot;
     const int offc = tb_offc(R);
     if (wave == WAVES - 1) {
         if (lane < nsb)
@@ -617,13 +617,16 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
             acc32[dd][k][1] = 0;
         }
 
+    // sub-bands per stage: nslot, and in the last stage whatever is left
+    const int nsb_last = (nchans - (nst - 1) * C + K - 1) / K;
     rows_issue<WAVES, true>(R, R.baseT + int64_t(tile) * nchans, t0, 0, min(C, nchans), lds,
                             wave, lane);
-    tables_issue<WAVES, DT>(R, tile, 0, Tb, wave, lane);
+    tables_issue<WAVES, DT>(R, tile, 0, nst > 1 ? R.nslot : nsb_last, Tb, wave, lane);
+    int widen_left = R.widen_every;
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
         const int cn = min(C, nchans - c0);
-        const int nsb = (cn + K - 1) / K;
+        const int nsb = st + 1 < nst ? R.nslot : nsb_last;
         uint32_t *A = lds + (st & 1) * (2 * CW);
         uint32_t *B = A + CW;
         const int32_t *T = Tb + (st & 1) * R.tb_words;
@@ -654,10 +657,13 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
             const int j = row - s * J0;
             const int kb = min(K, nchans - (c0 + s * K));
             const int32_t *qo = T + qoffs + (s * jmax + j) * dd::kSubband;
+            // the row's 8 channel offsets: broadcast word reads kept in VGPRs
+            // (word loads: the compiler does not order them behind the
+            // outstanding direct-to-LDS loads)
             int ov[dd::kSubband];
 #pragma unroll
             for (int k = 0; k < dd::kSubband; ++k)
-                ov[k] = k < kb ? lds_uniform(qo + k) : 0;
+                ov[k] = qo[k];
             uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
             if (kb == dd::kSubband && Wq <= 3 * kWave) {
                 qrow_even<3>(A, ov, qe, Wq, lane);
@@ -706,8 +712,8 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
             const int cs = c0 + C;
             rows_issue<WAVES, false>(R, T + 4, t0, cs, min(C, nchans - cs),
                                      lds + ((st + 1) & 1) * (2 * CW), wave, lane);
-            tables_issue<WAVES, DT>(R, tile, st + 1, Tb + ((st + 1) & 1) * R.tb_words, wave,
-                                    lane);
+            tables_issue<WAVES, DT>(R, tile, st + 1, st + 2 < nst ? R.nslot : nsb_last,
+                                    Tb + ((st + 1) & 1) * R.tb_words, wave, lane);
         }
         lds_barrier();
 
@@ -717,12 +723,12 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
         int offa[DPW];
 #pragma unroll
         for (int dd = 0; dd < DPW; ++dd)
-            offa[dd] = lds_uniform(oc + dd);
+            offa[dd] = oc[dd];
         if (nsb > 1) {
             int offb[DPW];
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd)
-                offb[dd] = lds_uniform(oc + DT + dd);
+                offb[dd] = oc[DT + dd];
             // groups of 4 DMs bound the loads in flight (and the VGPRs they hold)
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd) {
@@ -745,7 +751,8 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
                     __builtin_amdgcn_sched_barrier(0);
             }
         }
-        if ((st + 1) % R.widen_every == 0 || st + 1 == nst) {
+        if (--widen_left == 0 || st + 1 == nst) {
+            widen_left = R.widen_every;
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd)
 #pragma unroll
