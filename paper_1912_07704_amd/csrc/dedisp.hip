@@ -544,7 +544,9 @@ __device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
     for (int j = wave; j < cn; j += WAVES) {
-        const int32_t w0 = SCALAR_BASE ? table1(base + j) : __builtin_amdgcn_readfirstlane(base[j]);
+        // (from LDS the start stays a VGPR: only the LDS destination of a
+        // direct load has to be wave-uniform)
+        const int32_t w0 = SCALAR_BASE ? table1(base + j) : base[j];
         const uint16_t *g = R.src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
         for (int part = 0; part * kWave < chunks; ++part) {
             const int q = part * kWave + lane;
