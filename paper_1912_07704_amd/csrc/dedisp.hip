@@ -29,7 +29,6 @@ constexpr int kBlock = dd::kWaves * kWave;
 constexpr int kNW = dd::kWaveWords;
 constexpr int kDW = dd::kDmPerWave;
 constexpr int kTileT = dd::kTimeTile;
-constexpr int kTileD = dd::kDmTile;
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round-robin
 
 // Plan tables are read-only for the whole launch and read at wave-uniform
@@ -266,8 +265,12 @@ __device__ __forceinline__ void stage_issue(const RA &R, int nchans, int tile, i
         const int64_t c = cs + j;
         const int32_t w0 = table1(R.baseT + int64_t(tile) * nchans + c);
         if (q < chunks) {
+            // even copy, and the odd-aligned copy: the same row one sample later
             const uint16_t *g = R.src + c * R.pitch + t0 + 2 * int64_t(w0) + 8 * q;
+            const int CW = R.stage_chans * Wr;
             __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(g + 1, buf + CW + j * Wr + part * (4 * kWave), 16, 0,
+                                             0);
         }
     }
 }
@@ -280,7 +283,6 @@ template <bool DEDUP, int WAVES>
 __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, uint32_t *lds)
 {
     constexpr int kTileDW = WAVES * kDW;
-    constexpr int kBlockW = WAVES * kWave;
     const int64_t tt = lb / R.ndm_tiles;
     const int tile = int(lb - tt * R.ndm_tiles);
     const int d0 = tile * kTileDW;
@@ -314,32 +316,16 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         const int c0 = st * C;
         const int cn = min(C, nchans - c0);
         uint32_t *A = lds + (st & 1) * (2 * CW);
-        uint32_t *B = A + CW;
 
+        // Both copies of the stage's windows have landed (each wavefront
+        // waits for its own loads, the barrier for everyone's).
         wait_loads();
         lds_barrier();
-        // Odd-aligned copy: B[j][m] = (A[j][m] >> 16) | (A[j][m+1] << 16),
-        // four words per thread and step.
-        const int quads = Wr >> 2;
-        for (int g = tid; g < cn * quads; g += kBlockW) {
-            const int j = g / quads;
-            const int m = (g - j * quads) * 4;
-            const uint32_t *src = A + j * Wr + m;
-            const uint4 v = *reinterpret_cast<const uint4 *>(src);
-            const uint32_t nx = src[4];
-            uint4 o;
-            o.x = __builtin_amdgcn_alignbyte(v.y, v.x, 2);
-            o.y = __builtin_amdgcn_alignbyte(v.z, v.y, 2);
-            o.z = __builtin_amdgcn_alignbyte(v.w, v.z, 2);
-            o.w = __builtin_amdgcn_alignbyte(nx, v.w, 2);
-            *reinterpret_cast<uint4 *>(B + j * Wr + m) = o;
-        }
         if (st + 1 < nst) {
             const int cs = c0 + C;
             stage_issue<WAVES>(R, nchans, tile, t0, cs, min(C, nchans - cs),
                         lds + ((st + 1) & 1) * (2 * CW), wave, lane);
         }
-        lds_barrier();
 
         for (int jp = 0; jp < cn; jp += 2) {
             // Offsets of this wave's DMs in the two staged channels; the
@@ -537,12 +523,15 @@ __device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st,
 // Direct loads of the channel windows this wavefront owns (rows j with
 // j % WAVES == wave) of one stage; the window starts come from `base`
 // (global or LDS stage tables).
+// Both copies come from memory: the odd-aligned copy is the same 16-bit
+// row read one sample (2 bytes) later.
 template <int WAVES, bool SCALAR_BASE>
 __device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base, int64_t t0,
                                            int cs, int cn, uint32_t *buf, int wave, int lane)
 {
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
+    const int CW = R.stage_chans * Wr;
     for (int j = wave; j < cn; j += WAVES) {
         // (from LDS the start stays a VGPR: only the LDS destination of a
         // direct load has to be wave-uniform)
@@ -550,8 +539,10 @@ __device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base
         const uint16_t *g = R.src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
         for (int part = 0; part * kWave < chunks; ++part) {
             const int q = part * kWave + lane;
-            if (q < chunks)
+            if (q < chunks) {
                 dma16(g + 8 * q, buf + j * Wr + part * (4 * kWave));
+                dma16(g + 8 * q + 1, buf + CW + j * Wr + part * (4 * kWave));
+            }
         }
     }
 }
@@ -627,26 +618,12 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
     int widen_left = R.widen_every;
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
-        const int cn = min(C, nchans - c0);
         const int nsb = st + 1 < nst ? R.nslot : nsb_last;
         uint32_t *A = lds + (st & 1) * (2 * CW);
-        uint32_t *B = A + CW;
         const int32_t *T = Tb + (st & 1) * R.tb_words;
 
-        // This wavefront's windows have landed: form their odd-aligned copies.
+        // This wavefront's windows (both copies) have landed.
         wait_loads();
-        for (int j = wave; j < cn; j += WAVES)
-            for (int m = 4 * lane; m < Wr; m += 4 * kWave) {
-                const uint32_t *src = A + j * Wr + m;
-                const uint4 v = *reinterpret_cast<const uint4 *>(src);
-                const uint32_t nx = src[4];
-                uint4 o;
-                o.x = __builtin_amdgcn_alignbyte(v.y, v.x, 2);
-                o.y = __builtin_amdgcn_alignbyte(v.z, v.y, 2);
-                o.z = __builtin_amdgcn_alignbyte(v.w, v.z, 2);
-                o.w = __builtin_amdgcn_alignbyte(nx, v.w, 2);
-                *reinterpret_cast<uint4 *>(B + j * Wr + m) = o;
-            }
         lds_barrier();
 
         const int J0 = lds_uniform(T);

@@ -76,10 +76,11 @@ def test_batch_graph_replay():
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        if not torch.equal(out, eager):
-            bad = [(int((o != e).sum()), int(((o != e) & (o == 0)).sum()))
-                   for o, e in zip(batch.split(out), batch.split(eager))]
-            raise AssertionError(f"replay {i}: (mismatches, of them zeros) per beam {bad}")
+        # compare the beams' outputs (the alignment gaps between beams are
+        # never written)
+        bad = [(int((o != e).sum()), int(((o != e) & (o == 0)).sum()))
+               for o, e in zip(batch.split(out), batch.split(eager))]
+        assert all(b == (0, 0) for b in bad), f"replay {i}: (mismatches, of them zeros) {bad}"
         other = dd.dedisperse(torch.from_numpy(beams[0][0]).cuda(), plans[0])   # eager work between
         torch.cuda.synchronize()
         assert torch.equal(other, batch.split(eager)[0])
