@@ -552,12 +552,21 @@ __device__ __forceinline__ int lds_uniform(const int32_t *p)
     return __builtin_amdgcn_readfirstlane(*p);
 }
 
-// Even copy of one pattern row of up to NQ*64 words: every read issued
-// before the first sum (words past the row read other LDS data and are not
-// stored).
+// Whole-wavefront lane moves (DPP): lane i receives lane i+1's value
+// (lane 63 keeps `old`), and the rotation that brings lane 0's value to
+// lane 63.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveRol1 = 0x134;
+
+// One pattern row of up to NQ*64 words, both copies.  Even word
+// w = lane + 64i is the sum of the 8 channel words at the row's offsets
+// (every read issued before the first sum; words past the row read other
+// LDS data and are not stored).  Odd word w takes the upper half of even w
+// and the lower half of even w+1, which lane+1 holds (lane 63: lane 0 of
+// the next group).
 template <int NQ>
-__device__ __forceinline__ void qrow_even(const uint32_t *A, const int *ov, uint32_t *qe, int Wq,
-                                          int lane)
+__device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, uint32_t *qe, int Wq,
+                                     int lane)
 {
     uint32_t sv[NQ];
 #pragma unroll
@@ -569,9 +578,18 @@ __device__ __forceinline__ void qrow_even(const uint32_t *A, const int *ov, uint
         for (int i = 0; i < NQ; ++i)
             sv[i] += A[ov[k] + lane + kWave * i];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i)
-        if (lane + kWave * i < Wq)
-            qe[lane + kWave * i] = sv[i];
+    for (int i = 0; i < NQ; ++i) {
+        const int w = lane + kWave * i;
+        const int wrap = i + 1 < NQ ? __builtin_amdgcn_update_dpp(0, int(sv[i + 1]), kDppWaveRol1,
+                                                                   0xF, 0xF, false)
+                                    : 0;
+        const uint32_t nb = uint32_t(__builtin_amdgcn_update_dpp(wrap, int(sv[i]), kDppWaveShl1,
+                                                                 0xF, 0xF, false));
+        if (w < Wq)
+            qe[w] = sv[i];
+        if (w + 1 < Wq)
+            qe[Wq + w] = __builtin_amdgcn_alignbyte(nb, sv[i], 2);
+    }
 }
 
 template <int WAVES, int DPW, int NW>
@@ -645,10 +663,14 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
                 ov[k] = qo[k];
             uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
             if (kb == dd::kSubband && Wq <= 3 * kWave) {
-                qrow_even<3>(A, ov, qe, Wq, lane);
-            } else if (kb == dd::kSubband && Wq <= 4 * kWave) {
-                qrow_even<4>(A, ov, qe, Wq, lane);
-            } else if (kb == dd::kSubband) {
+                qrow<3>(A, ov, qe, Wq, lane);
+                continue;
+            }
+            if (kb == dd::kSubband && Wq <= 4 * kWave) {
+                qrow<4>(A, ov, qe, Wq, lane);
+                continue;
+            }
+            if (kb == dd::kSubband) {
                 // two words per lane per pass (read in pairs 64 words apart)
                 for (int w0 = 0; w0 < Wq; w0 += 2 * kWave) {
                     const int w = w0 + lane;
