@@ -127,8 +127,8 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
  *                partial sums allow).
  *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8)
- *                for variants 1 and 2; for variant 3, 128 (the default: 16
- *                wavefronts, 256-sample time tiles) or 96 or 64 (8
+ *                for variants 1 and 2; for variant 3, 192 (the default) or
+ *                128 (16 wavefronts, 256-sample time tiles), or 96 or 64 (8
  *                wavefronts, 512-sample time tiles).
  */
 typedef struct {

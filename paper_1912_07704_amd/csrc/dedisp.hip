@@ -507,9 +507,10 @@ __device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st,
         if (lane < cn1)
             dma4(R.baseT + int64_t(tile) * nch + c1 + lane, T + 4);
     } else if (wave == WAVES - 2) {
-        static_assert(2 * DT / 4 <= kWave, "one load instruction per stage for the DM offsets");
-        if (lane < nsb * DT / 4)
-            dma16(R.offC + gsb * DT + 4 * lane, T + offc);
+        const int n4 = nsb * DT / 4;
+        for (int b = 0; b < n4; b += kWave)
+            if (b + lane < n4)
+                dma16(R.offC + gsb * DT + 4 * (b + lane), T + offc + 4 * b);
     } else if (wave == WAVES - 3) {
         const int n4 = nsb * R.jmax * dd::kSubband / 4;
         const int32_t *g = R.qoff + gsb * R.jmax * dd::kSubband;
@@ -1327,9 +1328,10 @@ dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const 
         R.tb_words = ri.sb_tb_words;
     }
     const int64_t grid = a.per_xcd * kXcds;
-    // dm_tile 128: 16 wavefronts of 8 DMs x 2 words; 96 and 64: 8 wavefronts
-    // of 12 or 8 DMs x 4 words (the plan's time tile matches)
-    const void *fn = p.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 8, 2>)
+    // dm_tile 192 and 128: 16 wavefronts of 12 or 8 DMs x 2 words; 96 and
+    // 64: 8 wavefronts of 12 or 8 DMs x 4 words (the plan's time tile matches)
+    const void *fn = p.dm_tile == 192 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 12, 2>)
+                     : p.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 8, 2>)
                      : p.dm_tile == 96 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 12, 4>)
                                        : reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 8, 4>);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -317,11 +317,12 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
 {
     const int32_t nchans = p->nchans;
     const int32_t dmt = p->dm_tile;
-    // dm_tile 128: 16 wavefronts of 8 DMs, 2 words (4 samples) per lane;
-    // 64 and 96: 8 wavefronts of 8 or 12 DMs, 4 words per lane.
-    const int32_t T = dmt == 128 ? kTimeTile / 2 : kTimeTile;
+    // dm_tile 128 and 192: 16 wavefronts of 8 or 12 DMs, 2 words (4 samples)
+    // per lane; 64 and 96: 8 wavefronts of 8 or 12 DMs, 4 words per lane.
+    const bool wide = dmt >= 128;
+    const int32_t T = wide ? kTimeTile / 2 : kTimeTile;
     p->time_tile = T;
-    p->waves = dmt == 128 ? 2 * kWaves : kWaves;
+    p->waves = wide ? 2 * kWaves : kWaves;
     int64_t blocks = 0;
     size_t lds = 0;
     SbPatterns pt;
@@ -469,10 +470,10 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
     }
     const bool tile_ok = want_dm_tile == 0 ||
                          (want_variant == 3 ? (want_dm_tile == 64 || want_dm_tile == 96 ||
-                                               want_dm_tile == 128)
+                                               want_dm_tile == 128 || want_dm_tile == 192)
                                             : (want_dm_tile == 32 || want_dm_tile == 64));
     if (!tile_ok) {
-        *err = "options: dm_tile must be 32 or 64 (variants 1, 2) or 64, 96 or 128 (variant 3)";
+        *err = "options: dm_tile must be 32 or 64 (variants 1, 2) or 64, 96, 128 or 192 (variant 3)";
         return DD_ERR_INVALID;
     }
     if (want_variant == 3 && dtype != DD_U8) {
@@ -605,7 +606,7 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
 
         p->dedup = want_variant == 2;
         p->subband = want_variant == 3;
-        p->dm_tile = want_dm_tile ? want_dm_tile : (p->subband ? 2 * kDmTile : kDmTile);
+        p->dm_tile = want_dm_tile ? want_dm_tile : (p->subband ? 3 * kDmTile : kDmTile);
         p->waves = p->dm_tile / kDmPerWave;
         p->time_tile = kTimeTile;
         const int32_t dmt = p->dm_tile;

@@ -25,7 +25,7 @@ DM_TILES = (64, 32)
 STAGES = (16, 8, 4)
 # variant 3 (exact sub-band reuse): its own DM tiles; stages of one or two
 # 8-channel sub-bands
-SUBBAND = [(128, 16), (128, 8), (96, 16), (96, 8), (64, 16)]
+SUBBAND = [(192, 16), (192, 8), (128, 16), (128, 8), (96, 16), (64, 16)]
 
 
 def candidates():

@@ -202,15 +202,16 @@ def test_stream_step_of_the_ska_plan():
 
 
 def test_subband_variant_strategy():
-    """Variant 3 (exact sub-band reuse) on the SKA-like plan: 128-DM tiles
-    of 256 samples with 16-channel stages by default, 512-sample tiles at
-    dm_tile 96 and 64; the workgroup count follows the tiles."""
+    """Variant 3 (exact sub-band reuse) on the SKA-like plan: 192-DM tiles
+    of 256 samples with 16-channel stages by default, 256-sample tiles at
+    dm_tile 128, 512-sample tiles at 96 and 64; the workgroup count follows
+    the tiles."""
     w = synth.ska_single_beam()
-    for dm_tile, tt in ((0, 256), (128, 256), (96, 512), (64, 512)):
+    for dm_tile, tt in ((0, 256), (192, 256), (128, 256), (96, 512), (64, 512)):
         p = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3, dm_tile=dm_tile)
         s = p.strategy
         assert s["variant"] == 3 and s["time_tile"] == tt
-        assert s["dm_tile"] == (dm_tile or 128)
+        assert s["dm_tile"] == (dm_tile or 192)
         assert s["chans_stage"] % 8 == 0
         assert s["workgroups"] == sum(-(-r.nout // tt) * -(-r.ndms // s["dm_tile"])
                                       for r in p.ranges)

@@ -41,7 +41,7 @@ def forward(x, plan, extra=64):
     return got[: plan.out_elems]
 
 
-@pytest.mark.parametrize("dm_tile", [96, 64, 128])
+@pytest.mark.parametrize("dm_tile", [128, 192, 96, 64])
 @pytest.mark.parametrize("seed", range(16))
 def test_random_shapes_bit_exact(seed, dm_tile):
     x, freqs, tsamp, ranges = random_case(seed)
@@ -95,7 +95,7 @@ def test_small_workload_matches_direct_kernel():
     want = cref.dedisperse_u8(x, freqs, 64e-6, ranges)
     p1 = dd.Plan(freqs, 64e-6, 20000, ranges, "u8", variant=1)
     assert np.array_equal(forward(x, p1), want)
-    for dm_tile, stage in ((96, 0), (96, 8), (128, 0), (64, 0)):
+    for dm_tile, stage in ((128, 0), (128, 8), (192, 0), (96, 0), (64, 0)):
         plan = plan_v3(freqs, 64e-6, 20000, ranges, dm_tile=dm_tile, stage=stage)
         say("variant 3 small workload", plan.strategy)
         assert np.array_equal(forward(x, plan), want)
