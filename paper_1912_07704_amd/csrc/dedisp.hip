@@ -1269,11 +1269,100 @@ dd_status launch_check(const char *what)
     return DD_OK;
 }
 
+// The levels ds = 1, 2, 4, 8, 16 that a plan has, binned from the raw input
+// in one pass: a thread reads 16 consecutive samples of one channel (one
+// 16-byte load) and writes the 16/ds bins of each present level, from
+// packed 16-bit sums (no half can carry: 16 * 255 < 65536).  Needs
+// nsamp % 16 == 0 and a 16-byte aligned input.
+struct FusedLevels {
+    uint16_t *dst[5];         // ds = 1, 2, 4, 8, 16; nullptr when absent
+    int64_t pitch[5];
+};
+
+__global__ __launch_bounds__(256) void k_bin_fused_u8(const uint8_t *__restrict__ src,
+                                                      int64_t nsamp, FusedLevels L, int nchans)
+{
+    const int64_t ng = nsamp / 16;
+    for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y) {
+        const uint4 *row = reinterpret_cast<const uint4 *>(src + c * nsamp);
+        for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < ng;
+             g += int64_t(gridDim.x) * blockDim.x) {
+            const uint4 v = row[g];
+            const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+            uint32_t l1[8], l2[4], l4[2], l8, l16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // bytes b0..b3 of word i: ds 1 as the pairs (b0, b1) and
+                // (b2, b3); ds 2 as (b0 + b1, b2 + b3)
+                l1[2 * i] = (x[i] & 0xffu) | ((x[i] & 0xff00u) << 8);
+                l1[2 * i + 1] = ((x[i] >> 16) & 0xffu) | ((x[i] >> 8) & 0xff0000u);
+                l2[i] = (x[i] & 0x00ff00ffu) + ((x[i] >> 8) & 0x00ff00ffu);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                // ds 4: one sum per input word, two words per output pair
+                const uint32_t a = (l2[2 * i] & 0xffffu) + (l2[2 * i] >> 16);
+                const uint32_t b = (l2[2 * i + 1] & 0xffffu) + (l2[2 * i + 1] >> 16);
+                l4[i] = a | (b << 16);
+            }
+            {
+                const uint32_t a = (l4[0] & 0xffffu) + (l4[0] >> 16);
+                const uint32_t b = (l4[1] & 0xffffu) + (l4[1] >> 16);
+                l8 = a | (b << 16);
+                l16 = a + b;
+            }
+            if (L.dst[0]) {
+                uint4 *o = reinterpret_cast<uint4 *>(L.dst[0] + c * L.pitch[0] + 16 * g);
+                o[0] = make_uint4(l1[0], l1[1], l1[2], l1[3]);
+                o[1] = make_uint4(l1[4], l1[5], l1[6], l1[7]);
+            }
+            if (L.dst[1])
+                *reinterpret_cast<uint4 *>(L.dst[1] + c * L.pitch[1] + 8 * g) =
+                    make_uint4(l2[0], l2[1], l2[2], l2[3]);
+            if (L.dst[2])
+                *reinterpret_cast<uint2 *>(L.dst[2] + c * L.pitch[2] + 4 * g) = make_uint2(l4[0], l4[1]);
+            if (L.dst[3])
+                *reinterpret_cast<uint32_t *>(L.dst[3] + c * L.pitch[3] + 2 * g) = l8;
+            if (L.dst[4])
+                L.dst[4][c * L.pitch[4] + g] = uint16_t(l16);
+        }
+    }
+}
+
 dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t stream)
 {
-    // 16-bit copies, each from its source level (or the raw input), in
-    // increasing downsample order.
-    for (const dd::BinLevel &lv : p.levels) {
+    // Levels ds = 1, 2, 4, 8, 16 in one pass over the raw input when the
+    // rows allow 16-byte loads; every other level from its source level (or
+    // the raw input), in increasing downsample order.
+    std::vector<bool> done(p.levels.size(), false);
+    if (p.nsamp % 16 == 0 && reinterpret_cast<uintptr_t>(d_in) % 16 == 0) {
+        FusedLevels L;
+        std::memset(&L, 0, sizeof(L));
+        bool any = false;
+        for (size_t i = 0; i < p.levels.size(); ++i) {
+            const dd::BinLevel &lv = p.levels[i];
+            for (int k = 0; k < 5; ++k)
+                if (lv.ds == (1 << k)) {
+                    L.dst[k] = reinterpret_cast<uint16_t *>(d_ws + lv.ws_offset);
+                    L.pitch[k] = lv.pitch;
+                    done[i] = any = true;
+                }
+        }
+        if (any) {
+            const int64_t ng = p.nsamp / 16;
+            const dim3 grid(unsigned(std::min<int64_t>((ng + 255) / 256, 1024)),
+                            unsigned(std::min<int32_t>(p.nchans, 65535)));
+            hipLaunchKernelGGL(k_bin_fused_u8, grid, dim3(256), 0, stream, d_in, p.nsamp, L,
+                               p.nchans);
+            dd_status st = launch_check("k_bin_fused_u8");
+            if (st != DD_OK)
+                return st;
+        }
+    }
+    for (size_t i = 0; i < p.levels.size(); ++i) {
+        const dd::BinLevel &lv = p.levels[i];
+        if (done[i])
+            continue;
         uint16_t *dst = reinterpret_cast<uint16_t *>(d_ws + lv.ws_offset);
         const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 1023) / 1024, 1024)),
                         unsigned(std::min<int32_t>(p.nchans, 65535)));

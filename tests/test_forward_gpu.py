@@ -255,3 +255,34 @@ def test_ska_pulses_recovered(ska):
         say("pulse", p, dm_found, (t + lo) * ds)
         assert abs(dm_found - p.dm) <= tol
         assert abs((t + lo) * ds - p.t0) <= p.width + ds
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fused_binning_levels_bit_exact(seed):
+    """nsamp a multiple of 16, so downsamples 1, 2, 4, 8 and 16 are binned in
+    one pass over the input, next to 3, 6 and 32 (binned from their source
+    levels): bit-exact against the oracle for both integer kernels."""
+    rng = np.random.default_rng(3000 + seed)
+    nch = int(rng.integers(1, 200))
+    nsamp = 16 * int(rng.integers(300, 1500))
+    dss = sorted(int(d) for d in rng.choice([1, 2, 4, 8, 16, 3, 6, 32],
+                                            size=int(rng.integers(1, 6)), replace=False))
+    ranges, lo = [], 0.0
+    for ds in dss:
+        n = int(rng.integers(5, 40))
+        ranges.append((lo, lo + n * 0.5, 0.5, ds))
+        lo += n * 0.5
+    freqs = synth.band_freqs(1500.0, 1300.0, nch)
+    tsamp = 2.56e-4
+    x = rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8)
+    say("fused binning", seed, x.shape, ranges)
+    want = oracle_flat(x, freqs, tsamp, ranges)
+    for variant in (1, 3):
+        try:
+            plan = dd.Plan(freqs, tsamp, nsamp, ranges, "u8", variant=variant)
+        except dd.DDError:
+            continue                                # variant 3 beyond the LDS
+        xt = torch.from_numpy(x).cuda()
+        out = dd.dedisperse(xt, plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), variant
