@@ -135,10 +135,8 @@ def leg_batched(dd, synth, torch, plain_value, opts):
     on the GPU, excluded from timing)."""
     wls = synth.batched_beams()
     log("leg batched:", len(wls), "beams")
-    # batches run the direct kernels (variants 1 and 2)
-    o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile")}
-    if o.get("variant") == 3:
-        o = {}
+    # the single beam's tuned strategy (a batch holds plans of one kernel)
+    o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile", "stage_chans")}
     plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **o) for w in wls]
     batch = dd.Batch(plans)
     batch.prepare()

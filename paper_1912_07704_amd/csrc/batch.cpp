@@ -2,6 +2,7 @@
 // the order of the persistent launch's work items (most expensive first, so
 // the queue drains evenly).  Plain C++, no HIP.
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 
@@ -38,10 +39,6 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                 *err = "batches hold DD_U8 plans only";
                 return DD_ERR_DTYPE;
             }
-            if (p->subband) {
-                *err = "batches hold variant 1 or 2 plans (variant 3 runs per plan)";
-                return DD_ERR_INVALID;
-            }
             b->in_off[i] = int64_t(in);
             in = align_up(in + size_t(p->nchans) * size_t(p->nsamp), 256);
             b->out_off[i] = int64_t(out);
@@ -51,9 +48,13 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
             lds = std::max(lds, p->lds_bytes);
             if (i == 0) {
                 b->dedup = p->dedup;
+                b->subband = p->subband;
                 b->waves = p->waves;
-            } else if (p->waves != b->waves) {
-                *err = "all plans of a batch need the same DM tile";
+                b->dm_tile = p->dm_tile;
+            } else if (p->subband != b->subband || p->dm_tile != b->dm_tile ||
+                       p->waves != b->waves) {
+                *err = "all plans of a batch need the same kernel variant family (1/2 or 3) "
+                       "and DM tile";
                 return DD_ERR_INVALID;
             }
         }
@@ -77,11 +78,31 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                              return plans[x.beam]->nchans > plans[y.beam]->nchans;
                          });
         int64_t n = 0;
+        double total = 0.0;
         for (BatchDescHost &d : b->descs) {
             d.item_start = n;
             n += d.nitems;
+            total += double(d.nitems) * plans[d.beam]->nchans;
         }
         b->nitems = n;
+        // Queue x starts at the first item whose preceding cost reaches
+        // x/8 of the total: contiguous slices (neighbouring tiles share an
+        // XCD's L2) of equal cost, whatever the mix of channel counts.
+        b->queue_bounds[0] = 0;
+        double before = 0.0;
+        int q = 1;
+        for (const BatchDescHost &d : b->descs) {
+            const double w = plans[d.beam]->nchans;
+            while (q < kBatchQueues && before + double(d.nitems) * w >= total * q / kBatchQueues) {
+                const double need = total * q / kBatchQueues - before;
+                const int64_t k = std::min<int64_t>(
+                    d.nitems, std::max<int64_t>(0, int64_t(std::ceil(need / w))));
+                b->queue_bounds[q++] = d.item_start + k;
+            }
+            before += double(d.nitems) * w;
+        }
+        while (q <= kBatchQueues)
+            b->queue_bounds[q++] = n;
     } catch (const std::bad_alloc &) {
         *err = "host allocation failed";
         return DD_ERR_NOMEM;

@@ -30,6 +30,7 @@ constexpr int kNW = dd::kWaveWords;
 constexpr int kDW = dd::kDmPerWave;
 constexpr int kTileT = dd::kTimeTile;
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round-robin
+constexpr int kCusPerXcd = 32;
 
 // Plan tables are read-only for the whole launch and read at wave-uniform
 // addresses.  The compiler would use vector loads for them after the
@@ -488,11 +489,12 @@ __device__ __forceinline__ void dma16(const void *g, void *l)
 //   [4, tb_offc)       first staged word of the next stage's channel windows
 //   [tb_offc, tb_qoff) per-DM row and delay, nslot x dm_tile
 //   [tb_qoff, ...)     pattern row starts, nslot x jmax x kSubband
-__device__ __forceinline__ int tb_offc(const SbRange &R) { return 4 + ((R.stage_chans + 3) & ~3); }
+template <class RR>
+__device__ __forceinline__ int tb_offc(const RR &R) { return 4 + ((R.stage_chans + 3) & ~3); }
 
 // Direct loads of stage st's tables (its nsb sub-bands start at st*nslot).
-template <int WAVES, int DT>
-__device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st, int nsb,
+template <int WAVES, int DT, class RR>
+__device__ __forceinline__ void tables_issue(const RR &R, int tile, int st, int nsb,
                                              int32_t *T, int wave, int lane)
 {
     const int C = R.stage_chans, nch = R.nchans;
@@ -526,9 +528,10 @@ __device__ __forceinline__ void tables_issue(const SbRange &R, int tile, int st,
 // (global or LDS stage tables).
 // Both copies come from memory: the odd-aligned copy is the same 16-bit
 // row read one sample (2 bytes) later.
-template <int WAVES, bool SCALAR_BASE>
-__device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base, int64_t t0,
-                                           int cs, int cn, uint32_t *buf, int wave, int lane)
+template <int WAVES, bool SCALAR_BASE, class RR>
+__device__ __forceinline__ void rows_issue(const RR &R, const uint16_t *src, const int32_t *base,
+                                           int64_t t0, int cs, int cn, uint32_t *buf, int wave,
+                                           int lane)
 {
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
@@ -537,7 +540,7 @@ __device__ __forceinline__ void rows_issue(const SbRange &R, const int32_t *base
         // (from LDS the start stays a VGPR: only the LDS destination of a
         // direct load has to be wave-uniform)
         const int32_t w0 = SCALAR_BASE ? table1(base + j) : base[j];
-        const uint16_t *g = R.src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
+        const uint16_t *g = src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
         for (int part = 0; part * kWave < chunks; ++part) {
             const int q = part * kWave + lane;
             if (q < chunks) {
@@ -593,8 +596,11 @@ __device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, uint32_t 
     }
 }
 
-template <int WAVES, int DPW, int NW>
-__device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uint32_t *lds)
+// R: the range's fields (read where used, from constant memory: kernel
+// arguments or batch descriptors); src, out: its input rows and output.
+template <int WAVES, int DPW, int NW, class RR>
+__device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src, int32_t *out,
+                                               int64_t lb, uint32_t *lds)
 {
     constexpr int DT = WAVES * DPW;
     const int64_t tt = lb / R.ndm_tiles;
@@ -631,7 +637,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
 
     // sub-bands per stage: nslot, and in the last stage whatever is left
     const int nsb_last = (nchans - (nst - 1) * C + K - 1) / K;
-    rows_issue<WAVES, true>(R, R.baseT + int64_t(tile) * nchans, t0, 0, min(C, nchans), lds,
+    rows_issue<WAVES, true>(R, src, R.baseT + int64_t(tile) * nchans, t0, 0, min(C, nchans), lds,
                             wave, lane);
     tables_issue<WAVES, DT>(R, tile, 0, nst > 1 ? R.nslot : nsb_last, Tb, wave, lane);
     int widen_left = R.widen_every;
@@ -712,7 +718,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
         // barrier): start the next stage's loads.
         if (st + 1 < nst) {
             const int cs = c0 + C;
-            rows_issue<WAVES, false>(R, T + 4, t0, cs, min(C, nchans - cs),
+            rows_issue<WAVES, false>(R, src, T + 4, t0, cs, min(C, nchans - cs),
                                      lds + ((st + 1) & 1) * (2 * CW), wave, lane);
             tables_issue<WAVES, DT>(R, tile, st + 1, st + 2 < nst ? R.nslot : nsb_last,
                                     Tb + ((st + 1) & 1) * R.tb_words, wave, lane);
@@ -771,7 +777,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const SbRange &R, int64_t lb, uin
         const int d = dw0 + dd;
         if (d >= ndms)
             break;
-        int32_t *row = R.out + int64_t(d) * R.nout;
+        int32_t *row = out + int64_t(d) * R.nout;
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             const int64_t t = t0 + 2 * (lane + kWave * k);
@@ -798,7 +804,7 @@ k_dedisp_u8_sb(const SbArgs a)
     for (int i = 1; i < a.nranges; ++i)
         if (L >= a.r[i].block_start)
             r = i;
-    dedisp_tile_sb<WAVES, DPW, NW>(a.r[r], L - a.r[r].block_start, lds);
+    dedisp_tile_sb<WAVES, DPW, NW>(a.r[r], a.r[r].src, a.r[r].out, L - a.r[r].block_start, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1207,10 +1213,16 @@ __global__ void k_reset_counters(int32_t *counters, int n)
         counters[threadIdx.x] = 0;
 }
 
+// Item bounds of the per-XCD queues.
+struct QueueBounds {
+    int64_t b[dd::kBatchQueues + 1];
+};
+static_assert(dd::kBatchQueues == kXcds, "one queue per XCD");
+
 template <bool DEDUP, int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
-                  int ndesc, int64_t nitems, int64_t per_queue, const char *ws, int32_t *out,
+                  int ndesc, const QueueBounds qb, const char *ws, int32_t *out,
                   int32_t *counters)
 {
     // 16-byte rows: the staging loads and the odd-copy build move 16 bytes
@@ -1219,8 +1231,8 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ int64_t s_item;
     const int x = blockIdx.x % kXcds;
-    const int64_t q_begin = int64_t(x) * per_queue;
-    const int64_t q_end = min(nitems, q_begin + per_queue);
+    const int64_t q_begin = qb.b[x];
+    const int64_t q_end = qb.b[x + 1];
     for (;;) {
         if (threadIdx.x == 0)
             s_item = q_begin + atomicAdd(&counters[x], 1);
@@ -1254,6 +1266,70 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
         R.row_words = D.row_words;
         R.widen_every = D.widen_every;
         dedisp_tile_u8<DEDUP, WAVES>(R, L - D.item_start, lds);
+    }
+}
+
+// Variant 3 in the same persistent launch: each (beam, range) carries its
+// whole sub-band range; the workspace and output pointers are the launch's
+// own buffers plus the descriptor's offsets.
+struct SbBatchDesc {
+    SbRange R;                // src and out unset (set per launch from the offsets)
+    int64_t src_off;          // bytes into the workspace
+    int64_t out_off;          // elements into the batch output
+    int64_t item_start;
+    int64_t pad_[2];
+};
+
+static_assert(sizeof(SbBatchDesc) % 32 == 0, "descriptors are read 32 bytes at a time");
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// The descriptors and item starts do not change during a launch: read
+// through the constant address space, they load into scalar registers (the
+// item index is uniform) and the compiler may load a field again rather
+// than hold it in a register through the whole item.
+#define DD_CONST __attribute__((address_space(4)))
+
+template <int WAVES, int DPW, int NW>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
+k_dedisp_u8_sb_batch(const SbBatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
+                     int ndesc, const QueueBounds qb, const char *ws, int32_t *out,
+                     int32_t *counters)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ int64_t s_item;
+    for (;;) {
+        // thread 0 takes the next item of its XCD's queue (-1: queue empty),
+        // so that no queue bound stays live through the item
+        if (threadIdx.x == 0) {
+            const int x = blockIdx.x % kXcds;
+            const int64_t i = qb.b[x] + atomicAdd(&counters[x], 1);
+            s_item = i < qb.b[x + 1] ? i : -1;
+        }
+        __syncthreads();
+        // the item is the same for the whole workgroup: keep it (and with it
+        // the descriptor's fields) in scalar registers
+        const int64_t L = uniform64(s_item);
+        __syncthreads();
+        if (L < 0)
+            break;
+        const DD_CONST int64_t *cs = (const DD_CONST int64_t *)starts;
+        int lo = 0, hi = ndesc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cs[mid] <= L)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DD_CONST SbBatchDesc &D = ((const DD_CONST SbBatchDesc *)descs)[lo];
+        dedisp_tile_sb<WAVES, DPW, NW>(D.R, reinterpret_cast<const uint16_t *>(ws + D.src_off),
+                                       out + D.out_off, L - D.item_start, lds);
     }
 }
 
@@ -1382,6 +1458,31 @@ dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t str
     return DD_OK;
 }
 
+// A variant-3 range's fields apart from its input and output pointers.
+void fill_sb_range(const Plan &p, const DeviceTables &t, const RangeInfo &ri, SbRange &R)
+{
+    const dd::BinLevel &lv = p.levels[ri.level];
+    R.pitch = lv.pitch;
+    R.baseT = t.baseT + ri.base_offset;
+    R.qcnt = t.qcnt + ri.sb_n_offset;
+    R.qoff = t.qoff + ri.sb_q_offset;
+    R.offC = t.offC + ri.sb_c_offset;
+    R.nout = ri.nout;
+    R.block_start = ri.block_start;
+    R.nchans = p.nchans;
+    R.ndms = ri.ndms;
+    R.ndm_tiles = ri.ndm_tiles;
+    R.stage_chans = ri.stage_chans;
+    R.row_words = ri.row_words;
+    R.widen_every = ri.widen_every;
+    R.sb_chans = ri.sb_chans;
+    R.nsub = ri.sb_nsub;
+    R.jmax = ri.sb_jmax;
+    R.qwords = ri.sb_qwords;
+    R.nslot = ri.sb_nslot;
+    R.tb_words = ri.sb_tb_words;
+}
+
 dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const char *d_ws,
                     hipStream_t stream)
 {
@@ -1394,27 +1495,9 @@ dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const 
         const RangeInfo &ri = p.ranges[i];
         const dd::BinLevel &lv = p.levels[ri.level];
         SbRange &R = a.r[i];
+        fill_sb_range(p, t, ri, R);
         R.src = reinterpret_cast<const uint16_t *>(d_ws + lv.ws_offset);
-        R.pitch = lv.pitch;
-        R.baseT = t.baseT + ri.base_offset;
-        R.qcnt = t.qcnt + ri.sb_n_offset;
-        R.qoff = t.qoff + ri.sb_q_offset;
-        R.offC = t.offC + ri.sb_c_offset;
         R.out = d_out + ri.out_offset;
-        R.nout = ri.nout;
-        R.block_start = ri.block_start;
-        R.nchans = p.nchans;
-        R.ndms = ri.ndms;
-        R.ndm_tiles = ri.ndm_tiles;
-        R.stage_chans = ri.stage_chans;
-        R.row_words = ri.row_words;
-        R.widen_every = ri.widen_every;
-        R.sb_chans = ri.sb_chans;
-        R.nsub = ri.sb_nsub;
-        R.jmax = ri.sb_jmax;
-        R.qwords = ri.sb_qwords;
-        R.nslot = ri.sb_nslot;
-        R.tb_words = ri.sb_tb_words;
     }
     const int64_t grid = a.per_xcd * kXcds;
     // dm_tile 192 and 128: 16 wavefronts of 12 or 8 DMs x 2 words; 96 and
@@ -1824,7 +1907,7 @@ dd_status forward_sum(const Plan &p, const DeviceTables &t, void *d_out, const c
 
 // Device-side batch state: descriptor array and item starts, per device.
 struct BatchDevice {
-    BatchDesc *descs = nullptr;
+    void *descs = nullptr;        // BatchDesc[] (variants 1, 2) or SbBatchDesc[] (variant 3)
     int64_t *starts = nullptr;
 };
 
@@ -1846,7 +1929,8 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
         *out = &it->second;
         return DD_OK;
     }
-    std::vector<BatchDesc> hd(b.descs.size());
+    std::vector<BatchDesc> hd(b.subband ? 0 : b.descs.size());
+    std::vector<SbBatchDesc> hsb(b.subband ? b.descs.size() : 0);
     std::vector<int64_t> hs(b.descs.size());
     for (size_t i = 0; i < b.descs.size(); ++i) {
         const dd::BatchDescHost &d = b.descs[i];
@@ -1857,6 +1941,16 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
             return s2;
         const RangeInfo &ri = p.ranges[d.range];
         const dd::BinLevel &lv = p.levels[ri.level];
+        hs[i] = d.item_start;
+        if (b.subband) {
+            SbBatchDesc &S = hsb[i];
+            std::memset(&S, 0, sizeof(S));
+            fill_sb_range(p, *t, ri, S.R);
+            S.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
+            S.out_off = b.out_off[d.beam] + ri.out_offset;
+            S.item_start = d.item_start;
+            continue;
+        }
         BatchDesc &D = hd[i];
         std::memset(&D, 0, sizeof(D));
         D.offT = t->offT + ri.off_offset;
@@ -1873,10 +1967,10 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
         D.stage_chans = ri.stage_chans;
         D.row_words = ri.row_words;
         D.widen_every = ri.widen_every;
-        hs[i] = d.item_start;
     }
     BatchDevice bd;
-    const size_t db = hd.size() * sizeof(BatchDesc), sb = hs.size() * sizeof(int64_t);
+    const size_t db = b.subband ? hsb.size() * sizeof(SbBatchDesc) : hd.size() * sizeof(BatchDesc);
+    const size_t sb = hs.size() * sizeof(int64_t);
     e = hipMalloc(&bd.descs, db + sb + 64);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1884,7 +1978,8 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
         return DD_ERR_NOMEM;
     }
     bd.starts = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(bd.descs) + db);
-    e = hipMemcpy(bd.descs, hd.data(), db, hipMemcpyHostToDevice);
+    e = hipMemcpy(bd.descs, b.subband ? static_cast<const void *>(hsb.data()) : hd.data(), db,
+                  hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(bd.starts, hs.data(), sb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -1912,9 +2007,20 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
     dd_status st = launch_check("k_reset_counters");
     if (st != DD_OK)
         return st;
-    const int64_t per_queue = (b.nitems + kXcds - 1) / kXcds;
+    QueueBounds qb;
+    for (int i = 0; i <= dd::kBatchQueues; ++i)
+        qb.b[i] = b.queue_bounds[i];
     const void *fn = nullptr;
-    if (b.waves == 4)
+    // Persistent workgroups per XCD: two 8-wave (or four 4-wave) per CU of
+    // its 32; variant 3 fills a CU's LDS with one workgroup.
+    unsigned per_xcd = unsigned(kPersistPerXcd * (8 / b.waves));
+    if (b.subband) {
+        fn = b.dm_tile == 192  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 12, 2>)
+             : b.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 8, 2>)
+             : b.dm_tile == 96  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 4>)
+                                : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
+        per_xcd = unsigned(kCusPerXcd);
+    } else if (b.waves == 4)
         fn = b.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4>)
                      : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4>);
     else
@@ -1922,20 +2028,17 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
                      : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8>);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(dd::kMaxLdsBytes - 64));
-    const BatchDesc *descs = bd.descs;
+    const void *descs = bd.descs;
     const int64_t *starts = bd.starts;
     int ndesc = int(b.descs.size());
-    int64_t nitems = b.nitems;
     const char *ws = d_ws;
-    void *args[] = {&descs, &starts, &ndesc, &nitems, const_cast<int64_t *>(&per_queue), &ws,
-                    &d_out, &counters};
-    // Persistent workgroups per XCD: two 8-wave (or four 4-wave) per CU of its 32.
-    const unsigned per_xcd = unsigned(kPersistPerXcd * (8 / b.waves));
+    void *args[] = {&descs, &starts, &ndesc, &qb, &ws, &d_out, &counters};
+    const char *name = b.subband ? "k_dedisp_u8_sb_batch" : "k_dedisp_u8_batch";
     hipError_t e = hipLaunchKernel(fn, dim3(kXcds * per_xcd), dim3(unsigned(b.waves * kWave)),
                                    args, b.lds_bytes, stream);
     if (e != hipSuccess)
-        return hip_fail(e, "k_dedisp_u8_batch");
-    return launch_check("k_dedisp_u8_batch");
+        return hip_fail(e, name);
+    return launch_check(name);
 }
 
 // Argument checks shared by the compute entry points (synchronous, before

@@ -9,6 +9,8 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "plan.h"
 
@@ -31,6 +33,28 @@ std::string fmt(A &&...a)
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// fn(begin, end) over contiguous slices of [0, n) on up to 16 host threads
+// (one when the work is small).  Every element is computed by the same code
+// whatever the slicing, so the tables do not depend on the thread count.
+template <class F>
+void parallel_for(int64_t n, int64_t work_per_item, F fn)
+{
+    const int64_t hw = std::max<int64_t>(1, std::thread::hardware_concurrency());
+    const int64_t nt = std::min<int64_t>({hw, 16, n, std::max<int64_t>(1, n * work_per_item >> 20)});
+    if (nt <= 1) {
+        if (n > 0)
+            fn(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(size_t(nt - 1));
+    for (int64_t k = 1; k < nt; ++k)
+        th.emplace_back(fn, n * k / nt, n * (k + 1) / nt);
+    fn(int64_t(0), n / nt);
+    for (std::thread &t : th)
+        t.join();
+}
 
 
 // Tables of one float32 shift-and-sum problem (see plan.h).  S(a, b) gives
@@ -254,6 +278,7 @@ struct SbPatterns {
     int32_t J = 0;
     std::vector<int32_t> a, idx;          // per DM
     std::vector<int32_t> amin, amax, rep; // per pattern (rep: one of its DMs)
+    std::vector<uint64_t> key;            // per DM: packed pattern (fast path)
 };
 
 void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int32_t c0,
@@ -264,6 +289,8 @@ void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int
     t.a.resize(size_t(nd));
     t.idx.resize(size_t(nd));
     order.resize(size_t(nd));
+    t.key.resize(size_t(nd));
+    int32_t umax = 0;
     for (int32_t i = 0; i < nd; ++i) {
         const int32_t *si = s + size_t(i) * nch;
         int32_t m = si[0];
@@ -271,8 +298,21 @@ void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int
             m = std::min(m, si[k]);
         t.a[i] = m;
         order[i] = i;
+        uint64_t key = 0;
+        for (int32_t k = 0; k < kSubband; ++k) {
+            const int32_t u = k < kb ? si[k] - m : 0;
+            umax = std::max(umax, u);
+            key = (key << 8) | uint64_t(u & 0xff);
+        }
+        t.key[i] = key;
     }
+    // Patterns in lexicographic order of their delays (channel c0 first),
+    // ties in DM order.  With every delay difference below 256 the packed
+    // key (channel c0 in the top byte) orders them the same way.
+    const bool packed = umax < 256;
     auto cmp = [&](int32_t x, int32_t y) {
+        if (packed)
+            return t.key[x] == t.key[y] ? 0 : t.key[x] < t.key[y] ? -1 : 1;
         const int32_t *sx = s + size_t(x) * nch, *sy = s + size_t(y) * nch;
         for (int32_t k = 0; k < kb; ++k) {
             const int32_t u = sx[k] - t.a[x], v = sy[k] - t.a[y];
@@ -281,10 +321,15 @@ void sb_patterns(const Plan &p, const RangeInfo &ri, int32_t d0, int32_t nd, int
         }
         return 0;
     };
-    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-        const int c = cmp(x, y);
-        return c != 0 ? c < 0 : x < y;
-    });
+    if (packed)
+        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            return t.key[x] != t.key[y] ? t.key[x] < t.key[y] : x < y;
+        });
+    else
+        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            const int c = cmp(x, y);
+            return c != 0 ? c < 0 : x < y;
+        });
     t.J = 0;
     t.amin.clear();
     t.amax.clear();
@@ -325,30 +370,47 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
     p->waves = wide ? 2 * kWaves : kWaves;
     int64_t blocks = 0;
     size_t lds = 0;
-    SbPatterns pt;
-    std::vector<int32_t> order;
     for (size_t r = 0; r < p->ranges.size(); ++r) {
         RangeInfo &ri = p->ranges[r];
         const int32_t cap = int32_t(65535 / (255 * ri.ds));
         const int32_t K = std::max(1, std::min(kSubband, cap));
         const int32_t nsub = (nchans + K - 1) / K;
-        int32_t span = 0, jmax = 0, spanJ = 0;
         // pattern rows of at most 64*NW + 64 words: 3 words per lane at
         // 256-sample tiles, 5 at 512
         const int32_t max_spread = 2 * (kWave64 - 1);
-        for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
-            const int32_t nd = std::min(dmt, ri.ndms - d0);
-            const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
-            const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d0 + nd - 1) * nchans];
-            for (int32_t c = 0; c < nchans; ++c)
-                span = std::max(span, s1[c] - s0[c]);
-            for (int32_t b = 0; b < nsub; ++b) {
-                sb_patterns(*p, ri, d0, nd, b * K, std::min(K, nchans - b * K), max_spread, pt,
-                            order);
-                jmax = std::max(jmax, pt.J);
-                for (int32_t j = 0; j < pt.J; ++j)
-                    spanJ = std::max(spanJ, pt.amax[j] - pt.amin[j]);
+        // per DM tile: delay spread, most patterns of a sub-band, widest
+        // pattern spread
+        const int32_t ntiles = (ri.ndms + dmt - 1) / dmt;
+        const size_t nt = size_t(ntiles);
+        std::vector<int32_t> t_span(nt, 0), t_j(nt, 0), t_sj(nt, 0);
+        parallel_for(ntiles, int64_t(nchans) * dmt, [&](int64_t g0, int64_t g1) {
+            SbPatterns pt;
+            std::vector<int32_t> order;
+            for (int64_t g = g0; g < g1; ++g) {
+                const int32_t d0 = int32_t(g) * dmt;
+                const int32_t nd = std::min(dmt, ri.ndms - d0);
+                const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
+                const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d0 + nd - 1) * nchans];
+                int32_t sp = 0, jm = 0, sj = 0;
+                for (int32_t c = 0; c < nchans; ++c)
+                    sp = std::max(sp, s1[c] - s0[c]);
+                for (int32_t b = 0; b < nsub; ++b) {
+                    sb_patterns(*p, ri, d0, nd, b * K, std::min(K, nchans - b * K), max_spread,
+                                pt, order);
+                    jm = std::max(jm, pt.J);
+                    for (int32_t j = 0; j < pt.J; ++j)
+                        sj = std::max(sj, pt.amax[j] - pt.amin[j]);
+                }
+                t_span[size_t(g)] = sp;
+                t_j[size_t(g)] = jm;
+                t_sj[size_t(g)] = sj;
             }
+        });
+        int32_t span = 0, jmax = 0, spanJ = 0;
+        for (int32_t g = 0; g < ntiles; ++g) {
+            span = std::max(span, t_span[size_t(g)]);
+            jmax = std::max(jmax, t_j[size_t(g)]);
+            spanJ = std::max(spanJ, t_sj[size_t(g)]);
         }
         const int32_t Wq = ((spanJ >> 1) + T / 2 + 1 + 3) / 4 * 4;
         const int32_t Wr = (((span + 7) >> 1) + Wq + 1 + 3) / 4 * 4;
@@ -417,7 +479,10 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
     for (RangeInfo &ri : p->ranges) {
         const int32_t K = ri.sb_chans, S = ri.stage_chans, Wr = ri.row_words, Wq = ri.sb_qwords;
         const int32_t jmax = ri.sb_jmax;
-        for (int32_t g = 0; g < ri.ndm_tiles; ++g) {
+        parallel_for(ri.ndm_tiles, int64_t(nchans) * dmt, [&](int64_t g0, int64_t g1) {
+        SbPatterns pt;
+        std::vector<int32_t> order;
+        for (int32_t g = int32_t(g0); g < int32_t(g1); ++g) {
             const int32_t d0 = g * dmt;
             const int32_t nd = std::min(dmt, ri.ndms - d0);
             int32_t *base = &p->baseT[ri.base_offset + size_t(g) * nchans];
@@ -453,6 +518,7 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
                 }
             }
         }
+        });
     }
     return DD_OK;
 }
@@ -574,21 +640,35 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             ri.ndms = int32_t(std::floor((g.dm_hi - g.dm_lo) / g.dm_step + 0.5));
             ri.dm_index = dm_index;
             ri.nbin = nsamp / ri.ds;
+            for (int32_t i = 0; i < ri.ndms; ++i)
+                p->dms.push_back(g.dm_lo + double(i) * g.dm_step);
+            // per DM row: its largest delay, or -1 for a delay out of range
+            std::vector<int32_t> row_max(size_t(ri.ndms), 0);
+            parallel_for(ri.ndms, nchans, [&](int64_t i0, int64_t i1) {
+                for (int64_t i = i0; i < i1; ++i) {
+                    const double dm = p->dms[size_t(dm_index + i)];
+                    int32_t *row = &p->shifts[size_t(dm_index + i) * nchans];
+                    int32_t m = 0;
+                    for (int32_t c = 0; c < nchans; ++c) {
+                        const double x = kDispersion * dm * delta[c] / (tsamp * ri.ds);
+                        const double s = std::floor(x + 0.5);
+                        if (!(s >= 0.0) || s > 2.0e9) {
+                            m = -1;
+                            break;
+                        }
+                        row[c] = int32_t(s);
+                        m = std::max(m, row[c]);
+                    }
+                    row_max[size_t(i)] = m;
+                }
+            });
             int32_t smax = 0;
             for (int32_t i = 0; i < ri.ndms; ++i) {
-                const double dm = g.dm_lo + double(i) * g.dm_step;
-                p->dms.push_back(dm);
-                int32_t *row = &p->shifts[size_t(dm_index + i) * nchans];
-                for (int32_t c = 0; c < nchans; ++c) {
-                    const double x = kDispersion * dm * delta[c] / (tsamp * ri.ds);
-                    const double s = std::floor(x + 0.5);
-                    if (!(s >= 0.0) || s > 2.0e9) {
-                        *err = fmt("range ", r, ": delay out of range at DM ", dm);
-                        return DD_ERR_EMPTY_OUTPUT;
-                    }
-                    row[c] = int32_t(s);
-                    smax = std::max(smax, row[c]);
+                if (row_max[size_t(i)] < 0) {
+                    *err = fmt("range ", r, ": delay out of range at DM ", p->dms[size_t(dm_index + i)]);
+                    return DD_ERR_EMPTY_OUTPUT;
                 }
+                smax = std::max(smax, row_max[size_t(i)]);
             }
             ri.max_shift = smax;
             ri.nout = ri.nbin - smax;
@@ -677,7 +757,8 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         p->baseT.assign(nbase, 0);
         for (RangeInfo &ri : p->ranges) {
             const int32_t copy_words = ri.stage_chans * ri.row_words;
-            for (int32_t c = 0; c < nchans; ++c) {
+            parallel_for(nchans, ri.ndms_pad, [&](int64_t c0, int64_t c1) {
+            for (int32_t c = int32_t(c0); c < int32_t(c1); ++c) {
                 int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
                 for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile) {
                     const int32_t b = p->shifts[size_t(ri.dm_index + tile * dmt) * nchans + c];
@@ -691,6 +772,7 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
                     }
                 }
             }
+            });
         }
     } catch (const std::bad_alloc &) {
         *err = "host allocation failed";

@@ -213,6 +213,8 @@ struct BatchDescHost {
     int64_t nitems = 0;          // time tiles x DM tiles
 };
 
+constexpr int kBatchQueues = 8;                // one work queue per XCD
+
 struct Batch {
     std::vector<const Plan *> plans;       // not owned
     std::vector<int64_t> in_off;           // bytes into the batch input
@@ -223,9 +225,14 @@ struct Batch {
     size_t ws_bytes = 0;
     std::vector<BatchDescHost> descs;      // most expensive items first
     int64_t nitems = 0;
+    // XCD x's queue holds items [queue_bounds[x], queue_bounds[x+1]): equal
+    // shares of the cost (items weigh their beam's channel count)
+    int64_t queue_bounds[kBatchQueues + 1] = {};
     size_t lds_bytes = 0;
     bool dedup = true;
+    bool subband = false;                  // variant 3 plans, all with one DM tile
     int32_t waves = kWaves;
+    int32_t dm_tile = kDmTile;
     void *device = nullptr;
 };
 

@@ -1,6 +1,6 @@
 """Batched integer forward: one persistent launch over many beams of uneven
-shape, bit-exact against each beam's own forward and the oracle, and
-replayable from a HIP graph."""
+shape (direct kernel or variant 3), bit-exact against each beam's own
+forward and the oracle, and replayable from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -18,13 +18,15 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def small_beams(seed, n):
+def small_beams(seed, n, subband=False):
+    """Beams of uneven shape.  For variant 3, shapes whose delay patterns fit
+    the LDS at every DM tile (no 7-channel band, 128 us sampling)."""
     rng = np.random.default_rng(700 + seed)
     beams = []
     for b in range(n):
-        nch = int(rng.choice([7, 64, 130, 256]))
+        nch = int(rng.choice([64, 130, 256] if subband else [7, 64, 130, 256]))
         nsamp = int(rng.integers(3000, 20000))
-        tsamp = float(rng.choice([64e-6, 128e-6]))
+        tsamp = float(rng.choice([128e-6] if subband else [64e-6, 128e-6]))
         dm_max = float(rng.choice([150.0, 300.0, 500.0]))
         freqs = synth.band_freqs(1670.0, 1370.0, nch)
         beams.append((rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8), freqs, tsamp,
@@ -32,10 +34,20 @@ def small_beams(seed, n):
     return beams
 
 
-def test_small_batch_matches_single_plans_and_oracle():
-    beams = small_beams(0, 7)
-    say("small batch", [b[0].shape for b in beams])
-    plans = [dd.Plan(f, t, x.shape[1], r) for (x, f, t, r) in beams]
+# direct kernel (library default) and variant 3 at each of its workgroup shapes
+STRATEGIES = {"direct": {}, "v3-192": {"variant": 3}, "v3-128": {"variant": 3, "dm_tile": 128},
+              "v3-96": {"variant": 3, "dm_tile": 96}}
+
+
+def make_plans(beams, opts):
+    return [dd.Plan(f, t, x.shape[1], r, **opts) for (x, f, t, r) in beams]
+
+
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
+def test_small_batch_matches_single_plans_and_oracle(strategy):
+    beams = small_beams(0, 7, strategy != "direct")
+    say("small batch", strategy, [b[0].shape for b in beams])
+    plans = make_plans(beams, STRATEGIES[strategy])
     batch = dd.Batch(plans)
     xin = batch.pack([b[0] for b in beams])
     out = dd.dedisperse_batch(xin, batch)
@@ -47,10 +59,11 @@ def test_small_batch_matches_single_plans_and_oracle():
         assert np.array_equal(o.cpu().numpy(), cref.dedisperse_u8(x, f, t, r))
 
 
-def test_batch_graph_replay():
-    beams = small_beams(1, 5)
-    say("graph replay")
-    plans = [dd.Plan(f, t, x.shape[1], r) for (x, f, t, r) in beams]
+@pytest.mark.parametrize("strategy", ["direct", "v3-192"])
+def test_batch_graph_replay(strategy):
+    beams = small_beams(1, 5, strategy != "direct")
+    say("graph replay", strategy)
+    plans = make_plans(beams, STRATEGIES[strategy])
     batch = dd.Batch(plans)
     batch.prepare()
     xin = batch.pack([b[0] for b in beams])
@@ -86,14 +99,15 @@ def test_batch_graph_replay():
         assert torch.equal(other, batch.split(eager)[0])
 
 
-def test_batched_beams_full_size():
+@pytest.mark.parametrize("strategy", ["direct", "v3-192"])
+def test_batched_beams_full_size(strategy):
     """The 64-beam batched workload (channel counts 1024/2048/4096, lengths
     2^16..2^18, DM max 500/1000/2000), drawn on the GPU: every beam of the
     one persistent launch equals its own dd_forward, and sampled outputs of
     three beams equal the oracle."""
     wls = synth.batched_beams()
-    say("batched beams: plans")
-    plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges) for w in wls]
+    say("batched beams: plans", strategy)
+    plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **STRATEGIES[strategy]) for w in wls]
     batch = dd.Batch(plans)
     say("batched beams: inputs", batch.in_bytes, batch.out_elems, batch.workspace_bytes)
     xin = torch.empty(batch.in_bytes, dtype=torch.uint8, device="cuda")

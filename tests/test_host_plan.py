@@ -228,15 +228,29 @@ def test_subband_option_errors(opts):
     assert e.value.status == -2
 
 
-def test_subband_variant_is_integer_only_and_not_batched():
+def test_subband_variant_is_integer_only_and_batches_keep_one_kernel():
+    """Variant 3 is DD_U8 only.  A batch holds variant 3 plans of one DM
+    tile, or direct-kernel plans (variants 1 and 2) of one DM tile."""
     w = synth.tiny()
     with pytest.raises(dd.DDError) as e:
         dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
     assert e.value.status == -2
     p3 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3)
-    with pytest.raises(dd.DDError) as e:
-        dd.Batch([p3])
-    assert e.value.status == -2
+    p3b = dd.Plan(w.freqs, w.tsamp, w.nsamp // 2, w.ranges, "u8", variant=3)
+    p3_128 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3, dm_tile=128)
+    p1 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=1)
+    p2 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=2)
+    b = dd.Batch([p3, p3b])
+    def items(p):
+        tt, dt = p.strategy["time_tile"], p.strategy["dm_tile"]
+        return sum(-(-r.nout // tt) * -(-r.ndms // dt) for r in p.ranges)
+
+    assert b.work_items == items(p3) + items(p3b)
+    dd.Batch([p1, p2])
+    for mix in ([p3, p1], [p1, p3], [p3, p3_128]):
+        with pytest.raises(dd.DDError) as e:
+            dd.Batch(mix)
+        assert e.value.status == -2 and "DM tile" in str(e.value)
 
 
 def test_subband_variant_rejects_plans_beyond_the_lds():
