@@ -121,7 +121,7 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *                sub-band of 8 channels differ from their smallest by the
  *                same pattern share that sub-band's partial sum (the same
  *                integer result; DD_ERR_INVALID when the patterns of a
- *                plan do not fit the LDS).  Not for batches.
+ *                plan do not fit the LDS).
  *   stage_chans  channels staged in LDS at once (rounded down to even,
  *                or to a multiple of the sub-band for variant 3, and
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
@@ -303,8 +303,14 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
  * first).  Results equal dd_forward of each plan bit for bit.
  *
  * dd_batch_create   plans: [nbeams] DD_U8 plans (borrowed: they must
- *                   outlive the batch).  Host-only.  Errors: DD_ERR_NULL,
- *                   DD_ERR_INVALID (nbeams < 1), DD_ERR_DTYPE, DD_ERR_NOMEM.
+ *                   outlive the batch), all of one kernel family -- direct
+ *                   (variants 1 and 2) or sub-band (variant 3) -- and one
+ *                   DM tile.  The work items are dealt to one queue per
+ *                   XCD in contiguous slices of equal cost (an item weighs
+ *                   its beam's channel count).  Host-only.  Errors:
+ *                   DD_ERR_NULL, DD_ERR_INVALID (nbeams < 1, or plans of
+ *                   different kernel families or DM tiles), DD_ERR_DTYPE,
+ *                   DD_ERR_NOMEM.
  * dd_batch_info     in_bytes: size of the batch input buffer (each beam's
  *                   [nchans][nsamp] uint8 block at its in_offset);
  *                   out_elems: int32 elements of the batch output (each

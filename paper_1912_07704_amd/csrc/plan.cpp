@@ -429,7 +429,8 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         int32_t stage = std::min(cap >= 2 * K ? 2 * K : K, std::max(K, nchans));
         if (want_stage > 0)
             stage = std::max(K, std::min(stage, want_stage / K * K));
-        const size_t target = kMaxLdsBytes - 1024;
+        // (the batch kernel keeps 16 bytes of static LDS beside the dynamic)
+        const size_t target = kMaxLdsBytes - 64;
         if (stage > K && bytes_for(stage) > target)
             stage = K;
         if (bytes_for(stage) > target) {
@@ -438,6 +439,7 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
                        " bytes of LDS");
             return DD_ERR_INVALID;
         }
+        ri.sb_spread = max_spread;
         ri.sb_chans = K;
         ri.sb_nsub = nsub;
         ri.sb_jmax = jmax;
@@ -494,7 +496,7 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
                 const int32_t c0 = sb * K, kb = std::min(K, nchans - c0);
                 const int32_t cs = c0 / S * S;            // first channel of the stage
                 const int32_t slot = (c0 - cs) / K;
-                sb_patterns(*p, ri, d0, nd, c0, kb, 2 * (kWave64 - 1), pt, order);
+                sb_patterns(*p, ri, d0, nd, c0, kb, ri.sb_spread, pt, order);
                 const size_t gb = size_t(g) * ri.sb_nsub + sb;
                 p->qcntT[ri.sb_n_offset + gb] = pt.J;
                 int32_t *q = &p->qoffT[ri.sb_q_offset + gb * jmax * kSubband];

@@ -105,6 +105,7 @@ struct RangeInfo {
     size_t off_offset = 0;       // element offset of this range in offT
     size_t base_offset = 0;      // element offset of this range in baseT
     // integer variant 3 (exact sub-band reuse)
+    int32_t sb_spread = 0;       // largest spread of a pattern row's smallest delays
     int32_t sb_chans = 0;        // channels per sub-band (kSubband, fewer at large ds)
     int32_t sb_nsub = 0;         // sub-bands
     int32_t sb_jmax = 0;         // most delay patterns of one sub-band in one DM tile
