@@ -562,25 +562,28 @@ __device__ __forceinline__ int lds_uniform(const int32_t *p)
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveRol1 = 0x134;
 
-// One pattern row of up to NQ*64 words, both copies.  Even word
-// w = lane + 64i is the sum of the 8 channel words at the row's offsets
-// (every read issued before the first sum; words past the row read other
-// LDS data and are not stored).  Odd word w takes the upper half of even w
-// and the lower half of even w+1, which lane+1 holds (lane 63: lane 0 of
-// the next group).
-template <int NQ>
-__device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, uint32_t *qe, int Wq,
-                                     int lane)
+// One pattern row of NQ*64 words or fewer (Wq > 64 * (NQ - 1)), both
+// copies.  Even word w = lane + 64i is the sum of the kb channel words at
+// the row's offsets (all reads in flight before the first sum; words past
+// the row read other LDS data and are not stored).  Odd word w takes the
+// upper half of even w and the lower half of even w+1, which lane+1 holds
+// (lane 63: lane 0 of the next group).
+template <int NQ, bool FULL>
+__device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, int kb, uint32_t *qe,
+                                     int Wq, int lane)
 {
-    uint32_t sv[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i)
-        sv[i] = 0;
+    uint32_t v[dd::kSubband][NQ];
 #pragma unroll
     for (int k = 0; k < dd::kSubband; ++k)
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
-            sv[i] += A[ov[k] + lane + kWave * i];
+            v[k][i] = (FULL || k < kb) ? A[ov[k] + lane + kWave * i] : 0u;
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t sv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        sv[i] = ((v[0][i] + v[1][i]) + (v[2][i] + v[3][i])) +
+                ((v[4][i] + v[5][i]) + (v[6][i] + v[7][i]));
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int w = lane + kWave * i;
@@ -589,15 +592,15 @@ __device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, uint32_t 
                                     : 0;
         const uint32_t nb = uint32_t(__builtin_amdgcn_update_dpp(wrap, int(sv[i]), kDppWaveShl1,
                                                                  0xF, 0xF, false));
-        if (w < Wq)
+        // only the last group can reach the end of the row
+        const bool last = i == NQ - 1;
+        if (!last || w < Wq)
             qe[w] = sv[i];
-        if (w + 1 < Wq)
+        if (!last || w + 1 < Wq)
             qe[Wq + w] = __builtin_amdgcn_alignbyte(nb, sv[i], 2);
     }
 }
 
-// R: the range's fields (read where used, from constant memory: kernel
-// arguments or batch descriptors); src, out: its input rows and output.
 template <int WAVES, int DPW, int NW, class RR>
 __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src, int32_t *out,
                                                int64_t lb, uint32_t *lds)
@@ -653,65 +656,28 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
 
         const int J0 = lds_uniform(T);
         const int J1 = nsb > 1 ? lds_uniform(T + 1) : 0;
-        // Pattern rows, one per wavefront at a time: even copy (word w = sum
-        // of the sub-band's channels at the pattern's delays), then the odd
-        // copy from the even one (same wavefront: LDS keeps its order).
+        // Pattern rows, one per wavefront at a time; row r = s * jmax + j
+        // holds pattern j of the stage's sub-band s.  NW + 1 words per lane
+        // cover a row (the plan keeps 64 * NW < Wq <= 64 * (NW + 1)); only
+        // a band's last sub-band (or sub-bands of fewer than 8 channels at
+        // large downsampling) sums fewer channels.
+        const bool full = K == dd::kSubband && c0 + nsb * K <= nchans;
         for (int row = wave; row < J0 + J1; row += WAVES) {
             const int s = row >= J0 ? 1 : 0;
-            const int j = row - s * J0;
-            const int kb = min(K, nchans - (c0 + s * K));
-            const int32_t *qo = T + qoffs + (s * jmax + j) * dd::kSubband;
-            // the row's 8 channel offsets: broadcast word reads kept in VGPRs
-            // (word loads: the compiler does not order them behind the
-            // outstanding direct-to-LDS loads)
+            const int r = row + s * (jmax - J0);
+            const int32_t *qo = T + qoffs + r * dd::kSubband;
+            // the row's 8 channel offsets: broadcast word reads (word loads:
+            // the compiler does not order them behind the outstanding
+            // direct-to-LDS loads)
             int ov[dd::kSubband];
 #pragma unroll
             for (int k = 0; k < dd::kSubband; ++k)
                 ov[k] = qo[k];
-            uint32_t *qe = Q + ((s * jmax + j) * 2) * Wq;
-            if (kb == dd::kSubband && Wq <= 3 * kWave) {
-                qrow<3>(A, ov, qe, Wq, lane);
-                continue;
-            }
-            if (kb == dd::kSubband && Wq <= 4 * kWave) {
-                qrow<4>(A, ov, qe, Wq, lane);
-                continue;
-            }
-            if (kb == dd::kSubband) {
-                // two words per lane per pass (read in pairs 64 words apart)
-                for (int w0 = 0; w0 < Wq; w0 += 2 * kWave) {
-                    const int w = w0 + lane;
-                    uint32_t s0 = 0, s1 = 0;
-#pragma unroll
-                    for (int k = 0; k < dd::kSubband; ++k) {
-                        s0 += A[ov[k] + w];
-                        s1 += A[ov[k] + w + kWave];
-                    }
-                    if (w < Wq)
-                        qe[w] = s0;
-                    if (w + kWave < Wq)
-                        qe[w + kWave] = s1;
-                }
-            } else {
-                for (int w = lane; w < Wq; w += kWave) {
-                    uint32_t sum = A[ov[0] + w];
-#pragma unroll
-                    for (int k = 1; k < dd::kSubband; ++k)
-                        if (k < kb)
-                            sum += A[ov[k] + w];
-                    qe[w] = sum;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            for (int w0 = 0; w0 + 1 < Wq; w0 += 2 * kWave) {
-                const int w = w0 + lane;
-                const uint32_t a0 = qe[w], a1 = qe[w + 1];
-                const uint32_t b0 = qe[w + kWave], b1 = qe[w + kWave + 1];
-                if (w + 1 < Wq)
-                    qe[Wq + w] = __builtin_amdgcn_alignbyte(a1, a0, 2);
-                if (w + kWave + 1 < Wq)
-                    qe[Wq + w + kWave] = __builtin_amdgcn_alignbyte(b1, b0, 2);
-            }
+            uint32_t *qe = Q + r * 2 * Wq;
+            if (full)
+                qrow<NW + 1, true>(A, ov, dd::kSubband, qe, Wq, lane);
+            else
+                qrow<NW + 1, false>(A, ov, min(K, nchans - (c0 + s * K)), qe, Wq, lane);
         }
         // Every window, both copies and this stage's tables are in LDS (the
         // previous stage's sums finished before this stage's first

@@ -412,7 +412,13 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
             jmax = std::max(jmax, t_j[size_t(g)]);
             spanJ = std::max(spanJ, t_sj[size_t(g)]);
         }
+        // 64*NW < Wq <= 64*NW + 64 (NW = T/128 words per lane): the kernel
+        // builds a row with NW + 1 words per lane
         const int32_t Wq = ((spanJ >> 1) + T / 2 + 1 + 3) / 4 * 4;
+        if (Wq <= T / 2 || Wq > T / 2 + kWave64) {
+            *err = fmt("variant 3, range ", r, ": pattern rows of ", Wq, " words");
+            return DD_ERR_INVALID;
+        }
         const int32_t Wr = (((span + 7) >> 1) + Wq + 1 + 3) / 4 * 4;
         // LDS: two stages of channel windows (even and odd copies), the
         // pattern rows of one stage (even and odd), and two buffers of
