@@ -703,7 +703,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd)
                 offb[dd] = oc[DT + dd];
-            // groups of 4 DMs bound the loads in flight (and the VGPRs they hold)
+            // groups of 6 DMs bound the loads in flight (and the VGPRs they hold)
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd) {
                 const uint32_t *pa = rowq + offa[dd];
@@ -711,7 +711,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
 #pragma unroll
                 for (int k = 0; k < NW; ++k)
                     acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
-                if (dd % 4 == 3 && dd + 1 < DPW)
+                if (dd % 6 == 5 && dd + 1 < DPW)
                     __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -721,7 +721,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
 #pragma unroll
                 for (int k = 0; k < NW; ++k)
                     acc16[dd][k] += pa[kWave * k];
-                if (dd % 4 == 3 && dd + 1 < DPW)
+                if (dd % 6 == 5 && dd + 1 < DPW)
                     __builtin_amdgcn_sched_barrier(0);
             }
         }
