@@ -114,22 +114,27 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  * Strategy options for dd_plan_create_ex (paper, "Plan and strategy": the
  * strategy is configured once, then immutable).  Zero means "library
  * default" for every field.
- *   variant      DD_U8 shift-and-sum kernel: 1 (default) = read a
- *                channel's words for every DM, 2 = re-read them only when
- *                the DM's delay differs from the previous DM's, 3 = exact
- *                sub-band reuse: DMs of a DM tile whose delays over a
- *                sub-band of 8 channels differ from their smallest by the
- *                same pattern share that sub-band's partial sum (the same
- *                integer result; DD_ERR_INVALID when the patterns of a
- *                plan do not fit the LDS).
+ *   variant      DD_U8 shift-and-sum kernel: 1 = read a channel's words
+ *                for every DM, 2 = re-read them only when the DM's delay
+ *                differs from the previous DM's, 3 = exact sub-band reuse:
+ *                DMs of a DM tile whose delays over a sub-band of 8
+ *                channels differ from their smallest by the same pattern
+ *                share that sub-band's partial sum (the same integer
+ *                result; DD_ERR_INVALID when the patterns of a plan do not
+ *                fit the LDS).  0 (the default) = variant 3 at the
+ *                requested DM tile, or at 192 and then 128 when none is
+ *                requested, if the patterns fit; variant 1 otherwise (at
+ *                DM tile 32 when requested, else 64).  dd_plan_strategy
+ *                reports the choice.
  *   stage_chans  channels staged in LDS at once (rounded down to even,
  *                or to a multiple of the sub-band for variant 3, and
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit
  *                partial sums allow).
  *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8)
- *                for variants 1 and 2; for variant 3, 192 (the default) or
- *                128 (16 wavefronts, 256-sample time tiles), or 96 or 64 (8
- *                wavefronts, 512-sample time tiles).
+ *                for variants 1 and 2 (default 64); for variant 3, 192 (the
+ *                default) or 128 (16 wavefronts, 256-sample time tiles), or
+ *                96 or 64 (8 wavefronts, 512-sample time tiles); any of
+ *                these for variant 0.
  */
 typedef struct {
     int32_t variant;
@@ -296,26 +301,25 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
 
 /*
  * Batches: many integer plans (beams of uneven channel counts, lengths and
- * DM plans) summed by ONE persistent launch that takes its work items --
- * (beam, range, time tile, DM tile), most expensive first -- from queues
- * in the workspace.  The launch sequence allocates nothing and contains no
+ * DM plans) summed by persistent launches -- ONE per kernel the plans use
+ * (variant family and DM tile; usually one) -- that take their work items
+ * (beam, range, time tile, DM tile), most expensive first, from queues in
+ * the workspace.  The launch sequence allocates nothing and contains no
  * memset, so it can be captured in a HIP graph (call dd_batch_prepare
  * first).  Results equal dd_forward of each plan bit for bit.
  *
  * dd_batch_create   plans: [nbeams] DD_U8 plans (borrowed: they must
- *                   outlive the batch), all of one kernel family -- direct
- *                   (variants 1 and 2) or sub-band (variant 3) -- and one
- *                   DM tile.  The work items are dealt to one queue per
- *                   XCD in contiguous slices of equal cost (an item weighs
- *                   its beam's channel count).  Host-only.  Errors:
- *                   DD_ERR_NULL, DD_ERR_INVALID (nbeams < 1, or plans of
- *                   different kernel families or DM tiles), DD_ERR_DTYPE,
- *                   DD_ERR_NOMEM.
+ *                   outlive the batch).  Plans that run the same kernel
+ *                   form one group; a group's work items are dealt to one
+ *                   queue per XCD in contiguous slices of equal cost (an
+ *                   item weighs its beam's channel count).  Host-only.
+ *                   Errors: DD_ERR_NULL, DD_ERR_INVALID (nbeams < 1),
+ *                   DD_ERR_DTYPE, DD_ERR_NOMEM.
  * dd_batch_info     in_bytes: size of the batch input buffer (each beam's
  *                   [nchans][nsamp] uint8 block at its in_offset);
  *                   out_elems: int32 elements of the batch output (each
  *                   beam's dd_forward layout at its out_offset); ws_bytes:
- *                   workspace; work_items: items of the persistent launch.
+ *                   workspace; work_items: items of all its launches.
  *                   Any pointer may be NULL.
  * dd_batch_beam     byte offset of beam b's input and element offset of its
  *                   output (both 256-byte aligned).

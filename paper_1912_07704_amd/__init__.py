@@ -134,8 +134,8 @@ class Plan:
 
 
 class Batch:
-    """Many u8 plans summed by one persistent launch (dd_batch_*).  The
-    plans must stay alive as long as the batch."""
+    """Many u8 plans summed by persistent launches, one per kernel the plans
+    use (dd_batch_*).  The plans must stay alive as long as the batch."""
 
     def __init__(self, plans):
         L = lib()

@@ -27,8 +27,9 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
         b->in_off.assign(size_t(nbeams), 0);
         b->out_off.assign(size_t(nbeams), 0);
         b->ws_off.assign(size_t(nbeams), 0);
+        b->groups.clear();
+        std::vector<int32_t> group_of(size_t(nbeams), 0);
         size_t in = 0, out = 0, ws = kBatchCounterBytes;
-        size_t lds = 0;
         for (int32_t i = 0; i < nbeams; ++i) {
             const Plan *p = plans[i];
             if (!p) {
@@ -45,64 +46,86 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
             out = align_up(out + size_t(p->out_elems), 64);
             b->ws_off[i] = ws;
             ws = align_up(ws + p->ws_bytes, 256);
-            lds = std::max(lds, p->lds_bytes);
-            if (i == 0) {
-                b->dedup = p->dedup;
-                b->subband = p->subband;
-                b->waves = p->waves;
-                b->dm_tile = p->dm_tile;
-            } else if (p->subband != b->subband || p->dm_tile != b->dm_tile ||
-                       p->waves != b->waves) {
-                *err = "all plans of a batch need the same kernel variant family (1/2 or 3) "
-                       "and DM tile";
-                return DD_ERR_INVALID;
+            // plans that run the same kernel share a group (one launch)
+            int32_t g = 0;
+            while (g < int32_t(b->groups.size()) &&
+                   !(b->groups[g].subband == p->subband && b->groups[g].dedup == p->dedup &&
+                     b->groups[g].dm_tile == p->dm_tile))
+                ++g;
+            if (g == int32_t(b->groups.size())) {
+                if (g == kBatchMaxGroups) {
+                    *err = "a batch runs at most " + std::to_string(kBatchMaxGroups) +
+                           " kernels (variant, DM tile)";
+                    return DD_ERR_INVALID;
+                }
+                BatchGroup G;
+                G.subband = p->subband;
+                G.dedup = p->dedup;
+                G.dm_tile = p->dm_tile;
+                G.waves = p->waves;
+                b->groups.push_back(G);
             }
+            b->groups[g].lds_bytes = std::max(b->groups[g].lds_bytes, p->lds_bytes);
+            group_of[size_t(i)] = g;
         }
         b->in_bytes = int64_t(in);
         b->out_elems = int64_t(out);
         b->ws_bytes = ws;
-        b->lds_bytes = lds;
         // Work items: every (beam, range) contributes time tiles x DM tiles
         // items of equal shape whose cost grows with the beam's channels.
         b->descs.clear();
-        for (int32_t i = 0; i < nbeams; ++i)
-            for (int32_t r = 0; r < int32_t(plans[i]->ranges.size()); ++r) {
-                BatchDescHost d;
-                d.beam = i;
-                d.range = r;
-                d.nitems = plans[i]->ranges[r].ntime_tiles * plans[i]->ranges[r].ndm_tiles;
-                b->descs.push_back(d);
+        b->nitems = 0;
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            BatchGroup &G = b->groups[g];
+            G.desc_begin = b->descs.size();
+            for (int32_t i = 0; i < nbeams; ++i) {
+                if (group_of[size_t(i)] != int32_t(g))
+                    continue;
+                for (int32_t r = 0; r < int32_t(plans[i]->ranges.size()); ++r) {
+                    BatchDescHost d;
+                    d.beam = i;
+                    d.range = r;
+                    d.nitems = plans[i]->ranges[r].ntime_tiles * plans[i]->ranges[r].ndm_tiles;
+                    b->descs.push_back(d);
+                }
             }
-        std::stable_sort(b->descs.begin(), b->descs.end(),
-                         [&](const BatchDescHost &x, const BatchDescHost &y) {
-                             return plans[x.beam]->nchans > plans[y.beam]->nchans;
-                         });
-        int64_t n = 0;
-        double total = 0.0;
-        for (BatchDescHost &d : b->descs) {
-            d.item_start = n;
-            n += d.nitems;
-            total += double(d.nitems) * plans[d.beam]->nchans;
-        }
-        b->nitems = n;
-        // Queue x starts at the first item whose preceding cost reaches
-        // x/8 of the total: contiguous slices (neighbouring tiles share an
-        // XCD's L2) of equal cost, whatever the mix of channel counts.
-        b->queue_bounds[0] = 0;
-        double before = 0.0;
-        int q = 1;
-        for (const BatchDescHost &d : b->descs) {
-            const double w = plans[d.beam]->nchans;
-            while (q < kBatchQueues && before + double(d.nitems) * w >= total * q / kBatchQueues) {
-                const double need = total * q / kBatchQueues - before;
-                const int64_t k = std::min<int64_t>(
-                    d.nitems, std::max<int64_t>(0, int64_t(std::ceil(need / w))));
-                b->queue_bounds[q++] = d.item_start + k;
+            G.desc_end = b->descs.size();
+            std::stable_sort(b->descs.begin() + G.desc_begin, b->descs.end(),
+                             [&](const BatchDescHost &x, const BatchDescHost &y) {
+                                 return plans[x.beam]->nchans > plans[y.beam]->nchans;
+                             });
+            int64_t n = 0;
+            double total = 0.0;
+            for (size_t k = G.desc_begin; k < G.desc_end; ++k) {
+                BatchDescHost &d = b->descs[k];
+                d.item_start = n;
+                n += d.nitems;
+                total += double(d.nitems) * plans[d.beam]->nchans;
             }
-            before += double(d.nitems) * w;
+            G.nitems = n;
+            b->nitems += n;
+            // Queue x starts at the first item whose preceding cost reaches
+            // x/8 of the group's total: contiguous slices (neighbouring tiles
+            // share an XCD's L2) of equal cost, whatever the mix of channel
+            // counts.
+            G.queue_bounds[0] = 0;
+            double before = 0.0;
+            int q = 1;
+            for (size_t k = G.desc_begin; k < G.desc_end; ++k) {
+                const BatchDescHost &d = b->descs[k];
+                const double w = plans[d.beam]->nchans;
+                while (q < kBatchQueues &&
+                       before + double(d.nitems) * w >= total * q / kBatchQueues) {
+                    const double need = total * q / kBatchQueues - before;
+                    const int64_t m = std::min<int64_t>(
+                        d.nitems, std::max<int64_t>(0, int64_t(std::ceil(need / w))));
+                    G.queue_bounds[q++] = d.item_start + m;
+                }
+                before += double(d.nitems) * w;
+            }
+            while (q <= kBatchQueues)
+                G.queue_bounds[q++] = n;
         }
-        while (q <= kBatchQueues)
-            b->queue_bounds[q++] = n;
     } catch (const std::bad_alloc &) {
         *err = "host allocation failed";
         return DD_ERR_NOMEM;

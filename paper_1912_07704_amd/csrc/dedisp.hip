@@ -1871,10 +1871,12 @@ dd_status forward_sum(const Plan &p, const DeviceTables &t, void *d_out, const c
 }
 
 
-// Device-side batch state: descriptor array and item starts, per device.
+// Device-side batch state, per device: one allocation holding, per kernel
+// group, its descriptor array (BatchDesc or SbBatchDesc) and item starts.
 struct BatchDevice {
-    void *descs = nullptr;        // BatchDesc[] (variants 1, 2) or SbBatchDesc[] (variant 3)
-    int64_t *starts = nullptr;
+    void *mem = nullptr;
+    std::vector<const void *> descs;       // per group
+    std::vector<const int64_t *> starts;   // per group
 };
 
 struct BatchState {
@@ -1895,64 +1897,72 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
         *out = &it->second;
         return DD_OK;
     }
-    std::vector<BatchDesc> hd(b.subband ? 0 : b.descs.size());
-    std::vector<SbBatchDesc> hsb(b.subband ? b.descs.size() : 0);
-    std::vector<int64_t> hs(b.descs.size());
-    for (size_t i = 0; i < b.descs.size(); ++i) {
-        const dd::BatchDescHost &d = b.descs[i];
-        const Plan &p = *b.plans[d.beam];
-        DeviceTables *t = nullptr;
-        dd_status s2 = device_tables(p, &t);
-        if (s2 != DD_OK)
-            return s2;
-        const RangeInfo &ri = p.ranges[d.range];
-        const dd::BinLevel &lv = p.levels[ri.level];
-        hs[i] = d.item_start;
-        if (b.subband) {
-            SbBatchDesc &S = hsb[i];
-            std::memset(&S, 0, sizeof(S));
-            fill_sb_range(p, *t, ri, S.R);
-            S.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
-            S.out_off = b.out_off[d.beam] + ri.out_offset;
-            S.item_start = d.item_start;
-            continue;
+    // host image: per group, descriptors then starts, each 256-byte aligned
+    std::vector<char> img;
+    std::vector<size_t> off_desc(b.groups.size()), off_start(b.groups.size());
+    auto grow = [&](size_t bytes) {
+        const size_t at = (img.size() + 255) / 256 * 256;
+        img.resize(at + bytes, 0);
+        return at;
+    };
+    for (size_t g = 0; g < b.groups.size(); ++g) {
+        const dd::BatchGroup &G = b.groups[g];
+        const size_t n = G.desc_end - G.desc_begin;
+        off_desc[g] = grow(n * (G.subband ? sizeof(SbBatchDesc) : sizeof(BatchDesc)));
+        off_start[g] = grow(n * sizeof(int64_t));
+        for (size_t k = 0; k < n; ++k) {
+            const dd::BatchDescHost &d = b.descs[G.desc_begin + k];
+            const Plan &p = *b.plans[d.beam];
+            DeviceTables *t = nullptr;
+            dd_status s2 = device_tables(p, &t);
+            if (s2 != DD_OK)
+                return s2;
+            const RangeInfo &ri = p.ranges[d.range];
+            const dd::BinLevel &lv = p.levels[ri.level];
+            reinterpret_cast<int64_t *>(img.data() + off_start[g])[k] = d.item_start;
+            if (G.subband) {
+                SbBatchDesc &S = reinterpret_cast<SbBatchDesc *>(img.data() + off_desc[g])[k];
+                fill_sb_range(p, *t, ri, S.R);
+                S.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
+                S.out_off = b.out_off[d.beam] + ri.out_offset;
+                S.item_start = d.item_start;
+                continue;
+            }
+            BatchDesc &D = reinterpret_cast<BatchDesc *>(img.data() + off_desc[g])[k];
+            D.offT = t->offT + ri.off_offset;
+            D.baseT = t->baseT + ri.base_offset;
+            D.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
+            D.out_off = b.out_off[d.beam] + ri.out_offset;
+            D.pitch = lv.pitch;
+            D.nout = ri.nout;
+            D.item_start = d.item_start;
+            D.nchans = p.nchans;
+            D.ndms = ri.ndms;
+            D.ndms_pad = ri.ndms_pad;
+            D.ndm_tiles = ri.ndm_tiles;
+            D.stage_chans = ri.stage_chans;
+            D.row_words = ri.row_words;
+            D.widen_every = ri.widen_every;
         }
-        BatchDesc &D = hd[i];
-        std::memset(&D, 0, sizeof(D));
-        D.offT = t->offT + ri.off_offset;
-        D.baseT = t->baseT + ri.base_offset;
-        D.src_off = int64_t(b.ws_off[d.beam] + lv.ws_offset);
-        D.out_off = b.out_off[d.beam] + ri.out_offset;
-        D.pitch = lv.pitch;
-        D.nout = ri.nout;
-        D.item_start = d.item_start;
-        D.nchans = p.nchans;
-        D.ndms = ri.ndms;
-        D.ndms_pad = ri.ndms_pad;
-        D.ndm_tiles = ri.ndm_tiles;
-        D.stage_chans = ri.stage_chans;
-        D.row_words = ri.row_words;
-        D.widen_every = ri.widen_every;
     }
     BatchDevice bd;
-    const size_t db = b.subband ? hsb.size() * sizeof(SbBatchDesc) : hd.size() * sizeof(BatchDesc);
-    const size_t sb = hs.size() * sizeof(int64_t);
-    e = hipMalloc(&bd.descs, db + sb + 64);
+    e = hipMalloc(&bd.mem, img.size() + 256);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         dd::set_error(std::string("hipMalloc of the batch descriptors: ") + hipGetErrorString(e));
         return DD_ERR_NOMEM;
     }
-    bd.starts = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(bd.descs) + db);
-    e = hipMemcpy(bd.descs, b.subband ? static_cast<const void *>(hsb.data()) : hd.data(), db,
-                  hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(bd.starts, hs.data(), sb, hipMemcpyHostToDevice);
+    e = hipMemcpy(bd.mem, img.data(), img.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(bd.descs);
+        (void)hipFree(bd.mem);
         return hip_fail(e, "hipMemcpy of the batch descriptors");
     }
-    *out = &(st->per_device[dev] = bd);
+    for (size_t g = 0; g < b.groups.size(); ++g) {
+        bd.descs.push_back(static_cast<const char *>(bd.mem) + off_desc[g]);
+        bd.starts.push_back(
+            reinterpret_cast<const int64_t *>(static_cast<const char *>(bd.mem) + off_start[g]));
+    }
+    *out = &(st->per_device[dev] = std::move(bd));
     return DD_OK;
 }
 
@@ -1969,42 +1979,51 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
             return st;
     }
     int32_t *counters = reinterpret_cast<int32_t *>(d_ws);
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, counters, kXcds);
+    const int ncounters = int(b.groups.size()) * dd::kBatchQueues;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, stream, counters, ncounters);
     dd_status st = launch_check("k_reset_counters");
     if (st != DD_OK)
         return st;
-    QueueBounds qb;
-    for (int i = 0; i <= dd::kBatchQueues; ++i)
-        qb.b[i] = b.queue_bounds[i];
-    const void *fn = nullptr;
-    // Persistent workgroups per XCD: two 8-wave (or four 4-wave) per CU of
-    // its 32; variant 3 fills a CU's LDS with one workgroup.
-    unsigned per_xcd = unsigned(kPersistPerXcd * (8 / b.waves));
-    if (b.subband) {
-        fn = b.dm_tile == 192  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 12, 2>)
-             : b.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 8, 2>)
-             : b.dm_tile == 96  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 4>)
-                                : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
-        per_xcd = unsigned(kCusPerXcd);
-    } else if (b.waves == 4)
-        fn = b.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4>)
-                     : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4>);
-    else
-        fn = b.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8>)
-                     : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8>);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(dd::kMaxLdsBytes - 64));
-    const void *descs = bd.descs;
-    const int64_t *starts = bd.starts;
-    int ndesc = int(b.descs.size());
-    const char *ws = d_ws;
-    void *args[] = {&descs, &starts, &ndesc, &qb, &ws, &d_out, &counters};
-    const char *name = b.subband ? "k_dedisp_u8_sb_batch" : "k_dedisp_u8_batch";
-    hipError_t e = hipLaunchKernel(fn, dim3(kXcds * per_xcd), dim3(unsigned(b.waves * kWave)),
-                                   args, b.lds_bytes, stream);
-    if (e != hipSuccess)
-        return hip_fail(e, name);
-    return launch_check(name);
+    for (size_t g = 0; g < b.groups.size(); ++g) {
+        const dd::BatchGroup &G = b.groups[g];
+        QueueBounds qb;
+        for (int i = 0; i <= dd::kBatchQueues; ++i)
+            qb.b[i] = G.queue_bounds[i];
+        const void *fn = nullptr;
+        // Persistent workgroups per XCD: two 8-wave (or four 4-wave) per CU
+        // of its 32; variant 3 fills a CU's LDS with one workgroup.
+        unsigned per_xcd = unsigned(kPersistPerXcd * (8 / G.waves));
+        if (G.subband) {
+            fn = G.dm_tile == 192  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 12, 2>)
+                 : G.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 8, 2>)
+                 : G.dm_tile == 96  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 4>)
+                                    : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
+            per_xcd = unsigned(kCusPerXcd);
+        } else if (G.waves == 4) {
+            fn = G.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4>)
+                         : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4>);
+        } else {
+            fn = G.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8>)
+                         : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8>);
+        }
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dd::kMaxLdsBytes - 64));
+        const void *descs = bd.descs[g];
+        const int64_t *starts = bd.starts[g];
+        int ndesc = int(G.desc_end - G.desc_begin);
+        const char *ws = d_ws;
+        int32_t *cnt = counters + g * dd::kBatchQueues;
+        void *args[] = {&descs, &starts, &ndesc, &qb, &ws, &d_out, &cnt};
+        const char *name = G.subband ? "k_dedisp_u8_sb_batch" : "k_dedisp_u8_batch";
+        hipError_t e = hipLaunchKernel(fn, dim3(kXcds * per_xcd), dim3(unsigned(G.waves * kWave)),
+                                       args, G.lds_bytes, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, name);
+        st = launch_check(name);
+        if (st != DD_OK)
+            return st;
+    }
+    return DD_OK;
 }
 
 // Argument checks shared by the compute entry points (synchronous, before
@@ -2079,7 +2098,7 @@ void dd_batch_destroy(dd_batch *batch)
         const bool have_cur = hipGetDevice(&cur) == hipSuccess;
         for (auto &kv : st->per_device)
             if (hipSetDevice(kv.first) == hipSuccess)
-                (void)hipFree(kv.second.descs);
+                (void)hipFree(kv.second.mem);
         if (have_cur)
             (void)hipSetDevice(cur);
         delete st;

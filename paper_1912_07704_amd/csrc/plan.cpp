@@ -531,6 +531,110 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
     return DD_OK;
 }
 
+// Integer variants 1 and 2 (the direct sum): windows, stage width and the
+// per-DM offset tables.
+dd_status build_direct(Plan *p, int32_t want_stage, std::string *err)
+{
+    const int32_t nchans = p->nchans;
+    const int32_t nranges = int32_t(p->ranges.size());
+    const dd_dtype dtype = p->dtype;
+    const int32_t dmt = p->dm_tile;
+    // Tile strategy: a time tile of kTimeTile samples by a DM tile of
+    // kDmTile trials per workgroup.  Channels are staged in LDS in groups
+    // (double-buffered, two copies each), and the 16-bit partial sums are
+    // widened before 65535/(255*ds) channels have been added.
+    int64_t blocks = 0;
+    size_t lds = 0;
+    for (int32_t r = 0; r < nranges; ++r) {
+        RangeInfo &ri = p->ranges[r];
+        int32_t span = 0;
+        for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
+            const int32_t d1 = std::min(ri.ndms, d0 + dmt) - 1;
+            const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
+            const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d1) * nchans];
+            for (int32_t c = 0; c < nchans; ++c)
+                span = std::max(span, s1[c] - s0[c]);
+        }
+        ri.span = span;
+        const int32_t imax = 64 * kWaveWords + 2 + ((span + 1) >> 1);
+        ri.row_words = (imax + 2 + 3) / 4 * 4;
+        const int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
+        int32_t stage = std::max(1, std::min(want_stage > 0 ? want_stage : kMaxStageChans, cap));
+        if (stage > 1)
+            stage &= ~1;
+        auto bytes_for = [&](int32_t st) {
+            return size_t(16) * size_t(st) * size_t(ri.row_words);
+        };
+        // LDS per workgroup that still lets 16 wavefronts share a CU.
+        const size_t lds_target = kMaxLdsBytes * size_t(p->waves) / 16 - 1024;
+        while (stage > 1 && bytes_for(stage) > lds_target)
+            stage = stage > 2 ? stage - 2 : 1;
+        if (bytes_for(stage) > kMaxLdsBytes) {
+            *err = fmt("range ", r, ": delay spread ", span,
+                       " inside one DM tile needs more LDS than a workgroup has; use a "
+                       "finer DM step");
+            return DD_ERR_INVALID;
+        }
+        ri.stage_chans = stage;
+        ri.widen_every = std::max(1, cap / stage);
+        lds = std::max(lds, bytes_for(stage));
+        ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
+        ri.ndm_tiles = (ri.ndms + dmt - 1) / dmt;
+        ri.ndms_pad = ri.ndm_tiles * dmt;
+        ri.block_start = blocks;
+        blocks += ri.ntime_tiles * ri.ndm_tiles;
+    }
+    p->blocks = blocks;
+    p->lds_bytes = lds;
+
+    build_levels(p);
+
+    // Device tables of the integer kernel (see plan.h).
+    size_t noff = 0, nbase = 0;
+    for (RangeInfo &ri : p->ranges) {
+        ri.off_offset = noff;
+        ri.base_offset = nbase;
+        noff += size_t(nchans) * ri.ndms_pad;
+        nbase += size_t(nchans) * ri.ndm_tiles;
+    }
+    p->offT.assign(noff, 0);
+    p->baseT.assign(nbase, 0);
+    for (RangeInfo &ri : p->ranges) {
+        const int32_t copy_words = ri.stage_chans * ri.row_words;
+        parallel_for(nchans, ri.ndms_pad, [&](int64_t c0, int64_t c1) {
+        for (int32_t c = int32_t(c0); c < int32_t(c1); ++c) {
+            int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
+            for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile) {
+                const int32_t b = p->shifts[size_t(ri.dm_index + tile * dmt) * nchans + c];
+                const int32_t par = b & 1;
+                const int32_t e = ((b - par) / 2) & 3;
+                p->baseT[ri.base_offset + size_t(tile) * nchans + c] = (b - par) / 2 - e;
+                for (int32_t d = tile * dmt; d < (tile + 1) * dmt; ++d) {
+                    const int32_t dv = std::min(d, ri.ndms - 1);
+                    const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] - b;
+                    off[d] = ((o + par) & 1) * copy_words + e + ((o + par) >> 1);
+                }
+            }
+        }
+        });
+    }
+    return DD_OK;
+}
+
+// Drops what a failed variant-3 attempt left in a plan.
+void reset_subband(Plan *p)
+{
+    p->qcntT.clear();
+    p->qoffT.clear();
+    p->offCT.clear();
+    p->baseT.clear();
+    for (RangeInfo &ri : p->ranges) {
+        ri.sb_spread = ri.sb_chans = ri.sb_nsub = ri.sb_jmax = ri.sb_span = 0;
+        ri.sb_qwords = ri.sb_nslot = ri.sb_tb_words = 0;
+        ri.sb_q_offset = ri.sb_n_offset = ri.sb_c_offset = 0;
+    }
+}
+
 dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t nsamp,
                      const dd_range *ranges, int32_t nranges, dd_dtype dtype,
                      const dd_options *opts, Plan *p, std::string *err)
@@ -542,12 +646,16 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         *err = "options: variant must be 0 to 3 and stage_chans >= 0";
         return DD_ERR_INVALID;
     }
+    const bool direct_tile = want_dm_tile == 32 || want_dm_tile == 64;
+    const bool sb_tile = want_dm_tile == 64 || want_dm_tile == 96 || want_dm_tile == 128 ||
+                         want_dm_tile == 192;
     const bool tile_ok = want_dm_tile == 0 ||
-                         (want_variant == 3 ? (want_dm_tile == 64 || want_dm_tile == 96 ||
-                                               want_dm_tile == 128 || want_dm_tile == 192)
-                                            : (want_dm_tile == 32 || want_dm_tile == 64));
+                         (want_variant == 3   ? sb_tile
+                          : want_variant == 0 ? direct_tile || sb_tile
+                                              : direct_tile);
     if (!tile_ok) {
-        *err = "options: dm_tile must be 32 or 64 (variants 1, 2) or 64, 96, 128 or 192 (variant 3)";
+        *err = "options: dm_tile must be 32 or 64 (variants 1, 2), 64, 96, 128 or 192 (variant 3), "
+               "or any of these (variant 0)";
         return DD_ERR_INVALID;
     }
     if (want_variant == 3 && dtype != DD_U8) {
@@ -692,96 +800,41 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         }
         p->out_elems = out_off;
 
-        p->dedup = want_variant == 2;
-        p->subband = want_variant == 3;
-        p->dm_tile = want_dm_tile ? want_dm_tile : (p->subband ? 3 * kDmTile : kDmTile);
-        p->waves = p->dm_tile / kDmPerWave;
-        p->time_tile = kTimeTile;
-        const int32_t dmt = p->dm_tile;
-        if (dtype == DD_F32)
+        if (dtype == DD_F32) {
+            p->dm_tile = kDmTile;
+            p->waves = kWaves;
+            p->time_tile = kTimeTile;
             return build_f32(p, want_stage, err);
-        if (p->subband)
-            return build_subband(p, want_stage, err);
-
-        // Tile strategy: a time tile of kTimeTile samples by a DM tile of
-        // kDmTile trials per workgroup.  Channels are staged in LDS in groups
-        // (double-buffered, two copies each), and the 16-bit partial sums are
-        // widened before 65535/(255*ds) channels have been added.
-        int64_t blocks = 0;
-        size_t lds = 0;
-        for (int32_t r = 0; r < nranges; ++r) {
-            RangeInfo &ri = p->ranges[r];
-            int32_t span = 0;
-            for (int32_t d0 = 0; d0 < ri.ndms; d0 += dmt) {
-                const int32_t d1 = std::min(ri.ndms, d0 + dmt) - 1;
-                const int32_t *s0 = &p->shifts[size_t(ri.dm_index + d0) * nchans];
-                const int32_t *s1 = &p->shifts[size_t(ri.dm_index + d1) * nchans];
-                for (int32_t c = 0; c < nchans; ++c)
-                    span = std::max(span, s1[c] - s0[c]);
-            }
-            ri.span = span;
-            const int32_t imax = 64 * kWaveWords + 2 + ((span + 1) >> 1);
-            ri.row_words = (imax + 2 + 3) / 4 * 4;
-            const int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
-            int32_t stage = std::max(1, std::min(want_stage > 0 ? want_stage : kMaxStageChans, cap));
-            if (stage > 1)
-                stage &= ~1;
-            auto bytes_for = [&](int32_t st) {
-                return size_t(16) * size_t(st) * size_t(ri.row_words);
-            };
-            // LDS per workgroup that still lets 16 wavefronts share a CU.
-            const size_t lds_target = kMaxLdsBytes * size_t(p->waves) / 16 - 1024;
-            while (stage > 1 && bytes_for(stage) > lds_target)
-                stage = stage > 2 ? stage - 2 : 1;
-            if (bytes_for(stage) > kMaxLdsBytes) {
-                *err = fmt("range ", r, ": delay spread ", span,
-                           " inside one DM tile needs more LDS than a workgroup has; use a "
-                           "finer DM step");
-                return DD_ERR_INVALID;
-            }
-            ri.stage_chans = stage;
-            ri.widen_every = std::max(1, cap / stage);
-            lds = std::max(lds, bytes_for(stage));
-            ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
-            ri.ndm_tiles = (ri.ndms + dmt - 1) / dmt;
-            ri.ndms_pad = ri.ndm_tiles * dmt;
-            ri.block_start = blocks;
-            blocks += ri.ntime_tiles * ri.ndm_tiles;
         }
-        p->blocks = blocks;
-        p->lds_bytes = lds;
-
-        build_levels(p);
-
-        // Device tables of the integer kernel (see plan.h).
-        size_t noff = 0, nbase = 0;
-        for (RangeInfo &ri : p->ranges) {
-            ri.off_offset = noff;
-            ri.base_offset = nbase;
-            noff += size_t(nchans) * ri.ndms_pad;
-            nbase += size_t(nchans) * ri.ndm_tiles;
-        }
-        p->offT.assign(noff, 0);
-        p->baseT.assign(nbase, 0);
-        for (RangeInfo &ri : p->ranges) {
-            const int32_t copy_words = ri.stage_chans * ri.row_words;
-            parallel_for(nchans, ri.ndms_pad, [&](int64_t c0, int64_t c1) {
-            for (int32_t c = int32_t(c0); c < int32_t(c1); ++c) {
-                int32_t *off = &p->offT[ri.off_offset + size_t(c) * ri.ndms_pad];
-                for (int32_t tile = 0; tile < ri.ndm_tiles; ++tile) {
-                    const int32_t b = p->shifts[size_t(ri.dm_index + tile * dmt) * nchans + c];
-                    const int32_t par = b & 1;
-                    const int32_t e = ((b - par) / 2) & 3;
-                    p->baseT[ri.base_offset + size_t(tile) * nchans + c] = (b - par) / 2 - e;
-                    for (int32_t d = tile * dmt; d < (tile + 1) * dmt; ++d) {
-                        const int32_t dv = std::min(d, ri.ndms - 1);
-                        const int32_t o = p->shifts[size_t(ri.dm_index + dv) * nchans + c] - b;
-                        off[d] = ((o + par) & 1) * copy_words + e + ((o + par) >> 1);
-                    }
-                }
+        auto use = [&](int32_t variant, int32_t dm_tile, std::string *e) {
+            p->dedup = variant == 2;
+            p->subband = variant == 3;
+            p->dm_tile = dm_tile;
+            p->waves = dm_tile / kDmPerWave;
+            p->time_tile = kTimeTile;
+            return p->subband ? build_subband(p, want_stage, e) : build_direct(p, want_stage, e);
+        };
+        if (want_variant != 0)
+            return use(want_variant,
+                       want_dm_tile ? want_dm_tile : (want_variant == 3 ? 3 * kDmTile : kDmTile), err);
+        // Variant 0: exact sub-band reuse (192-DM tiles, then 128) when the
+        // plan's delay patterns fit the LDS, else the direct kernel.
+        std::vector<int32_t> tiles;
+        if (want_dm_tile == 0)
+            tiles = {3 * kDmTile, 2 * kDmTile};
+        else if (want_dm_tile != kDmTile / 2)
+            tiles = {want_dm_tile};
+        for (int32_t t : tiles) {
+            std::string e;
+            const dd_status st = use(3, t, &e);
+            if (st != DD_ERR_INVALID) {
+                if (st != DD_OK)
+                    *err = e;
+                return st;
             }
-            });
         }
+        reset_subband(p);
+        return use(1, want_dm_tile == kDmTile / 2 ? want_dm_tile : kDmTile, err);
     } catch (const std::bad_alloc &) {
         *err = "host allocation failed";
         return DD_ERR_NOMEM;

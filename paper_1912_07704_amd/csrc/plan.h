@@ -205,16 +205,31 @@ void *new_batch_device_state();
 void set_error(const std::string &msg);
 void clear_error();
 
-// A batch of integer plans (beams) summed by one persistent launch.  Inputs
-// and outputs of all beams share one buffer each, at fixed offsets.
+// A batch of integer plans (beams) summed by persistent launches, one per
+// group of plans that share a kernel (variant family, DM tile).  Inputs and
+// outputs of all beams share one buffer each, at fixed offsets.
 struct BatchDescHost {
     int32_t beam = 0;
     int32_t range = 0;
-    int64_t item_start = 0;      // first work item of this (beam, range)
+    int64_t item_start = 0;      // first work item of this (beam, range) within its group
     int64_t nitems = 0;          // time tiles x DM tiles
 };
 
 constexpr int kBatchQueues = 8;                // one work queue per XCD
+constexpr int kBatchMaxGroups = 8;             // kernels per batch
+
+struct BatchGroup {
+    bool subband = false;                  // variant 3 (else the direct kernel)
+    bool dedup = false;                    // direct kernel: variant 2
+    int32_t dm_tile = kDmTile;
+    int32_t waves = kWaves;
+    size_t lds_bytes = 0;
+    size_t desc_begin = 0, desc_end = 0;   // its (beam, range) descriptors in Batch::descs
+    int64_t nitems = 0;
+    // XCD x's queue holds items [queue_bounds[x], queue_bounds[x+1]): equal
+    // shares of the group's cost (items weigh their beam's channel count)
+    int64_t queue_bounds[kBatchQueues + 1] = {};
+};
 
 struct Batch {
     std::vector<const Plan *> plans;       // not owned
@@ -224,20 +239,15 @@ struct Batch {
     int64_t in_bytes = 0;
     int64_t out_elems = 0;
     size_t ws_bytes = 0;
-    std::vector<BatchDescHost> descs;      // most expensive items first
-    int64_t nitems = 0;
-    // XCD x's queue holds items [queue_bounds[x], queue_bounds[x+1]): equal
-    // shares of the cost (items weigh their beam's channel count)
-    int64_t queue_bounds[kBatchQueues + 1] = {};
-    size_t lds_bytes = 0;
-    bool dedup = true;
-    bool subband = false;                  // variant 3 plans, all with one DM tile
-    int32_t waves = kWaves;
-    int32_t dm_tile = kDmTile;
+    std::vector<BatchDescHost> descs;      // by group, most expensive items first in each
+    std::vector<BatchGroup> groups;
+    int64_t nitems = 0;                    // all groups
     void *device = nullptr;
 };
 
-constexpr size_t kBatchCounterBytes = 256;     // queue counters at the start of the workspace
+constexpr size_t kBatchCounterBytes = 256;     // queue counters (kBatchQueues per group) at the
+                                               // start of the workspace
+static_assert(kBatchCounterBytes >= sizeof(int32_t) * kBatchQueues * kBatchMaxGroups, "counters");
 
 // Streaming over a long series in chunks of the plan's nsamp samples.
 // Consecutive chunks start `step` samples apart; step is the largest

@@ -34,9 +34,11 @@ def small_beams(seed, n, subband=False):
     return beams
 
 
-# direct kernel (library default) and variant 3 at each of its workgroup shapes
-STRATEGIES = {"direct": {}, "v3-192": {"variant": 3}, "v3-128": {"variant": 3, "dm_tile": 128},
-              "v3-96": {"variant": 3, "dm_tile": 96}}
+# the library default (each plan's own choice: beams of one batch may run
+# different kernels, one persistent launch per kernel), the direct kernel,
+# and variant 3 at each of its workgroup shapes
+STRATEGIES = {"auto": {}, "direct": {"variant": 1}, "v3-192": {"variant": 3},
+              "v3-128": {"variant": 3, "dm_tile": 128}, "v3-96": {"variant": 3, "dm_tile": 96}}
 
 
 def make_plans(beams, opts):
@@ -45,7 +47,7 @@ def make_plans(beams, opts):
 
 @pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 def test_small_batch_matches_single_plans_and_oracle(strategy):
-    beams = small_beams(0, 7, strategy != "direct")
+    beams = small_beams(0, 7, strategy.startswith("v3"))
     say("small batch", strategy, [b[0].shape for b in beams])
     plans = make_plans(beams, STRATEGIES[strategy])
     batch = dd.Batch(plans)
@@ -59,9 +61,9 @@ def test_small_batch_matches_single_plans_and_oracle(strategy):
         assert np.array_equal(o.cpu().numpy(), cref.dedisperse_u8(x, f, t, r))
 
 
-@pytest.mark.parametrize("strategy", ["direct", "v3-192"])
+@pytest.mark.parametrize("strategy", ["auto", "direct", "v3-192"])
 def test_batch_graph_replay(strategy):
-    beams = small_beams(1, 5, strategy != "direct")
+    beams = small_beams(1, 5, strategy.startswith("v3"))
     say("graph replay", strategy)
     plans = make_plans(beams, STRATEGIES[strategy])
     batch = dd.Batch(plans)

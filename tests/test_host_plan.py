@@ -220,7 +220,8 @@ def test_subband_variant_strategy():
 
 
 @pytest.mark.parametrize("opts", [dict(variant=3, dm_tile=32), dict(variant=1, dm_tile=128),
-                                  dict(variant=2, dm_tile=96), dict(variant=4)])
+                                  dict(variant=2, dm_tile=96), dict(variant=4),
+                                  dict(variant=0, dm_tile=48)])
 def test_subband_option_errors(opts):
     w = synth.tiny()
     with pytest.raises(dd.DDError) as e:
@@ -228,9 +229,10 @@ def test_subband_option_errors(opts):
     assert e.value.status == -2
 
 
-def test_subband_variant_is_integer_only_and_batches_keep_one_kernel():
-    """Variant 3 is DD_U8 only.  A batch holds variant 3 plans of one DM
-    tile, or direct-kernel plans (variants 1 and 2) of one DM tile."""
+def test_subband_variant_is_integer_only_and_batches_mix_kernels():
+    """Variant 3 is DD_U8 only.  A batch may mix kernels (variant family and
+    DM tile): each kernel's plans form one group of work items, summed by
+    their own persistent launch."""
     w = synth.tiny()
     with pytest.raises(dd.DDError) as e:
         dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
@@ -240,17 +242,40 @@ def test_subband_variant_is_integer_only_and_batches_keep_one_kernel():
     p3_128 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3, dm_tile=128)
     p1 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=1)
     p2 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=2)
-    b = dd.Batch([p3, p3b])
+
     def items(p):
         tt, dt = p.strategy["time_tile"], p.strategy["dm_tile"]
         return sum(-(-r.nout // tt) * -(-r.ndms // dt) for r in p.ranges)
 
-    assert b.work_items == items(p3) + items(p3b)
-    dd.Batch([p1, p2])
-    for mix in ([p3, p1], [p1, p3], [p3, p3_128]):
-        with pytest.raises(dd.DDError) as e:
-            dd.Batch(mix)
-        assert e.value.status == -2 and "DM tile" in str(e.value)
+    for mix in ([p3, p3b], [p1, p2], [p3, p1], [p1, p3, p3_128, p2, p3b]):
+        b = dd.Batch(mix)
+        assert b.work_items == sum(items(p) for p in mix)
+        b.close()
+
+
+def test_default_strategy_prefers_exact_subband_reuse():
+    """Variant 0 (the default) takes exact sub-band reuse at 192-DM tiles
+    when the plan's delay patterns fit the LDS, else 128-DM tiles, else the
+    direct kernel at 64-DM tiles; a requested DM tile is kept."""
+    w = synth.ska_single_beam()
+    s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges).strategy
+    assert (s["variant"], s["dm_tile"], s["time_tile"]) == (3, 192, 256)
+    s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, dm_tile=96).strategy
+    assert (s["variant"], s["dm_tile"], s["time_tile"]) == (3, 96, 512)
+    s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, dm_tile=32).strategy
+    assert (s["variant"], s["dm_tile"]) == (1, 32)
+    # 1024 wide channels at 128 us, DM step 1: too many delay patterns for
+    # the LDS at any sub-band tile
+    d = synth.differentiable()
+    with pytest.raises(dd.DDError):
+        dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3)
+    with pytest.raises(dd.DDError):
+        dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3, dm_tile=128)
+    p = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8")
+    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (1, 64)
+    assert p.shifts().shape == (512, 1024)
+    s = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", dm_tile=192).strategy
+    assert (s["variant"], s["dm_tile"]) == (1, 64)
 
 
 def test_subband_variant_rejects_plans_beyond_the_lds():
