@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <sstream>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -47,13 +49,31 @@ void parallel_for(int64_t n, int64_t work_per_item, F fn)
             fn(int64_t(0), n);
         return;
     }
+    // a slice's exception (an allocation failure) is rethrown here after
+    // every thread has joined
+    std::vector<std::exception_ptr> fail(static_cast<size_t>(nt));
+    auto run = [&](int64_t k) {
+        try {
+            fn(n * k / nt, n * (k + 1) / nt);
+        } catch (...) {
+            fail[size_t(k)] = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
     th.reserve(size_t(nt - 1));
-    for (int64_t k = 1; k < nt; ++k)
-        th.emplace_back(fn, n * k / nt, n * (k + 1) / nt);
-    fn(int64_t(0), n / nt);
+    for (int64_t k = 1; k < nt; ++k) {
+        try {
+            th.emplace_back(run, k);
+        } catch (const std::system_error &) {
+            run(k);                                  // no thread to spare: this one does it
+        }
+    }
+    run(0);
     for (std::thread &t : th)
         t.join();
+    for (const std::exception_ptr &e : fail)
+        if (e)
+            std::rethrow_exception(e);
 }
 
 
