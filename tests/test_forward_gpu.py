@@ -23,8 +23,13 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
-def gpu_forward(x, freqs, tsamp, ranges, out_extra=0, canary=-123456789):
-    plan = dd.Plan(freqs, tsamp, x.shape[1], ranges)
+# the library default (variant 3 where its patterns fit the LDS, else the
+# direct kernel) and both direct variants
+STRATEGIES = {"default": {}, "v1": {"variant": 1}, "v2": {"variant": 2}}
+
+
+def gpu_forward(x, freqs, tsamp, ranges, out_extra=0, canary=-123456789, opts=None):
+    plan = dd.Plan(freqs, tsamp, x.shape[1], ranges, **(opts or {}))
     xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     out = torch.full((plan.out_elems + out_extra,), canary, dtype=torch.int32, device="cuda")
     dd.dedisperse(xt, plan, out=out)
@@ -32,11 +37,19 @@ def gpu_forward(x, freqs, tsamp, ranges, out_extra=0, canary=-123456789):
     return out.cpu().numpy(), plan
 
 
+_ORACLE = {}
+
+
 def oracle_flat(x, freqs, tsamp, ranges):
-    if x.shape[0] * x.shape[1] <= 2_000_000 and len(ranges) <= 3:
-        outs, _ = O.dedisperse(x, freqs, tsamp, ranges)
-        return O.concat(outs)
-    return cref.dedisperse_u8(x, freqs, tsamp, ranges).astype(np.int64)
+    key = (x.shape, x.tobytes().__hash__(), tuple(np.asarray(freqs).tolist()), tsamp,
+           tuple(map(tuple, ranges)))
+    if key not in _ORACLE:
+        if x.shape[0] * x.shape[1] <= 2_000_000 and len(ranges) <= 3:
+            outs, _ = O.dedisperse(x, freqs, tsamp, ranges)
+            _ORACLE[key] = O.concat(outs)
+        else:
+            _ORACLE[key] = cref.dedisperse_u8(x, freqs, tsamp, ranges).astype(np.int64)
+    return _ORACLE[key]
 
 
 def test_tiny_workload_bit_exact():
@@ -76,11 +89,12 @@ def random_case(seed):
         return x, freqs, tsamp, ranges
 
 
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 @pytest.mark.parametrize("seed", range(16))
-def test_random_shapes_bit_exact(seed):
+def test_random_shapes_bit_exact(seed, strategy):
     x, freqs, tsamp, ranges = random_case(seed)
-    say("random", seed, x.shape, ranges)
-    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=64)
+    say("random", seed, strategy, x.shape, ranges)
+    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=64, opts=STRATEGIES[strategy])
     assert np.array_equal(got[: plan.out_elems], oracle_flat(x, freqs, tsamp, ranges))
     assert (got[plan.out_elems:] == -123456789).all()
 
@@ -102,8 +116,9 @@ EDGES = {
 }
 
 
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 @pytest.mark.parametrize("name", sorted(EDGES))
-def test_edge_cases_bit_exact(name):
+def test_edge_cases_bit_exact(name, strategy):
     nch, nsamp, ranges = EDGES[name]
     freqs = synth.band_freqs(1500.0, 1200.0, nch) if nch > 1 else np.array([1400.0])
     tsamp = 1e-3
@@ -117,23 +132,24 @@ def test_edge_cases_bit_exact(name):
     x = rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8)
     if name == "downsample_256":
         x[:] = 255                               # the largest binned value, 255*256
-    say("edge", name, x.shape, ranges)
-    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=8)
+    say("edge", name, strategy, x.shape, ranges)
+    got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=8, opts=STRATEGIES[strategy])
     want = oracle_flat(x, freqs, tsamp, ranges)
     assert np.array_equal(got[: plan.out_elems], want)
     if name == "single_dm_single_sample":
         assert plan.out_elems == 1
 
 
-def test_all_255_and_all_zero_extremes():
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
+def test_all_255_and_all_zero_extremes(strategy):
     """Saturated input: every sum reaches its bound (255*nchans*ds) without a
     carry between the packed 16-bit halves."""
     freqs = synth.band_freqs(1670.0, 1370.0, 1024)
     ranges = [(0.0, 40.0, 1.0, 1), (40.0, 80.0, 2.0, 16)]
     for val in (255, 0):
         x = np.full((1024, 8192), val, dtype=np.uint8)
-        say("extreme", val)
-        got, plan = gpu_forward(x, freqs, 64e-6, ranges)
+        say("extreme", val, strategy)
+        got, plan = gpu_forward(x, freqs, 64e-6, ranges, opts=STRATEGIES[strategy])
         outs = plan.split(got)
         assert (outs[0] == 255 * 1024 * (val // 255)).all()
         assert (outs[1] == 255 * 1024 * 16 * (val // 255)).all()
