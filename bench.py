@@ -131,7 +131,7 @@ def leg_fwdbwd(dd, synth, torch, plain_value):
 
 
 def leg_batched(dd, synth, torch, plain_value, opts):
-    """64 uint8 beams of uneven shape in one persistent launch (inputs drawn
+    """64 uint8 beams of uneven shape in one persistent launch per kernel (inputs drawn
     on the GPU, excluded from timing)."""
     wls = synth.batched_beams()
     log("leg batched:", len(wls), "beams")
@@ -155,7 +155,8 @@ def leg_batched(dd, synth, torch, plain_value, opts):
                        "500/1000/2000", "ms": ms, "dm_trial_samples": samples,
            "dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
            "strategy": plans[0].strategy,
-           "work_items": batch.work_items, "launches": "bins per beam + 1 persistent"}
+           "work_items": batch.work_items, "launches": "bins per beam + %d persistent" % len(
+               {(p.strategy["variant"], p.strategy["dm_tile"]) for p in plans})}
     del xin, out, ws
     batch.close()
     return res

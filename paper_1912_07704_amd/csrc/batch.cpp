@@ -1,6 +1,6 @@
-// Host core of the batched integer forward: buffer layout of the beams and
-// the order of the persistent launch's work items (most expensive first, so
-// the queue drains evenly).  Plain C++, no HIP.
+// Host core of the batched integer forward: buffer layout of the beams, the
+// kernel groups, and the order of each group's work items (most expensive
+// first, so the queues drain evenly).  Plain C++, no HIP.
 #include <algorithm>
 #include <cmath>
 #include <new>

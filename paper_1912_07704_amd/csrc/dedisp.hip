@@ -1147,12 +1147,13 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const float *__restrict__ p
 
 
 // ---------------------------------------------------------------------------
-// Batched integer forward: one persistent launch over the work items of
-// many beams.  Item L of the cost-ordered list belongs to the descriptor
-// whose item_start is the largest not above L.  The list is cut into one
-// contiguous queue per XCD; a workgroup dealt to XCD x takes its next item
-// from queue x (a counter in the workspace, reset by k_reset_counters
-// before the launch), so the tiles of a time tile still share an L2.
+// Batched integer forward: one persistent launch per kernel group over the
+// work items of its beams.  Item L of the group's cost-ordered list belongs
+// to the descriptor whose item_start is the largest not above L.  The list
+// is cut into one contiguous queue per XCD of equal cost; a workgroup dealt
+// to XCD x takes its next item from queue x (a counter in the workspace,
+// reset by k_reset_counters before the launches), so the tiles of a time
+// tile still share an L2.
 // ---------------------------------------------------------------------------
 
 struct BatchDesc {
@@ -1235,7 +1236,7 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
     }
 }
 
-// Variant 3 in the same persistent launch: each (beam, range) carries its
+// Variant 3 in a persistent launch of its own: each (beam, range) carries its
 // whole sub-band range; the workspace and output pointers are the launch's
 // own buffers plus the descriptor's offsets.
 struct SbBatchDesc {

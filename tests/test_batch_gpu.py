@@ -1,6 +1,6 @@
-"""Batched integer forward: one persistent launch over many beams of uneven
-shape (direct kernel or variant 3), bit-exact against each beam's own
-forward and the oracle, and replayable from a HIP graph."""
+"""Batched integer forward: persistent launches (one per kernel) over many
+beams of uneven shape (direct kernel, variant 3 or both), bit-exact against
+each beam's own forward and the oracle, and replayable from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -105,7 +105,7 @@ def test_batch_graph_replay(strategy):
 def test_batched_beams_full_size(strategy):
     """The 64-beam batched workload (channel counts 1024/2048/4096, lengths
     2^16..2^18, DM max 500/1000/2000), drawn on the GPU: every beam of the
-    one persistent launch equals its own dd_forward, and sampled outputs of
+    batch equals its own dd_forward, and sampled outputs of
     three beams equal the oracle."""
     wls = synth.batched_beams()
     say("batched beams: plans", strategy)
