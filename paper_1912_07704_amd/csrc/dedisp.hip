@@ -50,6 +50,26 @@ __device__ __forceinline__ sgpr8 table8(const int32_t *p)
     return v;
 }
 
+// Two rows' worth of four table entries (row p and row q), one wait.
+typedef int sgpr4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void table4x2(const int32_t *p, const int32_t *q, sgpr4 &u, sgpr4 &v)
+{
+    // (the halves as unsigned 32-bit values: readfirstlane returns int,
+    // and a sign-extended low half would corrupt the high one)
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint64_t b = reinterpret_cast<uint64_t>(q);
+    const uint32_t alo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t ahi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    const uint32_t blo = __builtin_amdgcn_readfirstlane(uint32_t(b));
+    const uint32_t bhi = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32));
+    const uint64_t pa = (uint64_t(ahi) << 32) | alo;
+    const uint64_t pb = (uint64_t(bhi) << 32) | blo;
+    asm volatile("s_load_dwordx4 %0, %2, 0x0\n\ts_load_dwordx4 %1, %3, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&s"(u), "=&s"(v)
+                 : "s"(pa), "s"(pb));
+}
+
 __device__ __forceinline__ int32_t table1(const int32_t *p)
 {
     const uint64_t a = reinterpret_cast<uint64_t>(p);
@@ -864,7 +884,9 @@ __device__ __forceinline__ void stage_issue_f32(const SumArgs &R, int tile, int6
         const int part = i - j * ipr;
         const int q = part * kWave + lane;
         const int64_t b = bs + j;
-        const int32_t m = R.base[int64_t(tile) * R.nrows + b];
+        // (a scalar load: a vector load's wait would also wait for the
+        // staging loads in flight)
+        const int32_t m = table1(R.base + int64_t(tile) * R.nrows + b);
         if (q < chunks) {
             const float *g = R.src + b * R.pitch + t0 + m + 4 * q;
             __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
@@ -942,14 +964,15 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                             wave, lane);
         }
         for (int jp = 0; jp < bn; jp += 2) {
-            static_assert(kFP == 4, "offsets are loaded as one int4 per row");
+            static_assert(kFP == 4, "offsets are loaded as four ints per row");
+            // the two rows' offsets by scalar loads (a last unpaired row
+            // reads its own offsets twice)
             const int32_t *oa = R.off + int64_t(b0 + jp) * npad + aw0;
-            const int4 a0 = *reinterpret_cast<const int4 *>(oa);
+            sgpr4 a0, b0v;
+            table4x2(oa, oa + (jp + 1 < bn ? npad : 0), a0, b0v);
             const int offa[kFP] = {a0.x, a0.y, a0.z, a0.w};
             const float *rowa = A + jp * Wr + lane;
             if (jp + 1 < bn) {
-                const int32_t *ob = oa + npad;
-                const int4 b0v = *reinterpret_cast<const int4 *>(ob);
                 const int offb[kFP] = {b0v.x, b0v.y, b0v.z, b0v.w};
                 const float *rowb = rowa + Wr;
 #pragma unroll
