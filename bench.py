@@ -135,7 +135,7 @@ def leg_batched(dd, synth, torch, plain_value, opts):
     on the GPU, excluded from timing)."""
     wls = synth.batched_beams()
     log("leg batched:", len(wls), "beams")
-    # the single beam's tuned strategy (a batch holds plans of one kernel)
+    # the single beam's tuned strategy for every beam
     o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile", "stage_chans")}
     plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **o) for w in wls]
     batch = dd.Batch(plans)
