@@ -87,11 +87,21 @@ def cpu_baseline(w, x, target_s: float):
     t = time.perf_counter()
     cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n, nout)
     dt = time.perf_counter() - t
+    # the same oracle on one thread, over a few DM trials (about 3 s)
+    t = time.perf_counter()
+    cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, 1, nout, threads=1)
+    n1 = int(min(len(plan[0].dms), max(1, 3.0 / max(time.perf_counter() - t, 1e-3))))
+    t = time.perf_counter()
+    cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n1, nout, threads=1)
+    dt1 = time.perf_counter() - t
     return {"value": n * nout / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "seconds": round(dt, 3),
             "sample": (f"DM trials 0..{n - 1} of the native-resolution range (DM 0-150 step "
                        f"0.1), all {w.nchans} channels, all {nout} output samples; plain C "
-                       f"oracle, OpenMP over DM trials")}
+                       f"oracle, OpenMP over DM trials"),
+            "single_thread_value": n1 * nout / dt1,
+            "single_thread_sample": f"DM trials 0..{n1 - 1} of the same range on 1 thread "
+                                    f"({dt1:.2f} s)"}
 
 
 def _time(torch, fn, n):
