@@ -699,17 +699,28 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
             else
                 qrow<NW + 1, false>(A, ov, min(K, nchans - (c0 + s * K)), qe, Wq, lane);
         }
-        // Every window, both copies and this stage's tables are in LDS (the
-        // previous stage's sums finished before this stage's first
-        // barrier): start the next stage's loads.
-        if (st + 1 < nst) {
-            const int cs = c0 + C;
-            rows_issue<WAVES, false>(R, src, T + 4, t0, cs, min(C, nchans - cs),
-                                     lds + ((st + 1) & 1) * (2 * CW), wave, lane);
-            tables_issue<WAVES, DT>(R, tile, st + 1, st + 2 < nst ? R.nslot : nsb_last,
-                                    Tb + ((st + 1) & 1) * R.tb_words, wave, lane);
-        }
+        // The next stage's loads go to the other buffers, whose last readers
+        // (the previous stage's sums) finished before this stage's first
+        // barrier.  At 192-DM tiles they are issued once every pattern row
+        // is built and fly while this stage's (long) sums run: issued
+        // earlier, their LDS writes compete with the rows' reads.  At the
+        // smaller tiles the sums are too short to cover them, and each
+        // wavefront issues its own right after its rows (measured).
+        auto issue_next = [&]() {
+            if (st + 1 < nst) {
+                const int cs = c0 + C;
+                rows_issue<WAVES, false>(R, src, T + 4, t0, cs, min(C, nchans - cs),
+                                         lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+                tables_issue<WAVES, DT>(R, tile, st + 1, st + 2 < nst ? R.nslot : nsb_last,
+                                        Tb + ((st + 1) & 1) * R.tb_words, wave, lane);
+            }
+        };
+        constexpr bool issue_after = WAVES == 16 && DPW == 12;
+        if constexpr (!issue_after)
+            issue_next();
         lds_barrier();
+        if constexpr (issue_after)
+            issue_next();
 
         // One pattern-row word per DM, sub-band and sample pair.
         const uint32_t *rowq = Q + lane;
