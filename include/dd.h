@@ -323,6 +323,13 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
  *                   Any pointer may be NULL.
  * dd_batch_beam     byte offset of beam b's input and element offset of its
  *                   output (both 256-byte aligned).
+ * dd_batch_groups   the number of kernel groups (one persistent launch each).
+ * dd_batch_group    group g's kernel (variant 1, 2 or 3 and DM tile), its
+ *                   work items, and the bounds of its per-XCD queues:
+ *                   queue x holds items [queue_bounds[x], queue_bounds[x+1])
+ *                   of the group (queue_bounds: 9 int64, or NULL).  Any
+ *                   other pointer may be NULL; DD_ERR_INVALID for g out of
+ *                   range.
  * dd_batch_prepare  upload the batch's and its plans' device tables to the
  *                   current device.
  * dd_batch_forward  d_in: batch input (256-byte aligned); d_out: int32,
@@ -336,6 +343,9 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t nbeams, dd_batch 
 void dd_batch_destroy(dd_batch *batch);
 dd_status dd_batch_info(const dd_batch *batch, int64_t *in_bytes, int64_t *out_elems,
                         size_t *ws_bytes, int64_t *work_items);
+dd_status dd_batch_groups(const dd_batch *batch, int32_t *ngroups);
+dd_status dd_batch_group(const dd_batch *batch, int32_t g, int32_t *variant, int32_t *dm_tile,
+                         int64_t *work_items, int64_t *queue_bounds);
 dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
                         int64_t *out_offset);
 dd_status dd_batch_prepare(dd_batch *batch);

@@ -154,6 +154,16 @@ class Batch:
             check(L.dd_batch_beam(self._h, b, ctypes.byref(io), ctypes.byref(oo)), "dd_batch_beam")
             self.in_offsets.append(io.value)
             self.out_offsets.append(oo.value)
+        ng = ctypes.c_int32()
+        check(L.dd_batch_groups(self._h, ctypes.byref(ng)), "dd_batch_groups")
+        self.groups = []
+        for g in range(ng.value):
+            va, dt, wi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            qb = (ctypes.c_int64 * 9)()
+            check(L.dd_batch_group(self._h, g, ctypes.byref(va), ctypes.byref(dt),
+                                   ctypes.byref(wi), qb), "dd_batch_group")
+            self.groups.append({"variant": va.value, "dm_tile": dt.value,
+                                "work_items": wi.value, "queue_bounds": list(qb)})
 
     @property
     def handle(self):

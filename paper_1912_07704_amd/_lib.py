@@ -32,6 +32,8 @@ SIGNATURES = {
     "dd_batch_destroy": (None, [P]),
     "dd_batch_info": (ctypes.c_int, [P, P, P, P, P]),
     "dd_batch_beam": (ctypes.c_int, [P, I32, P, P]),
+    "dd_batch_groups": (ctypes.c_int, [P, P]),
+    "dd_batch_group": (ctypes.c_int, [P, I32, P, P, P, P]),
     "dd_batch_prepare": (ctypes.c_int, [P]),
     "dd_batch_forward": (ctypes.c_int, [P, P, P, I64, P, SZ, P]),
     "dd_stream_create": (ctypes.c_int, [P, I32, P]),

@@ -240,6 +240,42 @@ dd_status dd_batch_info(const dd_batch *batch, int64_t *in_bytes, int64_t *out_e
     return DD_OK;
 }
 
+dd_status dd_batch_groups(const dd_batch *batch, int32_t *ngroups)
+{
+    clear_error();
+    if (!batch || !ngroups) {
+        set_error("batch and ngroups must not be NULL");
+        return DD_ERR_NULL;
+    }
+    *ngroups = int32_t(batch->b.groups.size());
+    return DD_OK;
+}
+
+dd_status dd_batch_group(const dd_batch *batch, int32_t g, int32_t *variant, int32_t *dm_tile,
+                         int64_t *work_items, int64_t *queue_bounds)
+{
+    clear_error();
+    if (!batch) {
+        set_error("batch must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (g < 0 || g >= int32_t(batch->b.groups.size())) {
+        set_error("group index out of bounds");
+        return DD_ERR_INVALID;
+    }
+    const dd::BatchGroup &G = batch->b.groups[size_t(g)];
+    if (variant)
+        *variant = G.subband ? 3 : (G.dedup ? 2 : 1);
+    if (dm_tile)
+        *dm_tile = G.dm_tile;
+    if (work_items)
+        *work_items = G.nitems;
+    if (queue_bounds)
+        for (int i = 0; i <= dd::kBatchQueues; ++i)
+            queue_bounds[i] = G.queue_bounds[i];
+    return DD_OK;
+}
+
 dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
                         int64_t *out_offset)
 {

@@ -285,3 +285,61 @@ def test_subband_variant_rejects_plans_beyond_the_lds():
     with pytest.raises(dd.DDError) as e:
         dd.Plan(freqs, 1e-3, 20000, [(0.0, 400.0, 12.5, 1)], "u8", variant=3)
     assert e.value.status == -2 and "LDS" in str(e.value)
+
+
+def _queue_costs(batch, plans, g=0):
+    """Per-XCD cost (items x their beam's channels) of group g's queues,
+    from the item order the batch documents: the group's (beam, range)
+    lists in beam order, stably sorted by channel count, most first."""
+    G = batch.groups[g]
+    descs = []
+    for p in plans:
+        s = p.strategy
+        if (s["variant"], s["dm_tile"]) != (G["variant"], G["dm_tile"]):
+            continue
+        for r in p.ranges:
+            n = -(-r.nout // s["time_tile"]) * -(-r.ndms // s["dm_tile"])
+            descs.append((p.nchans, n))
+    descs.sort(key=lambda d: -d[0])
+    weights = np.concatenate([np.full(n, c, dtype=np.int64) for c, n in descs])
+    assert len(weights) == G["work_items"]
+    prefix = np.concatenate([[0], np.cumsum(weights)])
+    qb = G["queue_bounds"]
+    return [int(prefix[qb[x + 1]] - prefix[qb[x]]) for x in range(8)], int(prefix[-1]), weights
+
+
+def test_batch_queues_share_the_cost_evenly():
+    """Beams of 4096 and 1024 channels: each XCD queue holds an eighth of
+    the group's cost (items weighted by channel count) to within one item,
+    so the queues hold unequal item counts."""
+    freqs = {n: synth.band_freqs(1670.0, 1370.0, n) for n in (1024, 4096)}
+    ranges = synth.ska_ranges_upto(500.0)
+    plans = [dd.Plan(freqs[n], 64e-6, 1 << 16, ranges, "u8", variant=3)
+             for n in (4096, 1024, 1024, 4096, 1024, 1024, 1024, 4096)]
+    batch = dd.Batch(plans)
+    assert len(batch.groups) == 1
+    costs, total, weights = _queue_costs(batch, plans)
+    qb = batch.groups[0]["queue_bounds"]
+    assert qb[0] == 0 and qb[-1] == batch.work_items
+    assert all(a <= b for a, b in zip(qb, qb[1:]))
+    for c in costs:
+        assert abs(c - total / 8) <= weights.max()
+    counts = [qb[x + 1] - qb[x] for x in range(8)]
+    assert max(counts) > 2 * min(counts)          # the 1024-channel items are cheaper
+
+
+def test_batch_of_default_plans_groups_by_kernel():
+    """Default plans whose patterns do or do not fit the LDS run different
+    kernels: one group, with its own balanced queues, per kernel."""
+    plans = []
+    for nch, tsamp in ((256, 128e-6), (7, 64e-6), (64, 128e-6), (7, 64e-6)):
+        plans.append(dd.Plan(synth.band_freqs(1670.0, 1370.0, nch), tsamp, 6000,
+                             synth.ska_ranges_upto(150.0), "u8"))
+    kernels = {(p.strategy["variant"], p.strategy["dm_tile"]) for p in plans}
+    batch = dd.Batch(plans)
+    assert {(g["variant"], g["dm_tile"]) for g in batch.groups} == kernels and len(kernels) > 1
+    assert sum(g["work_items"] for g in batch.groups) == batch.work_items
+    for g in range(len(batch.groups)):
+        costs, total, weights = _queue_costs(batch, plans, g)
+        assert sum(costs) == total
+        assert all(abs(c - total / 8) <= weights.max() for c in costs)
