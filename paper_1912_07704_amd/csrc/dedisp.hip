@@ -1,5 +1,8 @@
 // Device side of the dedispersion library for MI355X (gfx950): the binning
-// kernel, the integer shift-and-sum kernel, device copies of the plan
+// kernels, the integer shift-and-sum kernels (direct, and exact sub-band
+// reuse), their persistent batch forms, the float32 shift-and-sum (forward,
+// adjoint, boxcar loss and its gradient) with its level and finalize
+// kernels, the streaming and corner-turn copies, device copies of the plan
 // tables, and the compute entry points of the C ABI.
 //
 // The operator (brute-force incoherent dedispersion; the paper names it as
