@@ -689,13 +689,13 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
             const int s = row >= J0 ? 1 : 0;
             const int r = row + s * (jmax - J0);
             const int32_t *qo = T + qoffs + r * dd::kSubband;
-            // the row's 8 channel offsets: broadcast word reads (word loads:
-            // the compiler does not order them behind the outstanding
-            // direct-to-LDS loads)
-            int ov[dd::kSubband];
-#pragma unroll
-            for (int k = 0; k < dd::kSubband; ++k)
-                ov[k] = qo[k];
+            // the row's 8 channel offsets: two broadcast 16-byte reads (the
+            // wait the compiler puts before them finds none of this
+            // wavefront's direct loads in flight: they are issued after its
+            // rows)
+            const int4 q0 = *reinterpret_cast<const int4 *>(qo);
+            const int4 q1 = *reinterpret_cast<const int4 *>(qo + 4);
+            const int ov[dd::kSubband] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
             uint32_t *qe = Q + r * 2 * Wq;
             if (full)
                 qrow<NW + 1, true>(A, ov, dd::kSubband, qe, Wq, lane);
