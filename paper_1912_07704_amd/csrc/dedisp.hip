@@ -460,10 +460,10 @@ __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4
 //   out[d][t] = sum_b Q_{b,j(d)}[t + a[d][b] - amin_j],
 //   Q_{b,j}[u] = sum_{c in b} x[c][u + amin_j + v_j[c]].
 // Per stage (stage_chans channels, one or two sub-bands) a workgroup stages
-// the channel windows as the direct kernel does (even and odd copies), then
-// builds the even copy of every pattern row Q of its sub-bands, then their
-// odd copies, and finally adds one row word per DM, sub-band and sample
-// pair -- the same integer sums in another grouping, so exact.
+// one copy of each channel window (16-bit samples, two per word), builds
+// every pattern row Q of its sub-bands in an even and an odd-aligned copy,
+// and adds one row word per DM, sub-band and sample pair -- the same
+// integer sums in another grouping, so exact.
 // ---------------------------------------------------------------------------
 
 struct SbRange {
@@ -511,7 +511,8 @@ __device__ __forceinline__ void dma16(const void *g, void *l)
 //   [0, 4)             patterns of the stage's sub-bands
 //   [4, tb_offc)       first staged word of the next stage's channel windows
 //   [tb_offc, tb_qoff) per-DM row and delay, nslot x dm_tile
-//   [tb_qoff, ...)     pattern row starts, nslot x jmax x kSubband
+//   [tb_qoff, ...)     pattern row starts, nslot x jmax x kSubband (channels whose
+//                      row starts odd first; bits 24-27 of entry 0 count them)
 template <class RR>
 __device__ __forceinline__ int tb_offc(const RR &R) { return 4 + ((R.stage_chans + 3) & ~3); }
 
@@ -549,8 +550,6 @@ __device__ __forceinline__ void tables_issue(const RR &R, int tile, int st, int 
 // Direct loads of the channel windows this wavefront owns (rows j with
 // j % WAVES == wave) of one stage; the window starts come from `base`
 // (global or LDS stage tables).
-// Both copies come from memory: the odd-aligned copy is the same 16-bit
-// row read one sample (2 bytes) later.
 template <int WAVES, bool SCALAR_BASE, class RR>
 __device__ __forceinline__ void rows_issue(const RR &R, const uint16_t *src, const int32_t *base,
                                            int64_t t0, int cs, int cn, uint32_t *buf, int wave,
@@ -558,7 +557,6 @@ __device__ __forceinline__ void rows_issue(const RR &R, const uint16_t *src, con
 {
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
-    const int CW = R.stage_chans * Wr;
     for (int j = wave; j < cn; j += WAVES) {
         // (from LDS the start stays a VGPR: only the LDS destination of a
         // direct load has to be wave-uniform)
@@ -566,10 +564,8 @@ __device__ __forceinline__ void rows_issue(const RR &R, const uint16_t *src, con
         const uint16_t *g = src + (cs + j) * R.pitch + t0 + 2 * int64_t(w0);
         for (int part = 0; part * kWave < chunks; ++part) {
             const int q = part * kWave + lane;
-            if (q < chunks) {
+            if (q < chunks)
                 dma16(g + 8 * q, buf + j * Wr + part * (4 * kWave));
-                dma16(g + 8 * q + 1, buf + CW + j * Wr + part * (4 * kWave));
-            }
         }
     }
 }
@@ -579,48 +575,62 @@ __device__ __forceinline__ int lds_uniform(const int32_t *p)
     return __builtin_amdgcn_readfirstlane(*p);
 }
 
-// Whole-wavefront lane moves (DPP): lane i receives lane i+1's value
-// (lane 63 keeps `old`), and the rotation that brings lane 0's value to
-// lane 63.
+// Whole-wavefront lane move (DPP): lane i receives lane i+1's value (lane
+// 63 keeps `old`).
 constexpr int kDppWaveShl1 = 0x130;
-constexpr int kDppWaveRol1 = 0x134;
 
 // One pattern row of NQ*64 words or fewer (Wq > 64 * (NQ - 1)), both
-// copies.  Even word w = lane + 64i is the sum of the kb channel words at
-// the row's offsets (all reads in flight before the first sum; words past
-// the row read other LDS data and are not stored).  Odd word w takes the
-// upper half of even w and the lower half of even w+1, which lane+1 holds
-// (lane 63: lane 0 of the next group).
+// copies; lane l builds words NQ*l .. NQ*l + NQ - 1 (a stride of NQ words
+// between lanes, odd, so the LDS reads and writes stay conflict-free).
+// Channel k's words at ov[k] + w hold its samples from an even position
+// on; the rows of the first nodd (wave-uniform) channels start one sample
+// later.  The even channels' words sum to sv, the odd channels' to so,
+// realigned once: word w takes the upper half of so[w] and the lower half
+// of so[w+1] (packed 16-bit halves never carry, so realigning the sum
+// equals summing realigned words).  Word w+1 of a lane's last word is
+// lane+1's first (lane 63: 0, past every needed word -- the plan keeps
+// them below 64 * NQ - 1).  The odd copy of the row is realigned the same
+// way.  All reads are in flight before the first sum; words past the row
+// read other LDS data and are not stored.
 template <int NQ, bool FULL>
-__device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, int kb, uint32_t *qe,
-                                     int Wq, int lane)
+__device__ __forceinline__ void qrow(const uint32_t *A, const int *ov, int nodd, int kb,
+                                     uint32_t *qe, int Wq, int lane)
 {
+    const int wb = lane * NQ;
     uint32_t v[dd::kSubband][NQ];
 #pragma unroll
     for (int k = 0; k < dd::kSubband; ++k)
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
-            v[k][i] = (FULL || k < kb) ? A[ov[k] + lane + kWave * i] : 0u;
+            v[k][i] = (FULL || k < kb) ? A[ov[k] + wb + i] : 0u;
     __builtin_amdgcn_sched_barrier(0);
-    uint32_t sv[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i)
-        sv[i] = ((v[0][i] + v[1][i]) + (v[2][i] + v[3][i])) +
-                ((v[4][i] + v[5][i]) + (v[6][i] + v[7][i]));
+    // running sums over the channels; the odd channels' sum is the one
+    // after the first nodd (a register picked by a uniform index)
+    uint32_t sv[NQ], so[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        const int w = lane + kWave * i;
-        const int wrap = i + 1 < NQ ? __builtin_amdgcn_update_dpp(0, int(sv[i + 1]), kDppWaveRol1,
-                                                                   0xF, 0xF, false)
-                                    : 0;
-        const uint32_t nb = uint32_t(__builtin_amdgcn_update_dpp(wrap, int(sv[i]), kDppWaveShl1,
-                                                                 0xF, 0xF, false));
-        // only the last group can reach the end of the row
-        const bool last = i == NQ - 1;
-        if (!last || w < Wq)
+        uint32_t pre[dd::kSubband + 1];
+        pre[0] = 0u;
+#pragma unroll
+        for (int k = 0; k < dd::kSubband; ++k)
+            pre[k + 1] = pre[k] + v[k][i];
+        so[i] = pre[nodd];
+        sv[i] = pre[dd::kSubband] - so[i];
+    }
+    const uint32_t so_n = uint32_t(__builtin_amdgcn_update_dpp(0, int(so[0]), kDppWaveShl1, 0xF,
+                                                               0xF, false));
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+        sv[i] += __builtin_amdgcn_alignbyte(i + 1 < NQ ? so[i + 1] : so_n, so[i], 2);
+    const uint32_t sv_n = uint32_t(__builtin_amdgcn_update_dpp(0, int(sv[0]), kDppWaveShl1, 0xF,
+                                                               0xF, false));
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int w = wb + i;
+        if (w < Wq)
             qe[w] = sv[i];
-        if (!last || w + 1 < Wq)
-            qe[Wq + w] = __builtin_amdgcn_alignbyte(nb, sv[i], 2);
+        if (w + 1 < Wq)
+            qe[Wq + w] = __builtin_amdgcn_alignbyte(i + 1 < NQ ? sv[i + 1] : sv_n, sv[i], 2);
     }
 }
 
@@ -645,7 +655,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
     const int Wq = R.qwords;
     const int jmax = R.jmax;
     const int nst = (nchans + C - 1) / C;
-    uint32_t *Q = lds + 4 * CW;
+    uint32_t *Q = lds + 2 * CW;
     int32_t *Tb = reinterpret_cast<int32_t *>(Q + R.nslot * jmax * 2 * Wq + 4);
     const int offc = tb_offc(R);
     const int qoffs = offc + R.nslot * DT;
@@ -670,10 +680,10 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
         const int nsb = st + 1 < nst ? R.nslot : nsb_last;
-        uint32_t *A = lds + (st & 1) * (2 * CW);
+        uint32_t *A = lds + (st & 1) * CW;
         const int32_t *T = Tb + (st & 1) * R.tb_words;
 
-        // This wavefront's windows (both copies) have landed.
+        // This wavefront's windows have landed.
         wait_loads();
         lds_barrier();
 
@@ -695,12 +705,15 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
             // rows)
             const int4 q0 = *reinterpret_cast<const int4 *>(qo);
             const int4 q1 = *reinterpret_cast<const int4 *>(qo + 4);
-            const int ov[dd::kSubband] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+            // entry 0 carries the count of odd-aligned channels in bits 24-27
+            const int nodd = __builtin_amdgcn_readfirstlane(q0.x) >> 24;
+            const int ov[dd::kSubband] = {q0.x & 0xffffff, q0.y, q0.z, q0.w,
+                                          q1.x, q1.y, q1.z, q1.w};
             uint32_t *qe = Q + r * 2 * Wq;
             if (full)
-                qrow<NW + 1, true>(A, ov, dd::kSubband, qe, Wq, lane);
+                qrow<NW + 1, true>(A, ov, nodd, dd::kSubband, qe, Wq, lane);
             else
-                qrow<NW + 1, false>(A, ov, min(K, nchans - (c0 + s * K)), qe, Wq, lane);
+                qrow<NW + 1, false>(A, ov, nodd, min(K, nchans - (c0 + s * K)), qe, Wq, lane);
         }
         // The next stage's loads go to the other buffers, whose last readers
         // (the previous stage's sums) finished before this stage's first
@@ -713,7 +726,7 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
             if (st + 1 < nst) {
                 const int cs = c0 + C;
                 rows_issue<WAVES, false>(R, src, T + 4, t0, cs, min(C, nchans - cs),
-                                         lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+                                         lds + ((st + 1) & 1) * CW, wave, lane);
                 tables_issue<WAVES, DT>(R, tile, st + 1, st + 2 < nst ? R.nslot : nsb_last,
                                         Tb + ((st + 1) & 1) * R.tb_words, wave, lane);
             }

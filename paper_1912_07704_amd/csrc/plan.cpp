@@ -395,9 +395,11 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         const int32_t cap = int32_t(65535 / (255 * ri.ds));
         const int32_t K = std::max(1, std::min(kSubband, cap));
         const int32_t nsub = (nchans + K - 1) / K;
-        // pattern rows of at most 64*NW + 64 words: 3 words per lane at
-        // 256-sample tiles, 5 at 512
-        const int32_t max_spread = 2 * (kWave64 - 1);
+        // pattern rows of at most 64*NW + 64 words (3 words per lane at
+        // 256-sample tiles, 5 at 512), whose odd-aligned channels' partial
+        // sum reaches one word further: a row's needed words stay below
+        // 64*NW + 63, so (spread >> 1) <= 62
+        const int32_t max_spread = 2 * (kWave64 - 2) + 1;
         // per DM tile: delay spread, most patterns of a sub-band, widest
         // pattern spread
         const int32_t ntiles = (ri.ndms + dmt - 1) / dmt;
@@ -440,16 +442,16 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
             return DD_ERR_INVALID;
         }
         const int32_t Wr = (((span + 7) >> 1) + Wq + 1 + 3) / 4 * 4;
-        // LDS: two stages of channel windows (even and odd copies), the
-        // pattern rows of one stage (even and odd), and two buffers of
-        // stage tables; one workgroup per CU.
+        // LDS: two stages of channel windows, the pattern rows of one stage
+        // (even and odd copies), and two buffers of stage tables; one
+        // workgroup per CU.
         auto slots_for = [&](int32_t st) { return (std::min(st, nchans) + K - 1) / K; };
         auto tb_words = [&](int32_t st) {
             const int32_t n = 4 + (st + 3) / 4 * 4 + slots_for(st) * (dmt + jmax * kSubband);
             return (n + 3) / 4 * 4;
         };
         auto bytes_for = [&](int32_t st) {
-            return size_t(4) * (size_t(4) * st * Wr + size_t(slots_for(st)) * jmax * 2 * Wq + 4 +
+            return size_t(4) * (size_t(2) * st * Wr + size_t(slots_for(st)) * jmax * 2 * Wq + 4 +
                                 size_t(2) * tb_words(st));
         };
         int32_t stage = std::min(cap >= 2 * K ? 2 * K : K, std::max(K, nchans));
@@ -529,14 +531,20 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
                 for (int32_t j = 0; j < pt.J; ++j) {
                     const int32_t *srep =
                         &p->shifts[size_t(ri.dm_index + d0 + pt.rep[j]) * nchans + c0];
+                    // the word holding the first sample of pattern j's row in
+                    // channel c0 + k, relative to the channel's staged
+                    // window; channels whose first sample is odd come first,
+                    // and entry 0 carries their count in bits 24-27
+                    int32_t loc[kSubband], nodd = 0;
                     for (int32_t k = 0; k < kb; ++k) {
-                        // first sample of pattern j's row in channel c0 + k,
-                        // relative to the channel's staged window
-                        const int32_t local = pt.amin[j] + (srep[k] - pt.a[pt.rep[j]]) -
-                                              2 * base[c0 + k];
-                        q[j * kSubband + k] = (local & 1) * S * Wr + (c0 + k - cs) * Wr +
-                                              (local >> 1);
+                        loc[k] = pt.amin[j] + (srep[k] - pt.a[pt.rep[j]]) - 2 * base[c0 + k];
+                        nodd += loc[k] & 1;
                     }
+                    for (int32_t k = 0, io = 0, ie = nodd; k < kb; ++k) {
+                        const int32_t e = (loc[k] & 1) ? io++ : ie++;
+                        q[j * kSubband + e] = (c0 + k - cs) * Wr + (loc[k] >> 1);
+                    }
+                    q[j * kSubband] |= nodd << 24;
                 }
                 int32_t *oc = &p->offCT[ri.sb_c_offset + gb * dmt];
                 for (int32_t d = 0; d < dmt; ++d) {

@@ -265,16 +265,21 @@ def test_default_strategy_prefers_exact_subband_reuse():
     s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, dm_tile=32).strategy
     assert (s["variant"], s["dm_tile"]) == (1, 32)
     # 1024 wide channels at 128 us, DM step 1: too many delay patterns for
-    # the LDS at any sub-band tile
+    # the LDS at 192-DM tiles, not at 128
     d = synth.differentiable()
     with pytest.raises(dd.DDError):
         dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3)
-    with pytest.raises(dd.DDError):
-        dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3, dm_tile=128)
     p = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8")
-    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (1, 64)
+    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (3, 128)
     assert p.shifts().shape == (512, 1024)
-    s = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", dm_tile=192).strategy
+    # DM step 2: too many at every sub-band tile, so the direct kernel
+    coarse = [(0.0, 1024.0, 2.0, 1)]
+    for tile in (192, 128, 96, 64):
+        with pytest.raises(dd.DDError):
+            dd.Plan(d.freqs, d.tsamp, d.nsamp, coarse, "u8", variant=3, dm_tile=tile)
+    p = dd.Plan(d.freqs, d.tsamp, d.nsamp, coarse, "u8")
+    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (1, 64)
+    s = dd.Plan(d.freqs, d.tsamp, d.nsamp, coarse, "u8", dm_tile=192).strategy
     assert (s["variant"], s["dm_tile"]) == (1, 64)
 
 
