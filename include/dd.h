@@ -123,9 +123,12 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *                result; DD_ERR_INVALID when the patterns of a plan do not
  *                fit the LDS).  0 (the default) = variant 3 at the
  *                requested DM tile, or at 192 and then 128 when none is
- *                requested, if the patterns fit; variant 1 otherwise (at
- *                DM tile 32 when requested, else 64).  dd_plan_strategy
- *                reports the choice.
+ *                requested, if the patterns fit and a DM tile holds at
+ *                most one distinct pattern per four DMs and sub-band
+ *                (weighted over the ranges; denser plans run faster on the
+ *                direct sum); variant 1 otherwise (at DM tile 32 when
+ *                requested, else 64).  dd_plan_strategy reports the
+ *                choice.
  *   stage_chans  channels staged in LDS at once (rounded down to even,
  *                or to a multiple of the sub-band for variant 3, and
  *                clamped to what the LDS and, for DD_U8, the exact 16-bit

@@ -556,6 +556,18 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         }
         });
     }
+    // patterns per DM and sub-band, weighted by each range's DM-trial samples
+    double wsum = 0, dsum = 0;
+    for (const RangeInfo &ri : p->ranges) {
+        const size_t n = size_t(ri.ndm_tiles) * ri.sb_nsub;
+        double J = 0;
+        for (size_t i = 0; i < n; ++i)
+            J += p->qcntT[ri.sb_n_offset + i];
+        const double w = double(ri.ndms) * double(ri.nout);
+        dsum += w * J / (double(n) * p->dm_tile);
+        wsum += w;
+    }
+    p->sb_density = wsum > 0 ? dsum / wsum : 0;
     return DD_OK;
 }
 
@@ -656,6 +668,7 @@ void reset_subband(Plan *p)
     p->qoffT.clear();
     p->offCT.clear();
     p->baseT.clear();
+    p->sb_density = 0;
     for (RangeInfo &ri : p->ranges) {
         ri.sb_spread = ri.sb_chans = ri.sb_nsub = ri.sb_jmax = ri.sb_span = 0;
         ri.sb_qwords = ri.sb_nslot = ri.sb_tb_words = 0;
@@ -846,7 +859,9 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             return use(want_variant,
                        want_dm_tile ? want_dm_tile : (want_variant == 3 ? 3 * kDmTile : kDmTile), err);
         // Variant 0: exact sub-band reuse (192-DM tiles, then 128) when the
-        // plan's delay patterns fit the LDS, else the direct kernel.
+        // plan's delay patterns fit the LDS and are few enough per DM to pay
+        // (smaller tiles only hold more patterns per DM), else the direct
+        // kernel.
         std::vector<int32_t> tiles;
         if (want_dm_tile == 0)
             tiles = {3 * kDmTile, 2 * kDmTile};
@@ -855,6 +870,8 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
         for (int32_t t : tiles) {
             std::string e;
             const dd_status st = use(3, t, &e);
+            if (st == DD_OK && p->sb_density > kMaxPatternDensity)
+                break;
             if (st != DD_ERR_INVALID) {
                 if (st != DD_OK)
                     *err = e;

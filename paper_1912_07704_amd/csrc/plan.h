@@ -30,6 +30,12 @@ constexpr int kLevelAlign = 64;                  // samples; row pitch granule o
 // by the same pattern share one partial sum of that sub-band, built once in
 // LDS and added at each DM's own smallest delay.
 constexpr int kSubband = 8;
+// The default strategy takes sub-band reuse only when a DM tile holds at
+// most this many distinct delay patterns per DM and sub-band (weighted by
+// DM-trial samples over the ranges); denser plans build nearly a row per DM
+// and run faster on the direct kernel (measured on gfx950: reuse won at
+// densities up to 0.16 and lost from 0.37 on).
+constexpr double kMaxPatternDensity = 0.25;
 constexpr size_t kWsAlign = 256;
 
 // Float32 path: one generic shift-and-sum over rows staged in LDS,
@@ -161,6 +167,7 @@ struct Plan {
     std::vector<int32_t> qoffT;
     std::vector<int32_t> offCT;
     bool subband = false;                  // integer variant 3
+    double sb_density = 0;                 // variant 3: distinct patterns per DM and sub-band
     std::vector<RangeInfo> ranges;
     std::vector<BinLevel> levels;
     int64_t out_elems = 0;

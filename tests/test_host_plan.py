@@ -256,7 +256,9 @@ def test_subband_variant_is_integer_only_and_batches_mix_kernels():
 def test_default_strategy_prefers_exact_subband_reuse():
     """Variant 0 (the default) takes exact sub-band reuse at 192-DM tiles
     when the plan's delay patterns fit the LDS, else 128-DM tiles, else the
-    direct kernel at 64-DM tiles; a requested DM tile is kept."""
+    direct kernel at 64-DM tiles; and the direct kernel too when the tile
+    holds more than one distinct pattern per four DMs and sub-band.  A
+    requested DM tile is kept."""
     w = synth.ska_single_beam()
     s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges).strategy
     assert (s["variant"], s["dm_tile"], s["time_tile"]) == (3, 192, 256)
@@ -265,13 +267,27 @@ def test_default_strategy_prefers_exact_subband_reuse():
     s = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, dm_tile=32).strategy
     assert (s["variant"], s["dm_tile"]) == (1, 32)
     # 1024 wide channels at 128 us, DM step 1: too many delay patterns for
-    # the LDS at 192-DM tiles, not at 128
+    # the LDS at 192-DM tiles; they fit at 128, but with about one pattern
+    # per three DMs reuse does not pay, so the default is the direct kernel
     d = synth.differentiable()
     with pytest.raises(dd.DDError):
         dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3)
+    s = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8", variant=3, dm_tile=128).strategy
+    assert (s["variant"], s["dm_tile"]) == (3, 128)
     p = dd.Plan(d.freqs, d.tsamp, d.nsamp, d.ranges, "u8")
-    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (3, 128)
+    assert (p.strategy["variant"], p.strategy["dm_tile"]) == (1, 64)
     assert p.shifts().shape == (512, 1024)
+    # the tiny plan (128 channels, DM step 1 at 256 us) fits at 192 but is as
+    # dense, and so is a 64-channel band
+    t = synth.tiny()
+    assert dd.Plan(t.freqs, t.tsamp, t.nsamp, t.ranges, "u8").strategy["variant"] == 1
+    assert dd.Plan(t.freqs, t.tsamp, t.nsamp, t.ranges, "u8", variant=3).strategy["variant"] == 3
+    f64 = synth.band_freqs(1500.0, 1200.0, 64)
+    assert dd.Plan(f64, 256e-6, 1 << 18, [(0.0, 200.0, 0.5, 1)], "u8").strategy["variant"] == 1
+    # 1024 channels of the SKA-like band to DM 500: sparse patterns, reuse
+    s = dd.Plan(synth.band_freqs(1670.0, 1370.0, 1024), 64e-6, 1 << 18,
+                synth.ska_ranges_upto(500.0), "u8").strategy
+    assert (s["variant"], s["dm_tile"]) == (3, 192)
     # DM step 2: too many at every sub-band tile, so the direct kernel
     coarse = [(0.0, 1024.0, 2.0, 1)]
     for tile in (192, 128, 96, 64):

@@ -126,19 +126,19 @@ def test_ska_full_size_equals_direct_kernel():
         assert np.array_equal(got, O.dedisperse_at(x, op, r, d, t))
 
 
-def test_wide_channel_plan_default_equals_direct_kernel():
-    """1024 wide channels at 128 us, DM 0..511 step 1, uint8: the default
-    strategy takes sub-band reuse at 128-DM tiles with one-sub-band stages
-    (too many delay patterns for 192); the whole output equals variant 1's,
-    and sampled outputs equal the oracle's."""
+def test_wide_channel_plan_equals_direct_kernel():
+    """1024 wide channels at 128 us, DM 0..511 step 1, uint8: sub-band reuse
+    fits at 128-DM tiles with one-sub-band stages (too many delay patterns
+    for 192); the whole output equals variant 1's, and sampled outputs equal
+    the oracle's."""
     w = synth.differentiable()
     rng = np.random.default_rng(512)
     x = rng.integers(0, 256, size=(1024, w.nsamp)).astype(np.uint8)
     xt = torch.from_numpy(x).cuda()
-    p0 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8")
-    assert (p0.strategy["variant"], p0.strategy["dm_tile"]) == (3, 128)
+    p0 = plan_v3(w.freqs, w.tsamp, w.nsamp, w.ranges, dm_tile=128)
+    assert p0.strategy["chans_stage"] == 8
     p1 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=1)
-    say("wide channels: default", p0.strategy)
+    say("wide channels: variant 3", p0.strategy)
     o0 = dd.dedisperse(xt, p0)
     o1 = dd.dedisperse(xt, p1)
     torch.cuda.synchronize()
