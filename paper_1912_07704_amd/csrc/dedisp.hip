@@ -738,38 +738,42 @@ __device__ __forceinline__ void dedisp_tile_sb(const RR &R, const uint16_t *src,
         if constexpr (issue_after)
             issue_next();
 
-        // One pattern-row word per DM, sub-band and sample pair.
-        const uint32_t *rowq = Q + lane;
-        const int32_t *oc = T + offc + wave * DPW;
-        int offa[DPW];
-#pragma unroll
-        for (int dd = 0; dd < DPW; ++dd)
-            offa[dd] = oc[dd];
-        if (nsb > 1) {
-            int offb[DPW];
+        // One pattern-row word per DM, sub-band and sample pair; a wavefront
+        // whose DMs all lie past the range's last (the last DM tile of a
+        // range) has nothing to sum.
+        if (dw0 < ndms) {
+            const uint32_t *rowq = Q + lane;
+            const int32_t *oc = T + offc + wave * DPW;
+            int offa[DPW];
 #pragma unroll
             for (int dd = 0; dd < DPW; ++dd)
-                offb[dd] = oc[DT + dd];
-            // groups of 6 DMs bound the loads in flight (and the VGPRs they hold)
+                offa[dd] = oc[dd];
+            if (nsb > 1) {
+                int offb[DPW];
 #pragma unroll
-            for (int dd = 0; dd < DPW; ++dd) {
-                const uint32_t *pa = rowq + offa[dd];
-                const uint32_t *pb = rowq + offb[dd];
+                for (int dd = 0; dd < DPW; ++dd)
+                    offb[dd] = oc[DT + dd];
+                // groups of 6 DMs bound the loads in flight (and the VGPRs they hold)
 #pragma unroll
-                for (int k = 0; k < NW; ++k)
-                    acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
-                if (dd % 6 == 5 && dd + 1 < DPW)
-                    __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
+                for (int dd = 0; dd < DPW; ++dd) {
+                    const uint32_t *pa = rowq + offa[dd];
+                    const uint32_t *pb = rowq + offb[dd];
 #pragma unroll
-            for (int dd = 0; dd < DPW; ++dd) {
-                const uint32_t *pa = rowq + offa[dd];
+                    for (int k = 0; k < NW; ++k)
+                        acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
+                    if (dd % 6 == 5 && dd + 1 < DPW)
+                        __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
 #pragma unroll
-                for (int k = 0; k < NW; ++k)
-                    acc16[dd][k] += pa[kWave * k];
-                if (dd % 6 == 5 && dd + 1 < DPW)
-                    __builtin_amdgcn_sched_barrier(0);
+                for (int dd = 0; dd < DPW; ++dd) {
+                    const uint32_t *pa = rowq + offa[dd];
+#pragma unroll
+                    for (int k = 0; k < NW; ++k)
+                        acc16[dd][k] += pa[kWave * k];
+                    if (dd % 6 == 5 && dd + 1 < DPW)
+                        __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
         if (--widen_left == 0 || st + 1 == nst) {

@@ -246,7 +246,11 @@ int run(const std::vector<double> &freqs, double tsamp, int64_t nsamp, const std
                 if (!issue_after) issue_next();
                 ++ph;   // barrier
                 if (issue_after) issue_next();
-                for (int d = 0; d < DT; ++d)
+                const int DPW = DT / P.waves;
+                for (int d = 0; d < DT; ++d) {
+                    // a wavefront whose DMs all lie past the range's last skips its sums
+                    if (tile * DT + (d / DPW) * DPW >= R.ndms)
+                        continue;
                     for (int s = 0; s < nsb; ++s) {
                         const int o = int(lds.rd(T + offc + s * DT + d, ph, TAG_TAB + k, "offC read"));
                         for (int i = 0; i < NW; ++i)
@@ -257,6 +261,7 @@ int run(const std::vector<double> &freqs, double tsamp, int64_t nsamp, const std
                                 acc16[(size_t(d) * NW + i) * 64 + ln] += need ? lds.rd(wi, ph, TAG_Q + k, "sum read") : lds.rd_any(wi, ph, "sum read (unused)");
                             }
                     }
+                }
                 if (--widen_left == 0 || k + 1 == nst) {
                     widen_left = R.widen_every;
                     for (int d = 0; d < DT; ++d)
