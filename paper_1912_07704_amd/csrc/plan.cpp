@@ -556,7 +556,9 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         }
         });
     }
-    // patterns per DM and sub-band, weighted by each range's DM-trial samples
+    // patterns per DM and sub-band, weighted by each range's DM-trial
+    // samples; per real DM (the padding DMs of a range's last tile have no
+    // patterns and no sums, so they do not dilute the density)
     double wsum = 0, dsum = 0;
     for (const RangeInfo &ri : p->ranges) {
         const size_t n = size_t(ri.ndm_tiles) * ri.sb_nsub;
@@ -564,7 +566,7 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
         for (size_t i = 0; i < n; ++i)
             J += p->qcntT[ri.sb_n_offset + i];
         const double w = double(ri.ndms) * double(ri.nout);
-        dsum += w * J / (double(n) * p->dm_tile);
+        dsum += w * J / (double(ri.ndms) * ri.sb_nsub);
         wsum += w;
     }
     p->sb_density = wsum > 0 ? dsum / wsum : 0;

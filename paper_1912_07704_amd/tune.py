@@ -18,7 +18,9 @@ import json
 import os
 import statistics
 
-from . import Plan, dedisperse, workspace
+from . import DDError, Plan, dedisperse, workspace
+
+DD_ERR_INVALID = -2
 
 VARIANTS = (1, 2)
 DM_TILES = (64, 32)
@@ -113,8 +115,10 @@ def tune(freqs, tsamp, nsamp, ranges, x=None, reps: int = 3, cands=None, use_cac
     for opts in (cands or candidates()):
         try:
             plan = Plan(freqs, tsamp, nsamp, ranges, "u8", **opts)
-        except Exception:            # an LDS-infeasible candidate for this plan
-            continue
+        except DDError as e:
+            if e.status != DD_ERR_INVALID:
+                raise
+            continue                 # a candidate whose tiles do not fit this plan
         ws = workspace(plan, x.device)
         out = torch.empty(plan.out_elems, dtype=torch.int32, device=x.device)
         dedisperse(x, plan, out=out, ws=ws)

@@ -364,3 +364,59 @@ def test_batch_of_default_plans_groups_by_kernel():
         costs, total, weights = _queue_costs(batch, plans, g)
         assert sum(costs) == total
         assert all(abs(c - total / 8) <= weights.max() for c in costs)
+
+
+def _pattern_density(plan, tile=192, K=8, max_spread=125):
+    """Distinct delay patterns per real DM and 8-channel sub-band, weighted
+    by each range's DM-trial samples, counted here from the plan's shift
+    table: in each DM tile and sub-band, DMs whose delays minus their
+    smallest delay agree share a pattern (a pattern whose smallest delays
+    spread over more than max_spread samples counts again)."""
+    S = plan.shifts()
+    num = den = 0.0
+    off = 0
+    for ri in plan.ranges:
+        s = S[off: off + ri.ndms]
+        off += ri.ndms
+        J = 0
+        nsub = -(-plan.nchans // K)
+        for g in range(0, ri.ndms, tile):
+            blk = s[g: g + tile]
+            for b in range(nsub):
+                sb = blk[:, b * K: (b + 1) * K]
+                a = sb.min(axis=1)
+                firsts = {}
+                for i in range(len(sb)):
+                    key = tuple(sb[i] - a[i])
+                    if key not in firsts or a[i] - firsts[key] > max_spread:
+                        firsts[key] = a[i]
+                        J += 1
+        w = ri.ndms * ri.nout
+        num += w * J / (ri.ndms * nsub)
+        den += w
+    return num / den
+
+
+@pytest.mark.parametrize("nch,tsamp,f_top,bw,step,ndms,want", [
+    # ragged last tiles (216, 198, 203 DMs at 192-DM tiles): per real DM the
+    # density is above the crossover, per padded tile it would be below it
+    (256, 128e-6, 1400.0, 100.0, 1.0, 216, 1),
+    (64, 128e-6, 1430.0, 250.0, 0.1, 198, 1),
+    (96, 64e-6, 1530.0, 54.0, 0.2, 203, 1),
+    # below the crossover either way
+    (256, 128e-6, 1670.0, 70.0, 1.0, 305, 3),
+    (128, 128e-6, 1530.0, 250.0, 0.1, 255, 3),
+])
+def test_default_density_counts_real_dms(nch, tsamp, f_top, bw, step, ndms, want):
+    """The default takes sub-band reuse only when a tile holds at most one
+    pattern per four real DMs and sub-band: the padding DMs of a range's
+    last DM tile have no sums and do not dilute the density."""
+    freqs = synth.band_freqs(f_top, f_top - bw, nch)
+    ranges = [(0.0, ndms * step, step, 1)]
+    p3 = dd.Plan(freqs, tsamp, 1 << 16, ranges, "u8", variant=3, dm_tile=192)
+    dens = _pattern_density(p3)
+    assert (dens > 0.25) == (want == 1), dens
+    s = dd.Plan(freqs, tsamp, 1 << 16, ranges, "u8").strategy
+    assert s["variant"] == want
+    if want == 3:
+        assert s["dm_tile"] == 192
