@@ -165,8 +165,14 @@ dd_status dd_plan_info(const dd_plan *plan, int32_t *ndms_total, int64_t *out_el
                        int64_t *overlap_samples);
 
 /*
- * Sizes of range r (0 <= r < nranges, else DD_ERR_INVALID).  Any output
- * pointer may be NULL.  out_offset is in elements.
+ * Sizes of range r (paper, "Plan and strategy": the user may query the
+ * configured plan and strategy).  0 <= r < nranges, else DD_ERR_INVALID;
+ * DD_ERR_NULL for a NULL plan.  Any output pointer may be NULL.
+ *   ndms        trial DMs of the range
+ *   nout        valid output samples per DM (binned samples)
+ *   out_offset  first output element of the range, in elements
+ *   max_shift   largest delay of the range, in binned samples
+ *   downsample  the range's ds_r
  */
 dd_status dd_plan_range(const dd_plan *plan, int32_t r, int32_t *ndms, int64_t *nout,
                         int64_t *out_offset, int32_t *max_shift, int32_t *downsample);
@@ -174,11 +180,16 @@ dd_status dd_plan_range(const dd_plan *plan, int32_t r, int32_t *ndms, int64_t *
 /* Number of ranges of the plan. */
 dd_status dd_plan_nranges(const dd_plan *plan, int32_t *nranges);
 
-/* Copy the trial DMs (host, [ndms_total] doubles, ranges in plan order). */
+/* Copy the trial DMs the plan expanded (paper, "Plan and strategy": the
+ * configured plan may be queried): dms_out is a caller-owned host array of
+ * [ndms_total] doubles, filled with lo + i*step per range, ranges in plan
+ * order.  DD_ERR_NULL for a NULL argument. */
 dd_status dd_plan_dms(const dd_plan *plan, double *dms_out);
 
-/* Copy the shift table (host, [ndms_total][nchans] int32, in binned samples
- * of each DM's range). */
+/* Copy the plan's FP64-derived shift table (paper, "Plan and strategy": the
+ * configured plan may be queried): shifts_out is a caller-owned host array
+ * of [ndms_total][nchans] int32, DM-major, each entry in binned samples of
+ * its DM's range.  DD_ERR_NULL for a NULL argument. */
 dd_status dd_plan_shifts(const dd_plan *plan, int32_t *shifts_out);
 
 /*
@@ -214,7 +225,10 @@ dd_status dd_workspace_bytes(const dd_plan *plan, size_t *bytes);
 dd_status dd_plan_prepare(dd_plan *plan);
 
 /*
- * Forward dedispersion of one filterbank.
+ * Forward dedispersion of one filterbank: the dedispersion module of the
+ * pipeline run on data already on the GPU (paper, Introduction: data are
+ * dedispersed entirely on the GPU; "Design of the API": the run step of a
+ * configured plan).
  *   d_in          [nchans][nsamp] channel-major, uint8 (DD_U8) or float32
  *                 (DD_F32); read only.
  *   d_weights     [nchans] float32 per-channel weights, DD_F32 only; NULL
@@ -401,10 +415,16 @@ dd_status dd_stream_push(dd_stream *stream, const void *d_block, int64_t samples
 dd_status dd_corner_turn(dd_dtype dtype, const void *d_in, int64_t nsamp, int32_t nchans,
                          void *d_out, int64_t out_pitch, void *stream);
 
-/* Text of a status code (static storage). */
+/* Text of a status code (paper, "Design of the API": the API gives the user
+ * feedback on errors; "Pipeline": a status code per call).  Returns a
+ * static string, never NULL ("unknown dd_status" for values outside
+ * dd_status). */
 const char *dd_status_str(dd_status status);
 
-/* Detail of the last failing call on this thread ("" if none). */
+/* Detail of the last failing call on this thread (paper, "Design of the
+ * API": configuration errors are reported back to the user).  Returns a
+ * thread-local string owned by the library, valid until the next failing
+ * call on the same thread; "" if no call on this thread has failed. */
 const char *dd_last_error(void);
 
 #ifdef __cplusplus

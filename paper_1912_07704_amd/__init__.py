@@ -458,7 +458,49 @@ def _autograd_fn():
     return DedispFn
 
 
+def _boxcar_fn():
+    import torch
+
+    class BoxcarLossFn(torch.autograd.Function):
+        """L = boxcar_loss(x, w) with a hand-written backward: forward runs
+        dd_boxcar_loss and saves (x, w), never the dedispersed output;
+        backward runs dd_boxcar_backward, which recomputes the output tiles
+        it needs.  The upstream scalar gradient scales the result (autograd's
+        chain rule; skipped when it is exactly 1)."""
+
+        @staticmethod
+        def forward(ctx, x, weights, plan, max_width):
+            ctx.plan, ctx.max_width = plan, int(max_width)
+            ctx.save_for_backward(x, weights)
+            return boxcar_loss(x, plan, weights, ctx.max_width)
+
+        @staticmethod
+        def backward(ctx, gL):
+            x, weights = ctx.saved_tensors
+            need_x, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            dx, dw = boxcar_backward(x, ctx.plan, weights, ctx.max_width, grad_in=need_x,
+                                     grad_w=need_w)
+            if float(gL) != 1.0:
+                dx = dx * gL if dx is not None else None
+                dw = dw * gL if dw is not None else None
+            return dx, dw, None, None
+
+    return BoxcarLossFn
+
+
 _FN = None
+_BOX_FN = None
+
+
+def boxcar_loss_autograd(x, weights, plan: Plan, max_width: int = 32):
+    """Differentiable boxcar loss of the dedispersed output (the output is
+    recomputed in the backward, never stored): gradients flow to x
+    ([nbeams, nchans, nsamp] or [nchans, nsamp]) and to the shared
+    per-channel weights (or None for unit weights)."""
+    global _BOX_FN
+    if _BOX_FN is None:
+        _BOX_FN = _boxcar_fn()
+    return _BOX_FN.apply(x, weights, plan, max_width)
 
 
 def dedisperse_autograd(x, weights, plan: Plan):

@@ -105,8 +105,9 @@ def test_batch_graph_replay(strategy):
 def test_batched_beams_full_size(strategy):
     """The 64-beam batched workload (channel counts 1024/2048/4096, lengths
     2^16..2^18, DM max 500/1000/2000), drawn on the GPU: every beam of the
-    batch equals its own dd_forward, and sampled outputs of
-    three beams equal the oracle."""
+    batch equals its own dd_forward, one whole beam of each channel count
+    equals the C oracle, and sampled outputs of three beams equal the numpy
+    oracle."""
     wls = synth.batched_beams()
     say("batched beams: plans", strategy)
     plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **STRATEGIES[strategy]) for w in wls]
@@ -128,6 +129,16 @@ def test_batched_beams_full_size(strategy):
         torch.cuda.synchronize()
         assert torch.equal(outs[i], single), f"beam {i}"
     del ws
+    # whole outputs against the C oracle: for each channel count, the beam
+    # with the most DM trials (ties: the longest)
+    for nch in sorted({p.nchans for p in plans}):
+        i = max((j for j, p in enumerate(plans) if p.nchans == nch),
+                key=lambda j: (plans[j].ndms_total, plans[j].nsamp))
+        w, p, off = wls[i], plans[i], batch.in_offsets[i]
+        say("batched beams: whole output of beam", i, nch, p.nsamp, p.ndms_total)
+        x = xin[off: off + p.nchans * p.nsamp].view(p.nchans, p.nsamp).cpu().numpy()
+        want = cref.dedisperse_u8(x, w.freqs, w.tsamp, w.ranges)
+        assert np.array_equal(outs[i].cpu().numpy(), want), f"beam {i} vs oracle"
     rng = np.random.default_rng(3)
     for i in sorted({0, len(wls) - 1, int(rng.integers(len(wls)))}):
         w, p, off = wls[i], plans[i], batch.in_offsets[i]

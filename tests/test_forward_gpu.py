@@ -218,18 +218,56 @@ def ska():
     return w, x, plan, out
 
 
-def test_ska_full_size_rows_bit_exact(ska):
-    """Whole rows at the DM-tile edges and inside tiles of every range,
-    against the C oracle's rows."""
+@pytest.fixture(scope="module")
+def ska_want(ska):
+    w, x, plan, out = ska
+    say("ska whole output: C oracle on", cref.max_threads(), "threads")
+    return cref.dedisperse_u8(x, w.freqs, w.tsamp, w.ranges)
+
+
+def test_ska_full_size_whole_output_bit_exact(ska, ska_want):
+    """Every one of the 536 529 400 outputs of the default strategy (the
+    launch configuration the benchmark times) against the plain C oracle
+    over the whole plan."""
+    w, x, plan, out = ska
+    want = ska_want
+    say("ska whole output: compare")
+    got = out.cpu().numpy()
+    assert got.shape == want.shape
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"{bad.size} outputs differ, first at {bad[:8]}"
+
+
+def tile_edge_rows(ndms, dm_tile, wave_dms=(8, 12)):
+    """Rows at every DM-tile edge (first, second, last two of each tile),
+    the first rows of a few wavefronts, and the range's last rows."""
+    rows = {ndms - 2, ndms - 1, ndms // 2}
+    for t0 in range(0, ndms, dm_tile):
+        rows |= {t0, t0 + 1, t0 + dm_tile - 2, t0 + dm_tile - 1}
+        for wd in wave_dms:
+            rows |= {t0 + wd - 1, t0 + wd}
+    return sorted(r for r in rows if 0 <= r < ndms)
+
+
+def test_ska_full_size_rows_bit_exact(ska, ska_want):
+    """Whole rows at the edges of the default strategy's DM tiles (and of
+    the direct kernel's 32/64-DM tiles) in every range, including the partial
+    last tile, against the C oracle: rows of the whole-plan reference, and
+    for range 0 the oracle's row-by-row entry as well."""
     w, x, plan, out = ska
     outs = plan.split(out)
+    wants = plan.split(ska_want)
+    dm_tile = plan.strategy["dm_tile"]
     for r, (rg, ri) in enumerate(zip(w.ranges, plan.ranges)):
-        rows = sorted({0, 1, 31, 32, 33, ri.ndms // 2, ri.ndms - 2, ri.ndms - 1})
+        rows = sorted(set(tile_edge_rows(ri.ndms, dm_tile)) | {31, 32, 33, 63, 64})
         say("ska rows", r, rows)
-        for d in rows:
-            want = cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, d, d + 1, ri.nout)[0]
-            got = outs[r][d].cpu().numpy()
-            assert np.array_equal(got, want), (r, d)
+        got = outs[r][torch.tensor(rows, device="cuda")].cpu().numpy()
+        for i, d in enumerate(rows):
+            assert np.array_equal(got[i], wants[r][d]), (r, d)
+        if r == 0:
+            for d in (dm_tile - 1, dm_tile, ri.ndms - 1):
+                want = cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, d, d + 1, ri.nout)[0]
+                assert np.array_equal(got[rows.index(d)], want), (r, d)
 
 
 def test_ska_full_size_sampled_outputs(ska):

@@ -1,10 +1,13 @@
-"""Streaming in chunks with the plan's largest delay as overlap, and the
-corner turn from time-major blocks: the concatenated chunks reproduce one
-forward over the whole series bit for bit."""
+"""Streaming in chunks with the plan's largest delay as overlap (the
+pipeline's chunked iterations, paper "Pipeline"), and the corner turn from
+time-major blocks: the concatenated chunks equal the CPU oracle over the
+whole series (bit for bit for uint8, within the float32 tolerance for
+float32) and reproduce one forward over the whole series."""
 import numpy as np
 import pytest
 
 import synth
+from oracle import cref
 
 pytestmark = pytest.mark.gpu
 
@@ -58,9 +61,26 @@ def test_stream_equals_one_shot(dtype, time_major):
         k += 1
     torch.cuda.synchronize()
     assert k == 4
+    # the oracle over the whole series, split per range
+    if dtype == "u8":
+        ref = cref.dedisperse_u8(x, freqs, tsamp, ranges)
+    else:
+        ref = cref.dedisperse_f32(x, freqs, tsamp, ranges)
+        terms = cref.dedisperse_f32(np.abs(x), freqs, tsamp, ranges)
     for r in range(len(ranges)):
         g = torch.cat(got[r], dim=1)
+        assert g.shape[1] == 4 * (s.step // plan.ranges[r].downsample)
         assert torch.equal(g, want[r][:, : g.shape[1]]), f"range {r}"
+        gn = g.cpu().numpy()
+        wr = full.split(ref)[r][:, : gn.shape[1]]
+        if dtype == "u8":
+            assert np.array_equal(gn, wr), f"range {r} vs oracle"
+        else:
+            tr = full.split(terms)[r][:, : gn.shape[1]]
+            err = np.abs(gn.astype(np.float64) - wr)
+            nw = float(err.max() / np.abs(wr).max())
+            assert nw <= 1e-5, f"range {r}: normwise {nw:.3e}"
+            assert not (err > 1e-5 * tr + 1e-30).any(), f"range {r}: elementwise bound"
 
 
 def test_stream_rejects_wrong_block_sizes():
