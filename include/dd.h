@@ -267,6 +267,32 @@ dd_status dd_forward_sum(const dd_plan *plan, void *d_out, int64_t out_capacity,
                          size_t ws_bytes, void *stream);
 
 /*
+ * dd_forward for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * computes exactly what dd_forward computes (same kernels, same results) but
+ * takes no workspace argument and calls no hipMalloc, hipFree or allocating
+ * library routine: its workspace is a static device array of
+ * DD_NOALLOC_WS_MAX bytes built into the library, one copy per GPU, held
+ * until the process ends.  The caller still owns d_in, d_weights and d_out
+ * (arguments as for dd_forward).
+ *
+ *   - The plan's tables must already be on the current device: call
+ *     dd_plan_prepare on that device first (else DD_ERR_INVALID).
+ *   - Plans whose forward needs more than DD_NOALLOC_WS_MAX bytes of
+ *     workspace (the binned copies of the input, reported for DD_U8 plans by
+ *     dd_workspace_bytes) are rejected with DD_ERR_WORKSPACE; use dd_forward.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents (the forward overwrites everything it reads).  Calls
+ *     that overlap in time on one GPU (two streams, two host threads) race:
+ *     order them on one stream or serialise them.
+ * Errors: as dd_forward, plus the two above.
+ */
+#define DD_NOALLOC_WS_MAX (64u << 20)
+
+dd_status dd_forward_noalloc(const dd_plan *plan, const void *d_in, const float *d_weights,
+                             void *d_out, int64_t out_capacity, void *stream);
+
+/*
  * Adjoint of the DD_F32 forward (the transpose of the linear map x -> out
  * for fixed weights, and its derivative in the weights), for the gradient
  * of a loss L given g = dL/dout:

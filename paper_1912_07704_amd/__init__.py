@@ -357,6 +357,20 @@ def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step
     return out
 
 
+def dedisperse_noalloc(x, plan: Plan, out, weights=None, stream=None):
+    """dd_forward_noalloc: the forward with the library's static workspace
+    (no device allocation in the call).  `out` must be given; the plan must
+    have been prepared on the device (plan.prepare())."""
+    _check_input(x, plan)
+    _check_weights(weights, plan)
+    if out is None:
+        raise ValueError("dedisperse_noalloc needs a preallocated `out`")
+    out = _out_tensor(plan, out, x.device)
+    check(lib().dd_forward_noalloc(plan.handle, _ptr(x), _ptr(weights), _ptr(out), out.numel(),
+                                   _stream_ptr(stream)), "dd_forward_noalloc")
+    return out
+
+
 def bin_input(x, plan: Plan, ws, weights=None, stream=None):
     """The binning step alone (dd_forward_bin) into the workspace ws."""
     _check_input(x, plan)

@@ -25,6 +25,7 @@ SIGNATURES = {
     "dd_forward": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),
     "dd_forward_bin": (ctypes.c_int, [P, P, P, P, SZ, P]),
     "dd_forward_sum": (ctypes.c_int, [P, P, I64, P, SZ, P]),
+    "dd_forward_noalloc": (ctypes.c_int, [P, P, P, P, I64, P]),
     "dd_adjoint": (ctypes.c_int, [P, P, P, P, P, P, P, SZ, P]),
     "dd_boxcar_loss": (ctypes.c_int, [P, P, I32, P, I32, P, P, SZ, P]),
     "dd_boxcar_backward": (ctypes.c_int, [P, P, I32, P, I32, P, P, P, SZ, P]),

@@ -2085,7 +2085,8 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
 // any HIP call).
 dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float *d_weights,
                              const void *d_out, int64_t out_capacity, const void *d_ws,
-                             size_t ws_bytes, bool need_out, bool need_in = true)
+                             size_t ws_bytes, bool need_out, bool need_in = true,
+                             size_t ws_need = SIZE_MAX)
 {
     if (!plan || (need_in && !d_in) || (need_out && !d_out)) {
         dd::set_error("plan, d_in and d_out must not be NULL");
@@ -2105,15 +2106,87 @@ dd_status check_forward_args(const dd_plan *plan, const void *d_in, const float 
                       std::to_string(p.out_elems));
         return DD_ERR_CAPACITY;
     }
-    if (ws_bytes < p.ws_bytes || (p.ws_bytes > 0 && !d_ws)) {
+    if (ws_need == SIZE_MAX)
+        ws_need = p.ws_bytes;
+    if (ws_bytes < ws_need || (ws_need > 0 && !d_ws)) {
         dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
-                      std::to_string(p.ws_bytes));
+                      std::to_string(ws_need));
         return DD_ERR_WORKSPACE;
     }
     if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
         dd::set_error("workspace must be 256-byte aligned");
         return DD_ERR_WORKSPACE;
     }
+    return DD_OK;
+}
+
+// Tables of the current device if they were uploaded already (never
+// uploads: used by the entry point that allocates nothing).
+DeviceTables *find_device_tables(const Plan &p)
+{
+    DeviceState *st = state_of(p);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(st->mu);
+    auto it = st->per_device.find(dev);
+    return it == st->per_device.end() ? nullptr : &it->second;
+}
+
+// Workspace bytes the forward itself touches: the binned levels (the rest of
+// a float plan's workspace serves the adjoint and the boxcar loss).
+size_t forward_ws_bytes(const Plan &p)
+{
+    size_t n = 0;
+    for (const dd::BinLevel &lv : p.levels)
+        n = std::max(n, lv.ws_offset + lv.bytes);
+    return n;
+}
+
+}  // namespace
+
+// Workspace of dd_forward_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code `scratch` is only a
+// host-side handle of the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (scratch_address), and only that address is passed to
+// kernels.
+static __device__ __align__(256) char scratch[DD_NOALLOC_WS_MAX];
+
+namespace {
+
+struct ScratchAddresses {
+    std::mutex mu;
+    std::map<int, char *> per_device;
+};
+
+ScratchAddresses &scratch_addresses()
+{
+    static ScratchAddresses s;
+    return s;
+}
+
+// The current device's address of `scratch`, looked up once per device with
+// that device current.
+dd_status scratch_address(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    ScratchAddresses &sa = scratch_addresses();
+    std::lock_guard<std::mutex> lock(sa.mu);
+    auto it = sa.per_device.find(dev);
+    if (it != sa.per_device.end()) {
+        *out = it->second;
+        return DD_OK;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return hip_fail(e, "hipGetSymbolAddress of the static workspace");
+    }
+    *out = sa.per_device[dev] = static_cast<char *>(ptr);
     return DD_OK;
 }
 
@@ -2258,6 +2331,43 @@ dd_status dd_forward(const dd_plan *plan, const void *d_in, const float *d_weigh
     if (st != DD_OK)
         return st;
     return forward_sum(plan->p, *t, d_out, static_cast<const char *>(d_ws), s);
+}
+
+dd_status dd_forward_noalloc(const dd_plan *plan, const void *d_in, const float *d_weights,
+                             void *d_out, int64_t out_capacity, void *stream)
+{
+    dd::clear_error();
+    if (!plan) {
+        dd::set_error("plan must not be NULL");
+        return DD_ERR_NULL;
+    }
+    const Plan &p = plan->p;
+    const size_t need = forward_ws_bytes(p);
+    if (need > size_t(DD_NOALLOC_WS_MAX)) {
+        dd::set_error("the plan's forward needs " + std::to_string(need) +
+                      " bytes of workspace, more than the static workspace's " +
+                      std::to_string(size_t(DD_NOALLOC_WS_MAX)) + " (use dd_forward)");
+        return DD_ERR_WORKSPACE;
+    }
+    DeviceTables *t = find_device_tables(p);
+    if (!t) {
+        dd::set_error("the plan's tables are not on the current device: call dd_plan_prepare "
+                      "on it first (dd_forward_noalloc allocates nothing)");
+        return DD_ERR_INVALID;
+    }
+    char *ws = nullptr;
+    dd_status st = scratch_address(&ws);
+    if (st != DD_OK)
+        return st;
+    st = check_forward_args(plan, d_in, d_weights, d_out, out_capacity, ws,
+                            size_t(DD_NOALLOC_WS_MAX), true, true, need);
+    if (st != DD_OK)
+        return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    st = forward_bin(p, d_in, d_weights, ws, s);
+    if (st != DD_OK)
+        return st;
+    return forward_sum(p, *t, d_out, ws, s);
 }
 
 dd_status dd_adjoint(const dd_plan *plan, const float *d_grad_out, const float *d_in,
