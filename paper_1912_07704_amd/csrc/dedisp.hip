@@ -53,26 +53,6 @@ __device__ __forceinline__ sgpr8 table8(const int32_t *p)
     return v;
 }
 
-// Two rows' worth of four table entries (row p and row q), one wait.
-typedef int sgpr4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void table4x2(const int32_t *p, const int32_t *q, sgpr4 &u, sgpr4 &v)
-{
-    // (the halves as unsigned 32-bit values: readfirstlane returns int,
-    // and a sign-extended low half would corrupt the high one)
-    const uint64_t a = reinterpret_cast<uint64_t>(p);
-    const uint64_t b = reinterpret_cast<uint64_t>(q);
-    const uint32_t alo = __builtin_amdgcn_readfirstlane(uint32_t(a));
-    const uint32_t ahi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
-    const uint32_t blo = __builtin_amdgcn_readfirstlane(uint32_t(b));
-    const uint32_t bhi = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32));
-    const uint64_t pa = (uint64_t(ahi) << 32) | alo;
-    const uint64_t pb = (uint64_t(bhi) << 32) | blo;
-    asm volatile("s_load_dwordx4 %0, %2, 0x0\n\ts_load_dwordx4 %1, %3, 0x0\n\ts_waitcnt lgkmcnt(0)"
-                 : "=&s"(u), "=&s"(v)
-                 : "s"(pa), "s"(pb));
-}
-
 __device__ __forceinline__ int32_t table1(const int32_t *p)
 {
     const uint64_t a = reinterpret_cast<uint64_t>(p);
@@ -91,7 +71,7 @@ __device__ __forceinline__ int32_t table1(const int32_t *p)
 struct DeviceTables {
     int32_t *offT = nullptr;     // start of the one allocation holding every table
     int32_t *baseT = nullptr;
-    int32_t *qcnt = nullptr;     // integer variant 3 only
+    int32_t *qcnt = nullptr;     // integer variant 3: pattern counts; float32: clsF
     int32_t *qoff = nullptr;
     int32_t *offC = nullptr;
 };
@@ -135,11 +115,11 @@ dd_status device_tables(const Plan &p, DeviceTables **out)
     }
     DeviceTables t;
     // integer plans use offT/baseT (variant 3: baseT, qcntT, qoffT, offCT),
-    // float plans offF/baseF; one allocation, each table 256-byte aligned
+    // float plans offF/baseF/clsF; one allocation, each table 256-byte aligned
     const std::vector<int32_t> empty;
     const bool u8 = p.dtype == DD_U8;
     const std::vector<int32_t> *parts[5] = {u8 ? &p.offT : &p.offF, u8 ? &p.baseT : &p.baseF,
-                                            p.subband ? &p.qcntT : &empty,
+                                            !u8 ? &p.clsF : p.subband ? &p.qcntT : &empty,
                                             p.subband ? &p.qoffT : &empty,
                                             p.subband ? &p.offCT : &empty};
     size_t at[5], total = 0;
@@ -833,8 +813,13 @@ k_dedisp_u8_sb(const SbArgs a)
 //                  DM, b = channel) and the adjoint (a = channel, b = DM over
 //                  zero-padded output-gradient rows, S = P - s).  Staging as
 //                  in the integer kernel (direct global-to-LDS loads,
-//                  double-buffered), one float per sample, lane l holding
-//                  t0 + l + 64k; two rows are added per step in a fixed order.
+//                  double-buffered), one float per sample.  Samples are read
+//                  as aligned 16-byte granules (lane l: granules l and
+//                  l + 63); a delay that is not a multiple of 4 takes the
+//                  granule's head from the next lane by a cross-lane move
+//                  folded into the add.  Each output adds a stage's rows in a
+//                  fixed order, grouped by delay mod 4 (a table per output and
+//                  stage), so every group runs one fixed register pattern.
 // k_pad_rows_f32:  the output gradient of one range with P zeros in front.
 // k_adj_finalize:  dX[c][t] = w_c * G[c][t], G summed over ranges at each
 //                  range's resolution, and per-chunk partials of
@@ -844,7 +829,8 @@ k_dedisp_u8_sb(const SbArgs a)
 
 constexpr int kFW = dd::kF32Words;
 constexpr int kFP = dd::kF32PerWave;
-constexpr int kFTileT = dd::kF32TimeTile;
+constexpr int kFTileT = dd::kF32TimeTile;      // 504 samples computed per tile
+constexpr int kFSpan = dd::kF32TileSpan;        // 512 samples the lanes cover
 constexpr int kFTileA = dd::kF32OutTile;
 
 __global__ __launch_bounds__(256) void k_level_f32(const float *__restrict__ src, int64_t src_pitch,
@@ -882,7 +868,8 @@ __global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ 
 
 struct SumArgs {
     const float *src;         // rows, `pitch` floats apart
-    const int32_t *off;       // [nrows][nouts_pad]
+    const int32_t *off;       // [nout_tiles][kF32OutTile][nstages][stage_rows] sorted entries
+    const int32_t *cls;       // [nout_tiles][kF32OutTile][nstages] class ends
     const int32_t *base;      // [nout_tiles][nrows]
     float *dst;               // output rows, `dst_pitch` floats apart
     int64_t pitch;
@@ -895,6 +882,8 @@ struct SumArgs {
     int32_t nout_tiles;
     int32_t stage_rows;
     int32_t row_words;
+    int32_t nstages;
+    int32_t pad_;
 };
 
 struct SumBatch {
@@ -946,6 +935,93 @@ struct BoxArgs {
 
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef int sgpr16 __attribute__((ext_vector_type(16)));
+
+// Sixteen table entries (those of one output and stage; the table is padded
+// so the load stays inside it) and the word at q, by two scalar loads and
+// one wait.
+__device__ __forceinline__ sgpr16 table16_1(const int32_t *p, const int32_t *q, int32_t &w)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint64_t b = reinterpret_cast<uint64_t>(q);
+    const uint32_t alo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t ahi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    const uint32_t blo = __builtin_amdgcn_readfirstlane(uint32_t(b));
+    const uint32_t bhi = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32));
+    const uint64_t pa = (uint64_t(ahi) << 32) | alo;
+    const uint64_t pb = (uint64_t(bhi) << 32) | blo;
+    sgpr16 v;
+    asm volatile("s_load_dwordx16 %0, %2, 0x0\n\ts_load_dword %1, %3, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&s"(v), "=&s"(w)
+                 : "s"(pa), "s"(pb));
+    return v;
+}
+
+// A wave-uniform value copied into a VGPR by an instruction the compiler
+// cannot rematerialise: the entries of a stage then stay in VGPRs while the
+// class loops index them, instead of being copied again from SGPRs before
+// every indexed read.
+__device__ __forceinline__ int to_vgpr(int s)
+{
+    int v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+// Lane l receives lane l + 1's v (lane 63 receives 0); the compiler folds
+// the move into the add that consumes it.
+__device__ __forceinline__ float from_next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                  kDppWaveShl1, 0xF, 0xF, true));
+}
+
+// Sample j of a window that starts R floats into granule g: g[j + R] while
+// inside it, else the head of the next lane's granule.
+template <int R, int J>
+__device__ __forceinline__ float window_at(const f4v g)
+{
+    if constexpr (J + R < 4)
+        return g[J + R];
+    else
+        return from_next_lane(g[J + R - 4]);
+}
+
+template <int R>
+__device__ __forceinline__ void add_window(float *acc, const f4v g)
+{
+    acc[0] += window_at<R, 0>(g);
+    acc[1] += window_at<R, 1>(g);
+    acc[2] += window_at<R, 2>(g);
+    acc[3] += window_at<R, 3>(g);
+}
+
+// The rows of one class (delay mod 4 = R) of one output in one stage:
+// entries [i, end) of its list, each the LDS float offset of the row's
+// first granule.  Two rows per step.
+template <int R>
+__device__ __forceinline__ void add_class(float *acc, const float *A, const int (&ent)[16], int &i,
+                                          int end, int lane)
+{
+    for (; i + 1 < end; i += 2) {
+        const f4v *p = reinterpret_cast<const f4v *>(A + ent[i]) + lane;
+        const f4v *q = reinterpret_cast<const f4v *>(A + ent[i + 1]) + lane;
+        const f4v p0 = p[0], p1 = p[63], q0 = q[0], q1 = q[63];
+        add_window<R>(acc, p0);
+        add_window<R>(acc + 4, p1);
+        add_window<R>(acc, q0);
+        add_window<R>(acc + 4, q1);
+    }
+    if (i < end) {
+        const f4v *p = reinterpret_cast<const f4v *>(A + ent[i]) + lane;
+        const f4v p0 = p[0], p1 = p[63];
+        add_window<R>(acc, p0);
+        add_window<R>(acc + 4, p1);
+        ++i;
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
@@ -972,94 +1048,84 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int Wr = R.row_words;
     const int CW = C * Wr;
     const int nrows = R.nrows;
-    const int npad = R.nouts_pad;
-    const int nst = (nrows + C - 1) / C;
+    const int nst = R.nstages;
+    // the lists of this wave's outputs: [tile][output][stage]
+    const int64_t list0 = int64_t(aw0) * nst;
 
+    // acc[d][k*4 + j]: output aw0 + d at tile sample 4*(lane + 63k) + j
     float acc[kFP][kFW];
 #pragma unroll
-    for (int dd = 0; dd < kFP; ++dd)
+    for (int d = 0; d < kFP; ++d)
 #pragma unroll
         for (int k = 0; k < kFW; ++k)
-            acc[dd][k] = 0.0f;
+            acc[d][k] = 0.0f;
 
     stage_issue_f32(R, tile, t0, 0, min(C, nrows), ldsf, wave, lane);
     for (int st = 0; st < nst; ++st) {
-        const int b0 = st * C;
-        const int bn = min(C, nrows - b0);
         const float *A = ldsf + (st & 1) * CW;
         wait_loads();
         lds_barrier();
         if (st + 1 < nst) {
-            const int bs = b0 + C;
+            const int bs = (st + 1) * C;
             stage_issue_f32(R, tile, t0, bs, min(C, nrows - bs), ldsf + ((st + 1) & 1) * CW,
                             wave, lane);
         }
-        for (int jp = 0; jp < bn; jp += 2) {
-            static_assert(kFP == 4, "offsets are loaded as four ints per row");
-            // the two rows' offsets by scalar loads (a last unpaired row
-            // reads its own offsets twice)
-            const int32_t *oa = R.off + int64_t(b0 + jp) * npad + aw0;
-            sgpr4 a0, b0v;
-            table4x2(oa, oa + (jp + 1 < bn ? npad : 0), a0, b0v);
-            const int offa[kFP] = {a0.x, a0.y, a0.z, a0.w};
-            const float *rowa = A + jp * Wr + lane;
-            if (jp + 1 < bn) {
-                const int offb[kFP] = {b0v.x, b0v.y, b0v.z, b0v.w};
-                const float *rowb = rowa + Wr;
 #pragma unroll
-                for (int dd = 0; dd < kFP; ++dd) {
-                    const float *pa = rowa + offa[dd];
-                    const float *pb = rowb + offb[dd];
+        for (int d = 0; d < kFP; ++d) {
+            const int64_t list = list0 + int64_t(d) * nst + st;
+            int32_t ends_i;
+            const sgpr16 es = table16_1(R.off + list * C, R.cls + list, ends_i);
+            const uint32_t ends = uint32_t(ends_i);
+            int ent[16];
 #pragma unroll
-                    for (int k = 0; k < kFW; ++k)
-                        acc[dd][k] += pa[kWave * k] + pb[kWave * k];
-                }
-            } else {
-#pragma unroll
-                for (int dd = 0; dd < kFP; ++dd) {
-                    const float *pa = rowa + offa[dd];
-#pragma unroll
-                    for (int k = 0; k < kFW; ++k)
-                        acc[dd][k] += pa[kWave * k];
-                }
-            }
+            for (int k = 0; k < 16; ++k)
+                ent[k] = to_vgpr(es[k]);
+            int i = 0;
+            add_class<0>(acc[d], A, ent, i, int(ends & 0xFF), lane);
+            add_class<1>(acc[d], A, ent, i, int((ends >> 8) & 0xFF), lane);
+            add_class<2>(acc[d], A, ent, i, int((ends >> 16) & 0xFF), lane);
+            add_class<3>(acc[d], A, ent, i, int(ends >> 24), lane);
         }
     }
 
+    // lane 63 only supplied the next-lane heads: its sums are not outputs
+    const bool lane_ok = lane < kWave - 1;
     if constexpr (MODE == kWrite) {
+        if (lane_ok) {
 #pragma unroll
-        for (int dd = 0; dd < kFP; ++dd) {
-            const int ao = aw0 + dd;
-            if (ao >= R.nouts)
-                break;
-            float *row = R.dst + int64_t(ao) * R.dst_pitch;
+            for (int d = 0; d < kFP; ++d) {
+                const int ao = aw0 + d;
+                if (ao >= R.nouts)
+                    break;
+                float *row = R.dst + int64_t(ao) * R.dst_pitch;
 #pragma unroll
-            for (int k = 0; k < kFW; ++k) {
-                const int64_t t = t0 + lane + kWave * k;
-                if (t >= 0 && t < R.nt)
-                    row[t] = acc[dd][k];
+                for (int k = 0; k < kFW; ++k) {
+                    const int64_t t = t0 + 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
+                    if (t >= 0 && t < R.nt)
+                        row[t] = acc[d][k];
+                }
             }
         }
     } else {
         lds_barrier();                          // staging rows are no longer read
-        float *rowR = ldsf + wave * (2 * kFTileT);
-        float *rowS = rowR + kFTileT;
+        float *rowR = ldsf + wave * (2 * kFSpan);
+        float *rowS = rowR + kFSpan;
         const int64_t nt = R.nt;
         float part = 0.0f;
-        for (int dd = 0; dd < kFP; ++dd) {
-            const int ao = aw0 + dd;
-            const bool dm_ok = ao < R.nouts;
+        for (int d = 0; d < kFP; ++d) {
+            const int ao = aw0 + d;
+            const bool dm_ok = ao < R.nouts && lane_ok;
             float b[kFW], gsum[kFW];
 #pragma unroll
             for (int k = 0; k < kFW; ++k) {
-                b[k] = acc[dd][k];
+                b[k] = acc[d][k];
                 gsum[k] = 0.0f;
             }
             for (int w = 1; w <= bx.max_width; w *= 2) {
                 if constexpr (MODE == kBoxLoss) {
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int t = lane + kWave * k;
+                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
                         const int64_t tg = t0 + t;
                         if (dm_ok && t < bx.t_stride && tg >= 0 && tg + w <= nt)
                             part += b[k] * b[k];
@@ -1068,18 +1134,19 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                     float c[kFW];
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int64_t tg = t0 + lane + kWave * k;
+                        const int64_t tg = t0 + 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
                         c[k] = (dm_ok && tg >= 0 && tg + w <= nt) ? b[k] : 0.0f;
                     }
                     for (int h = 1; h < w; h *= 2) {
+                        if (lane_ok)
 #pragma unroll
-                        for (int k = 0; k < kFW; ++k)
-                            rowS[lane + kWave * k] = c[k];
+                            for (int k = 0; k < kFW; ++k)
+                                rowS[4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3)] = c[k];
                         lds_wave_sync();
 #pragma unroll
                         for (int k = 0; k < kFW; ++k) {
-                            const int t = lane + kWave * k;
-                            c[k] += t >= h ? rowS[t - h] : 0.0f;
+                            const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
+                            c[k] += (t >= h && t - h < kFTileT) ? rowS[t - h] : 0.0f;
                         }
                         lds_wave_sync();
                     }
@@ -1088,13 +1155,14 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                         gsum[k] += c[k];
                 }
                 if (w < bx.max_width) {
+                    if (lane_ok)
 #pragma unroll
-                    for (int k = 0; k < kFW; ++k)
-                        rowR[lane + kWave * k] = b[k];
+                        for (int k = 0; k < kFW; ++k)
+                            rowR[4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3)] = b[k];
                     lds_wave_sync();
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int t = lane + kWave * k;
+                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
                         b[k] += t + w < kFTileT ? rowR[t + w] : 0.0f;
                     }
                     lds_wave_sync();
@@ -1105,7 +1173,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                     float *row = R.dst + int64_t(ao) * R.dst_pitch;
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int t = lane + kWave * k;
+                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
                         const int64_t tg = t0 + t;
                         if (t >= bx.t_lead && t < bx.t_lead + bx.t_stride && tg >= 0 && tg < nt)
                             row[tg] = 2.0f * gsum[k];
@@ -1114,7 +1182,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
             }
         }
         if constexpr (MODE == kBoxLoss) {
-            float *red = ldsf + kWavesPerBlock * 2 * kFTileT;
+            float *red = ldsf + kWavesPerBlock * 2 * kFSpan;
             red[tid] = part;
             __syncthreads();
             for (int h = kBlock / 2; h > 0; h >>= 1) {
@@ -1615,6 +1683,7 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     std::memset(&R, 0, sizeof(R));
     R.src = src;
     R.off = t.offT + sp.off_offset;
+    R.cls = t.qcnt + sp.cls_offset;
     R.base = t.baseT + sp.base_offset;
     R.dst = dst;
     R.pitch = pitch;
@@ -1627,6 +1696,7 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     R.nout_tiles = sp.nout_tiles;
     R.stage_rows = sp.stage_rows;
     R.row_words = sp.row_words;
+    R.nstages = sp.nstages;
     return R;
 }
 
@@ -1749,7 +1819,7 @@ int64_t box_batch(const Plan &p, const DeviceTables &t, const char *d_ws, float 
 
 size_t box_lds(const Plan &p)
 {
-    return std::max(p.lds_bytes, size_t(kWavesPerBlock * 2 * kFTileT + kBlock) * sizeof(float));
+    return std::max(p.lds_bytes, size_t(kWavesPerBlock * 2 * kFSpan + kBlock) * sizeof(float));
 }
 
 dd_status boxcar_loss_f32(const Plan &p, const DeviceTables &t, const float *d_in, int32_t nbeams,

@@ -82,8 +82,8 @@ void parallel_for(int64_t n, int64_t work_per_item, F fn)
 template <typename SFn>
 dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S,
                             std::vector<int32_t> &offF, std::vector<int32_t> &baseF,
-                            int64_t *blocks, size_t *lds, std::string *err, const char *what,
-                            int32_t want_stage)
+                            std::vector<int32_t> &clsF, int64_t *blocks, size_t *lds,
+                            std::string *err, const char *what, int32_t want_stage)
 {
     sp.nrows = nrows;
     sp.nouts = nouts;
@@ -108,7 +108,9 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         }
     }
     sp.span = span;
-    sp.row_words = (kF32TimeTile + 3 + span + 4 + 3) / 4 * 4;
+    // a delay o <= span + 3 inside the window; lane 63 of the second half
+    // reads the granule at 4*(o >> 2) + 4*126, up to float 4*(o >> 2) + 507
+    sp.row_words = (span + 3 + 4 * 127 + 3) / 4 * 4;
     int32_t stage = want_stage > 0 ? std::max(1, std::min(want_stage, kF32MaxStage)) : kF32MaxStage;
     if (stage > 1)
         stage &= ~1;
@@ -121,21 +123,46 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         return DD_ERR_INVALID;
     }
     sp.stage_rows = stage;
+    sp.nstages = (nrows + stage - 1) / stage;
     *lds = std::max(*lds, bytes_for(stage));
     sp.block_start = *blocks;
     *blocks += sp.ntime_tiles * sp.nout_tiles;
-    sp.off_offset = offF.size();
     sp.base_offset = baseF.size();
-    offF.resize(offF.size() + size_t(nrows) * sp.nouts_pad);
     baseF.resize(baseF.size() + size_t(sp.nout_tiles) * nrows);
     for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
         for (int32_t b = 0; b < nrows; ++b) {
             const int32_t m = mins[size_t(tile) * nrows + b];
-            const int32_t e = m & 3;
-            baseF[sp.base_offset + size_t(tile) * nrows + b] = m - e;
-            for (int32_t a = tile * kF32OutTile; a < (tile + 1) * kF32OutTile; ++a) {
-                const int32_t av = std::min(a, nouts - 1);
-                offF[sp.off_offset + size_t(b) * sp.nouts_pad + a] = e + S(av, b) - m;
+            baseF[sp.base_offset + size_t(tile) * nrows + b] = m - (m & 3);
+        }
+    // Per (tile, output, stage): the stage's rows ordered by the class o & 3
+    // of their delay in the window, so the kernel adds each class with its
+    // own fixed register pattern.  The kernel reads a stage's entries 16 at
+    // a time: the table ends with 16 entries of padding.
+    const size_t nlists = size_t(sp.nout_tiles) * kF32OutTile * size_t(sp.nstages);
+    sp.off_offset = offF.size();
+    offF.resize(offF.size() + nlists * size_t(stage) + 16, 0);
+    sp.cls_offset = clsF.size();
+    clsF.resize(clsF.size() + nlists, 0);
+    for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
+        for (int32_t al = 0; al < kF32OutTile; ++al) {
+            const int32_t av = std::min(tile * kF32OutTile + al, nouts - 1);
+            for (int32_t st = 0; st < sp.nstages; ++st) {
+                const size_t list = (size_t(tile) * kF32OutTile + al) * sp.nstages + st;
+                int32_t *ent = &offF[sp.off_offset + list * stage];
+                const int32_t b0 = st * stage, bn = std::min(stage, nrows - b0);
+                int32_t n = 0;
+                uint32_t ends = 0;
+                for (int32_t cls = 0; cls < 4; ++cls) {
+                    for (int32_t j = 0; j < bn; ++j) {
+                        const int32_t b = b0 + j;
+                        const int32_t m = mins[size_t(tile) * nrows + b];
+                        const int32_t o = (m & 3) + S(av, b) - m;
+                        if ((o & 3) == cls)
+                            ent[n++] = j * sp.row_words + 4 * (o >> 2);
+                    }
+                    ends |= uint32_t(n) << (8 * cls);
+                }
+                clsF[sp.cls_offset + list] = int32_t(ends);
             }
         }
     return DD_OK;
@@ -164,6 +191,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     p->levels.clear();
     p->offF.clear();
     p->baseF.clear();
+    p->clsF.clear();
     int64_t blocks = 0, ablocks = 0;
     size_t lds = 0, alds = 0;
     for (int32_t r = 0; r < int32_t(p->ranges.size()); ++r) {
@@ -171,7 +199,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
         auto Sf = [&](int32_t a, int32_t b) { return sh[size_t(a) * nchans + b]; };
         dd_status st = build_sum_problem(ri.fwd, nchans, ri.ndms, ri.nout, Sf, p->offF, p->baseF,
-                                         &blocks, &lds, err, "forward", want_stage);
+                                         p->clsF, &blocks, &lds, err, "forward", want_stage);
         if (st != DD_OK)
             return st;
     }
@@ -181,7 +209,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t P = ri.max_shift;
         auto Sa = [&](int32_t a, int32_t b) { return P - sh[size_t(b) * nchans + a]; };
         dd_status st = build_sum_problem(ri.adj, ri.ndms, nchans, ri.nbin, Sa, p->offF, p->baseF,
-                                         &ablocks, &alds, err, "adjoint", want_stage);
+                                         p->clsF, &ablocks, &alds, err, "adjoint", want_stage);
         if (st != DD_OK)
             return st;
     }

@@ -43,21 +43,27 @@ constexpr size_t kWsAlign = 256;
 // used for the forward (a = DM, b = channel, rows = weighted binned input,
 // S = s) and for the adjoint (a = channel, b = DM, rows = the output
 // gradient with P zeros on both sides, S = P - s).  A workgroup owns
-// kF32OutTile outputs (8 per wave) by kF32TimeTile samples (lane l holds
-// t0 + l + 64k, k < kF32Words).
-constexpr int kF32Words = 8;
+// kF32OutTile outputs (kF32PerWave per wave) by kF32TimeTile samples.
+// Samples come from LDS in aligned 4-float granules (one 16-byte read
+// each): lane l holds granules l and l + 63 of the tile, i.e. samples
+// 4(l + 63k) + j (k < 2, j < 4).  A delay that is not a multiple of 4 takes
+// the granule's tail from the lane itself and its head from the next lane
+// (a cross-lane move fused into the add); lane 63 only supplies that head,
+// so a tile is 63 granules x 2 = 504 samples wide and the lanes span 512.
+constexpr int kF32Words = 8;                     // samples per lane
 constexpr int kF32PerWave = 4;
-constexpr int kF32TimeTile = 64 * kF32Words;
+constexpr int kF32TileSpan = 64 * kF32Words;     // 512: samples the lanes cover
+constexpr int kF32TimeTile = 63 * kF32Words;     // 504: samples a tile computes
 constexpr int kF32OutTile = kWaves * kF32PerWave;
 constexpr int kF32MaxStage = 16;
 // Boxcar loss tiles: the loss tile counts windows starting in its first
 // kBoxLossStride samples; the gradient tile writes dL/dout for its samples
 // [kBoxLead, kBoxLead + kBoxGradStride).  Both keep the 31-sample reach of
-// the widest (32-sample) window inside the 512-sample tile.
+// the widest (32-sample) window inside the 504-sample tile.
 constexpr int kBoxMaxWidth = 32;
-constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 480
+constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 472
 constexpr int kBoxLead = kBoxMaxWidth;                                // 32
-constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 448
+constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 440
 
 struct SumProblem {
     int32_t nrows = 0;          // b: rows summed
@@ -70,9 +76,18 @@ struct SumProblem {
     int32_t nouts_pad = 0;      // nout_tiles * kF32OutTile
     int64_t ntime_tiles = 0;
     int64_t block_start = 0;
-    size_t off_offset = 0;      // offF: [nrows][nouts_pad] = e + S[a][b] - m
-    size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e, with
-                                // m = min over the tile of S[.][b], e = m & 3
+    int32_t nstages = 0;        // ceil(nrows / stage_rows)
+    // With m = min over the output tile of S[.][b], e = m & 3 and
+    // o = e + S[a][b] - m (the delay inside the staged window):
+    size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e
+    size_t off_offset = 0;      // offF: [nout_tiles][kF32OutTile][nstages][stage_rows]:
+                                // for output a and stage s, the stage's rows
+                                // ordered by o & 3 (stable), each entry
+                                // slot * row_words + 4 * (o >> 2) (slot = the
+                                // row's place in the stage's LDS buffer)
+    size_t cls_offset = 0;      // clsF: [nout_tiles][kF32OutTile][nstages]:
+                                // where each class o & 3 = 0, 1, 2, 3 ends in
+                                // that list, one byte each (low byte first)
 };
 
 // One 16-bit copy of the input, binned by ds (ds = 1: the samples widened
@@ -183,6 +198,7 @@ struct Plan {
     // then adjoint problems), and the adjoint's reduction buffer.
     std::vector<int32_t> offF;
     std::vector<int32_t> baseF;
+    std::vector<int32_t> clsF;
     int64_t adj_blocks = 0;
     size_t adj_lds_bytes = 0;
     int32_t dw_chunks = 0;                 // time chunks of the weight-gradient reduction
