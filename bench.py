@@ -30,6 +30,9 @@ UNIT = "DM-trial·samples/s"
 # Integer-add roof: 256 CUs x 64 lanes x 2.4 GHz x 2 adds per lane-cycle
 # (one v_add3_u32), i.e. 78.6 T adds/s.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# float32 adds without packed-FP32 instructions (this build disables them):
+# one add per lane-cycle, 39.3 T adds/s.
+F32_ADD_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 FETCH_SIZE/WRITE_SIZE summary of the shift-and-sum kernel, per kernel
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "{kernel}_ska-4096ch_traffic.json")
@@ -82,11 +85,31 @@ def measured_traffic(kernel):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(w, x, target_s: float):
-    """Time the C oracle on a bounded sample of the workload: the first DM
-    trials of the native-resolution range, all channels and samples."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, x, target_s: float, runs: int = 3):
+    """Time the C oracle (as it stands) on the host cores: a bounded sample
+    of the SKA-like workload -- the first DM trials of its native-resolution
+    range, all channels and samples -- sized to about target_s seconds per
+    run, median of `runs` runs; the whole tiny workload, median of `runs`;
+    and a few DM trials on one thread."""
+    import statistics
+
     from oracle import cref
     from oracle import dedisp as O
+
+    import synth
 
     rg = w.ranges[0]
     plan = O.expand_plan(w.freqs, w.tsamp, w.nsamp, [rg])
@@ -98,10 +121,24 @@ def cpu_baseline(w, x, target_s: float):
     cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n, nout)
     dt = time.perf_counter() - t
     n = int(min(len(plan[0].dms), max(n, n * target_s / max(dt, 1e-3))))
-    log(f"cpu baseline: {n} DM trials on {threads} threads")
-    t = time.perf_counter()
-    cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n, nout)
-    dt = time.perf_counter() - t
+    log(f"cpu baseline: {n} DM trials on {threads} threads, {runs} runs")
+    times = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n, nout)
+        times.append(time.perf_counter() - t)
+    dt = statistics.median(times)
+    # the whole tiny workload (128 channels, 2^16 samples, DM 0..99)
+    tw = synth.tiny()
+    tx = tw.make_input()
+    tiny_samples = int(sum(r.nout * len(r.dms)
+                           for r in O.expand_plan(tw.freqs, tw.tsamp, tw.nsamp, tw.ranges)))
+    cref.dedisperse_u8(tx, tw.freqs, tw.tsamp, tw.ranges)
+    ttimes = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        cref.dedisperse_u8(tx, tw.freqs, tw.tsamp, tw.ranges)
+        ttimes.append(time.perf_counter() - t)
     # the same oracle on one thread, over a few DM trials (about 3 s)
     t = time.perf_counter()
     cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, 1, nout, threads=1)
@@ -110,13 +147,81 @@ def cpu_baseline(w, x, target_s: float):
     cref.dedisperse_u8_rows(x, w.freqs, w.tsamp, rg, 0, n1, nout, threads=1)
     dt1 = time.perf_counter() - t
     return {"value": n * nout / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "seconds": round(dt, 3),
+            "cpu_model": cpu_model(), "runs": runs,
+            "seconds_median": round(dt, 3), "seconds_runs": [round(v, 3) for v in times],
             "sample": (f"DM trials 0..{n - 1} of the native-resolution range (DM 0-150 step "
                        f"0.1), all {w.nchans} channels, all {nout} output samples; plain C "
-                       f"oracle, OpenMP over DM trials"),
+                       f"oracle, OpenMP over DM trials; median of {runs} runs"),
+            "tiny_whole": {"workload": tw.name, "dm_trial_samples": tiny_samples,
+                           "seconds_median": round(statistics.median(ttimes), 4),
+                           "value": tiny_samples / statistics.median(ttimes),
+                           "threads": threads},
             "single_thread_value": n1 * nout / dt1,
             "single_thread_sample": f"DM trials 0..{n1 - 1} of the same range on 1 thread "
                                     f"({dt1:.2f} s)"}
+
+
+class SclkSampler:
+    """Samples the GPU's current shader clock while a region runs: the
+    starred level of the amdgpu driver's pp_dpm_sclk file, every 20 ms, on a
+    background thread (reads only).  If no such file is readable,
+    rocm-smi's clock report is taken once at the end instead."""
+
+    def __init__(self):
+        import glob
+        self.files = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.samples = []
+        self._stop = None
+        self._thread = None
+
+    def _read(self):
+        for f in self.files:
+            try:
+                with open(f) as fh:
+                    for line in fh:
+                        if line.rstrip().endswith("*"):
+                            m = re.search(r"(\d+)\s*Mhz", line, re.I)
+                            if m:
+                                return int(m.group(1))
+            except OSError:
+                continue
+        return None
+
+    def __enter__(self):
+        import threading
+        self._stop = threading.Event()
+
+        def run():
+            while not self._stop.is_set():
+                v = self._read()
+                if v is not None:
+                    self.samples.append(v)
+                self._stop.wait(0.02)
+
+        if self.files:
+            self._thread = threading.Thread(target=run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread:
+            self._stop.set()
+            self._thread.join()
+
+    def report(self):
+        if self.samples:
+            s = sorted(self.samples)
+            return {"source": "pp_dpm_sclk", "mhz_median": s[len(s) // 2], "mhz_min": s[0],
+                    "mhz_max": s[-1], "samples": len(s)}
+        import subprocess
+        try:
+            r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                               timeout=20)
+            m = re.findall(r"sclk.*?\((\d+)\s*Mhz\)", r.stdout, re.I)
+            return {"source": "rocm-smi --showclocks (after the timed region)",
+                    "mhz": [int(v) for v in m] or None}
+        except (OSError, subprocess.SubprocessError):
+            return {"source": "unavailable"}
 
 
 def _time(torch, fn, n):
@@ -131,7 +236,19 @@ def _time(torch, fn, n):
     return sorted(ts)[len(ts) // 2]
 
 
-def leg_fwdbwd(dd, synth, torch, plain_value):
+def add_rate(adds, ms):
+    """Adds per second (T) and the fractions of the two add roofs."""
+    tops = adds / (ms / 1e3) / 1e12
+    return {"t_adds_per_s": tops, "frac": tops / ALU_PEAK_TOPS,
+            "frac_f32_unpacked": tops / F32_ADD_PEAK_TOPS}
+
+
+def plan_adds(plan):
+    """Brute-force adds of one forward: nchans per DM-trial·sample."""
+    return sum(r.ndms * r.nout for r in plan.ranges) * plan.nchans
+
+
+def leg_fwdbwd(dd, synth, torch, plain_value, plain_rate, reps):
     """Differentiable workload (1024 ch float32, 2^16 samples, DM 0..511):
     forward with weights, then the hand-written adjoint (dX and dw)."""
     w = synth.differentiable()
@@ -145,24 +262,35 @@ def leg_fwdbwd(dd, synth, torch, plain_value):
                     generator=torch.Generator("cuda").manual_seed(w.seed))
     dd.adjoint(g, plan, x=x, weights=wt, ws=ws)
     torch.cuda.synchronize()
-    f_ms = _time(torch, lambda: dd.dedisperse(x, plan, out=out, weights=wt, ws=ws), 5)
-    b_ms = _time(torch, lambda: dd.adjoint(g, plan, x=x, weights=wt, ws=ws), 5)
+    f_ms = _time(torch, lambda: dd.dedisperse(x, plan, out=out, weights=wt, ws=ws), reps)
+    b_ms = _time(torch, lambda: dd.adjoint(g, plan, x=x, weights=wt, ws=ws), reps)
     samples = plan.out_elems
+    adds = plan_adds(plan)
     v = samples / ((f_ms + b_ms) / 1e3)
-    return {"workload": w.name, "fwd_ms": f_ms, "bwd_ms": b_ms,
+    fb = add_rate(2 * adds, f_ms + b_ms)
+    return {"workload": w.name, "reps": reps, "fwd_ms": f_ms, "bwd_ms": b_ms,
             "fwd_dm_trial_samples_per_s": samples / (f_ms / 1e3),
             "fwd_bwd_dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
-            "note": "float32; plain = the uint8 single-beam value of this line"}
+            "adds_per_fwd": adds, "fwd": add_rate(adds, f_ms), "bwd": add_rate(adds, b_ms),
+            "fwd_bwd": fb, "fwd_bwd_adds_vs_plain_single_beam": fb["t_adds_per_s"] / plain_rate,
+            "note": ("float32 (1024 ch) against the uint8 (4096 ch) single beam of this line: "
+                     "per DM-trial·sample the work differs by the channel count, so the add "
+                     "rates (fwd and adjoint each nchans adds per DM-trial·sample) compare "
+                     "like with like")}
 
 
-def leg_batched(dd, synth, torch, plain_value, opts):
-    """64 uint8 beams of uneven shape in one persistent launch per kernel (inputs drawn
-    on the GPU, excluded from timing)."""
+def leg_batched(dd, synth, torch, plain_value, plain_rate, reps, tuner):
+    """64 uint8 beams of uneven shape, each with its own tuned strategy (the
+    tuner's per-plan-class table: channel count, sampling time, DM plan),
+    summed by one persistent launch per kernel; inputs drawn on the GPU,
+    excluded from timing."""
     wls = synth.batched_beams()
     log("leg batched:", len(wls), "beams")
-    # the single beam's tuned strategy for every beam
-    o = {k: v for k, v in opts.items() if k in ("variant", "dm_tile", "stage_chans")}
-    plans = [dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **o) for w in wls]
+    plans, sources = [], {}
+    for w in wls:
+        opts, src = tuner.class_strategy(w.freqs, w.tsamp, w.ranges)
+        sources[src] = sources.get(src, 0) + 1
+        plans.append(dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, **opts))
     batch = dd.Batch(plans)
     batch.prepare()
     xin = torch.empty(batch.in_bytes, dtype=torch.uint8, device="cuda")
@@ -173,21 +301,31 @@ def leg_batched(dd, synth, torch, plain_value, opts):
     ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
     dd.dedisperse_batch(xin, batch, out=out, ws=ws)
     torch.cuda.synchronize()
-    ms = _time(torch, lambda: dd.dedisperse_batch(xin, batch, out=out, ws=ws), 3)
+    ms = _time(torch, lambda: dd.dedisperse_batch(xin, batch, out=out, ws=ws), reps)
     samples = sum(p.out_elems for p in plans)
+    adds = sum(plan_adds(p) for p in plans)
     v = samples / (ms / 1e3)
+    mix = {}
+    for p in plans:
+        k = f"variant {p.strategy['variant']}, dm_tile {p.strategy['dm_tile']}, " \
+            f"stage {p.strategy['chans_stage']}"
+        mix[k] = mix.get(k, 0) + 1
+    rate = add_rate(adds, ms)
     res = {"workload": f"{len(wls)} uint8 beams, 1024-4096 ch, 2^16-2^18 samples, DM max "
-                       "500/1000/2000", "ms": ms, "dm_trial_samples": samples,
+                       "500/1000/2000", "reps": reps, "ms": ms, "dm_trial_samples": samples,
            "dm_trial_samples_per_s": v, "vs_plain_single_beam": v / plain_value,
-           "strategy": plans[0].strategy,
-           "work_items": batch.work_items, "launches": "bins per beam + %d persistent" % len(
-               {(p.strategy["variant"], p.strategy["dm_tile"]) for p in plans})}
+           "adds": adds, **rate, "adds_vs_plain_single_beam": rate["t_adds_per_s"] / plain_rate,
+           "strategy_mix": mix, "strategy_sources": sources,
+           "groups": [{k: g[k] for k in ("variant", "dm_tile", "work_items")}
+                      for g in batch.groups],
+           "work_items": batch.work_items,
+           "launches": "binning per beam + %d persistent" % len(batch.groups)}
     del xin, out, ws
     batch.close()
     return res
 
 
-def leg_boxcar(dd, synth, torch):
+def leg_boxcar(dd, synth, torch, reps):
     """32 float32 beams x 4096 ch x 2^17, DM 0..999: boxcar loss (out never
     stored) and its backward (out recomputed, adjoint)."""
     wls = synth.batched_differentiable()
@@ -203,15 +341,20 @@ def leg_boxcar(dd, synth, torch):
     ws = dd.workspace(plan)
     dd.boxcar_loss(x, plan, wt, ws=ws)
     torch.cuda.synchronize()
-    l_ms = _time(torch, lambda: dd.boxcar_loss(x, plan, wt, ws=ws), 1)
+    l_ms = _time(torch, lambda: dd.boxcar_loss(x, plan, wt, ws=ws), reps)
     dx, dw = dd.boxcar_backward(x, plan, wt, ws=ws)
     torch.cuda.synchronize()
-    b_ms = _time(torch, lambda: dd.boxcar_backward(x, plan, wt, ws=ws), 1)
+    b_ms = _time(torch, lambda: dd.boxcar_backward(x, plan, wt, ws=ws), reps)
     samples = plan.out_elems * len(wls)
+    adds = plan_adds(plan) * len(wls)
     return {"workload": f"{len(wls)} float32 beams x 4096 ch x 2^17, DM 0..999, boxcar 1..32",
-            "loss_ms": l_ms, "backward_ms": b_ms,
+            "reps": reps, "loss_ms": l_ms, "backward_ms": b_ms,
             "fwd_dm_trial_samples_per_s": samples / (l_ms / 1e3),
-            "fwd_bwd_dm_trial_samples_per_s": samples / ((l_ms + b_ms) / 1e3)}
+            "fwd_bwd_dm_trial_samples_per_s": samples / ((l_ms + b_ms) / 1e3),
+            "adds_per_forward": adds, "loss": add_rate(adds, l_ms),
+            "backward": add_rate(2 * adds, b_ms),
+            "note": "the backward recomputes the forward and runs the adjoint: 2x the forward's "
+                    "adds"}
 
 
 def main() -> int:
@@ -219,7 +362,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=7.0,
+                    help="seconds of one run of the CPU oracle's sample (3 runs)")
+    ap.add_argument("--reps", type=int, default=20,
+                    help="repetitions of the float32 single-beam legs (median)")
+    ap.add_argument("--reps-large", type=int, default=5,
+                    help="repetitions of the batched and boxcar legs (median)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default strategy")
     ap.add_argument("--retune", action="store_true",
@@ -288,13 +436,14 @@ def main() -> int:
     log("timing", args.steps, "steps")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        dd.dedisperse(xt, plan, out=out, ws=ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall
+    with SclkSampler() as sclk:
+        wall = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            dd.dedisperse(xt, plan, out=out, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall
     ms_step = e0.elapsed_time(e1) / args.steps
 
     # The dominant kernel alone (dd_forward_sum is one launch of the
@@ -345,14 +494,26 @@ def main() -> int:
         "x_realtime": realtime,
         "x_realtime_full_chunk": w.nsamp * w.tsamp / (ms_step / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                     "unit": "T adds/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                     "achieved_is": ("brute-force-equivalent adds (nchans per DM-trial·sample, "
+                                     "2.198e12 per launch) / the kernel's mean launch time; "
+                                     "the sub-band kernel performs fewer, packed adds, so this "
+                                     "is time against the brute-force floor, not VALU "
+                                     "occupancy"),
+                     "brute_force_equivalent_frac": achieved / ALU_PEAK_TOPS,
                      "kernel": kernel, "kernel_ms": ms_sum,
                      "adds_per_launch": adds, "algorithmic_bytes_per_launch": alg_bytes,
                      "algorithmic_hbm_gbs": alg_bytes / (ms_sum / 1e3) / 1e9,
+                     "algorithmic_hbm_frac": alg_bytes / (ms_sum / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "hbm_frac_of_peak": (traffic / (ms_sum / 1e3) / 1e9 / HBM_PEAK_GBS
-                                          if traffic else None)},
+                                          if traffic else None),
+                     "hbm_note": ("the HBM fraction of peak: measured DRAM bytes (rocprofv3 "
+                                  "FETCH_SIZE + WRITE_SIZE, copy-calibrated) / kernel time / "
+                                  "8 TB/s; the kernel is bound by its adds and LDS traffic, "
+                                  "not by HBM")},
         "steps_ms": {"bin": ms_bin, "sum": ms_sum, "plan_create_s": t_plan,
                      "table_upload_s": t_upload, "wall_s": wall},
+        "sclk": sclk.report(),
         "strategy": plan.strategy,
         "tuning": tune_info,
     }
@@ -360,14 +521,15 @@ def main() -> int:
     torch.cuda.empty_cache()
     legs = [] if args.legs in ("", "none") else args.legs.split(",")
     if "fwdbwd" in legs:
-        res["fwd_bwd"] = leg_fwdbwd(dd, synth, torch, value)
+        res["fwd_bwd"] = leg_fwdbwd(dd, synth, torch, value, achieved, args.reps)
     if "batched" in legs:
         del xt
         torch.cuda.empty_cache()
-        res["batched"] = leg_batched(dd, synth, torch, value, opts)
+        from paper_1912_07704_amd import tune as tuner
+        res["batched"] = leg_batched(dd, synth, torch, value, achieved, args.reps_large, tuner)
     if "boxcar" in legs:
         torch.cuda.empty_cache()
-        res["boxcar"] = leg_boxcar(dd, synth, torch)
+        res["boxcar"] = leg_boxcar(dd, synth, torch, args.reps_large)
     if args.copy_gib > 0:
         n = int(args.copy_gib * (1 << 30))
         src = torch.empty(n, dtype=torch.uint8, device=dev)

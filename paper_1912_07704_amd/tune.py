@@ -1,10 +1,14 @@
-"""Autotuner of the integer forward's strategy (paper, "Design of the API":
-the strategy decides how input data are split and processed on the GPU).
+"""Autotuner of the forward's strategy (paper, "Design of the API": the
+strategy decides how input data are split and processed on the GPU).
 
-For one plan signature it times the shift-and-sum step of every candidate
-strategy -- kernel variant x DM tile x channels per LDS stage -- on the
-current device, checks that every candidate's output is bit-identical to
-the first one's, and keeps the fastest.  Results are cached per (plan
+For one integer plan signature it times the shift-and-sum step of every
+candidate strategy -- kernel variant x DM tile (which fixes the time tile:
+256 samples for 16-wavefront workgroups, 512 for 8) x channels per LDS
+stage -- on the current device, checks that every candidate's output is
+bit-identical to the first one's, and keeps the fastest.  Beams of one plan
+class (same band, sampling and DM plan, any length) share one tuned
+strategy (class_strategy).  Float32 plans tune the rows per LDS stage of
+the forward plus adjoint (tune_f32).  Results are cached per (plan
 signature, device) in a JSON file (``DD_TUNE_CACHE``, default
 ``~/.cache/paper_1912_07704_amd/tune.json``).  A table of strategies
 measured on MI355X for the standard workloads ships with the package
@@ -21,6 +25,7 @@ import statistics
 from . import DDError, Plan, dedisperse, workspace
 
 DD_ERR_INVALID = -2
+DD_ERR_EMPTY_OUTPUT = -3
 
 VARIANTS = (1, 2)
 DM_TILES = (64, 32)
@@ -144,6 +149,110 @@ def tune(freqs, tsamp, nsamp, ranges, x=None, reps: int = 3, cands=None, use_cac
         del ws, out
     if best is None:
         raise RuntimeError("no feasible strategy")
+    if use_cache:
+        cache = _load()
+        cache[sig] = {"best": best[0], "timings": timings}
+        _store(cache)
+    return best[0], timings
+
+
+def class_signature(freqs, tsamp, ranges, dtype="u8", device=None) -> str:
+    """Signature of a plan class: the channel frequencies, sampling time, DM
+    plan and device, without the series length (beams of one class differ
+    only in length, which does not move the best strategy)."""
+    import numpy as np
+    dev = device or device_arch()
+    f = np.ascontiguousarray(freqs, dtype=np.float64)
+    key = json.dumps({"class": True, "freqs": hashlib.sha1(f.tobytes()).hexdigest(),
+                      "nchans": int(f.size), "tsamp": float(tsamp),
+                      "ranges": [[float(a), float(b), float(c), int(d)] for a, b, c, d in ranges],
+                      "dtype": dtype, "device": dev}, sort_keys=True)
+    return hashlib.sha1(key.encode()).hexdigest()
+
+
+def class_strategy(freqs, tsamp, ranges, nsamp_probe: int = 1 << 17, reps: int = 3,
+                   use_cache: bool = True):
+    """(best options, source) for a plan class: from the user cache or the
+    shipped table, else tuned now on a seeded input of nsamp_probe samples
+    (doubled until every range has output) and cached."""
+    sig = class_signature(freqs, tsamp, ranges)
+    if use_cache:
+        hit = lookup(sig)
+        if hit:
+            return hit[0], hit[2]
+    nsamp = int(nsamp_probe)
+    while True:
+        try:
+            Plan(freqs, tsamp, nsamp, ranges, "u8").close()
+            break
+        except DDError as e:
+            if e.status != DD_ERR_EMPTY_OUTPUT or nsamp >= 1 << 24:
+                raise
+            nsamp *= 2
+    best, timings = tune(freqs, tsamp, nsamp, ranges, reps=reps, use_cache=False)
+    if use_cache:
+        cache = _load()
+        cache[sig] = {"best": best, "timings": timings, "probe_nsamp": nsamp}
+        _store(cache)
+    return best, "measured"
+
+
+# float32 plans: rows staged in LDS per step (the LDS budget may lower it)
+F32_STAGES = (16, 12, 8, 4, 2)
+
+
+def tune_f32(freqs, tsamp, nsamp, ranges, reps: int = 5, stages=F32_STAGES, use_cache=True):
+    """Time the float32 forward plus adjoint of every stage size on the
+    device and return (best options, [(options, median ms), ...]).  Stage
+    sizes change the order of the float32 sums, so each candidate's forward
+    must agree with the first one's within 1e-5 normwise (the float32
+    tolerance) instead of bit for bit.  Cached like tune()."""
+    import torch
+    from . import adjoint
+    sig = signature(freqs, tsamp, nsamp, ranges, dtype="f32")
+    if use_cache:
+        hit = lookup(sig)
+        if hit:
+            return hit[0], hit[1]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.randn((len(freqs), nsamp), generator=g, device="cuda")
+    timings, ref, best, seen = [], None, None, set()
+    for st in stages:
+        plan = Plan(freqs, tsamp, nsamp, ranges, "f32", stage_chans=st)
+        key = plan.strategy["chans_stage"]
+        if key in seen:                  # clamped to a stage size already timed
+            plan.close()
+            continue
+        seen.add(key)
+        ws = workspace(plan, x.device)
+        out = dedisperse(x, plan, ws=ws)
+        gout = torch.randn(plan.out_elems, generator=g, device="cuda")
+        adjoint(gout, plan, x=x, ws=ws)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        else:
+            nw = float((out - ref).abs().max() / ref.abs().max().clamp_min(1e-30))
+            if nw > 1e-5:
+                raise RuntimeError(f"stage {st} moved the float32 forward by {nw:.2e} normwise")
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            dedisperse(x, plan, out=out, ws=ws)
+            adjoint(gout, plan, x=x, ws=ws)
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        med = statistics.median(ms)
+        opts = {"stage_chans": key}
+        timings.append((opts, med))
+        if best is None or med < best[1]:
+            best = (opts, med)
+        plan.close()
+        del ws, out, gout
     if use_cache:
         cache = _load()
         cache[sig] = {"best": best[0], "timings": timings}
