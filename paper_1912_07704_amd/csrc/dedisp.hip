@@ -893,22 +893,39 @@ struct SumBatch {
     int32_t nprob;
 };
 
-__device__ __forceinline__ void stage_issue_f32(const SumArgs &R, int tile, int64_t t0, int bs,
+typedef int sgpr16 __attribute__((ext_vector_type(16)));
+
+// The fields of a problem the stage loop reads, held in registers (read
+// through the kernel-argument reference they would be loaded again after
+// every direct-to-LDS load, which the compiler takes for a possible write).
+struct StageSrc {
+    const float *src;
+    const int32_t *base;
+    int64_t pitch;
+    int32_t nrows;
+    int32_t row_words;
+};
+
+__device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int64_t t0, int bs,
                                                 int bn, float *buf, int wave, int lane)
 {
-    const int Wr = R.row_words;
+    const int Wr = S.row_words;
     const int chunks = Wr >> 2;
     const int ipr = (chunks + kWave - 1) / kWave;
+    int jl = -1;
+    int32_t m = 0;
     for (int i = wave; i < bn * ipr; i += kWavesPerBlock) {
         const int j = i / ipr;
         const int part = i - j * ipr;
         const int q = part * kWave + lane;
-        const int64_t b = bs + j;
-        // (a scalar load: a vector load's wait would also wait for the
-        // staging loads in flight)
-        const int32_t m = table1(R.base + int64_t(tile) * R.nrows + b);
+        // (a scalar load, once per row: a vector load's wait would also wait
+        // for the staging loads in flight)
+        if (j != jl) {
+            m = table1(S.base + int64_t(tile) * S.nrows + bs + j);
+            jl = j;
+        }
         if (q < chunks) {
-            const float *g = R.src + b * R.pitch + t0 + m + 4 * q;
+            const float *g = S.src + int64_t(bs + j) * S.pitch + t0 + m + 4 * q;
             __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
         }
     }
@@ -936,7 +953,6 @@ struct BoxArgs {
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef int sgpr16 __attribute__((ext_vector_type(16)));
 
 // Sixteen table entries (those of one output and stage; the table is padded
 // so the load stays inside it) and the word at q, by two scalar loads and
@@ -1051,6 +1067,9 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int nst = R.nstages;
     // the lists of this wave's outputs: [tile][output][stage]
     const int64_t list0 = int64_t(aw0) * nst;
+    const StageSrc S = {R.src, R.base, R.pitch, nrows, Wr};
+    const int32_t *const off_tab = R.off;
+    const int32_t *const cls_tab = R.cls;
 
     // acc[d][k*4 + j]: output aw0 + d at tile sample 4*(lane + 63k) + j
     float acc[kFP][kFW];
@@ -1060,21 +1079,21 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         for (int k = 0; k < kFW; ++k)
             acc[d][k] = 0.0f;
 
-    stage_issue_f32(R, tile, t0, 0, min(C, nrows), ldsf, wave, lane);
+    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane);
     for (int st = 0; st < nst; ++st) {
         const float *A = ldsf + (st & 1) * CW;
         wait_loads();
         lds_barrier();
         if (st + 1 < nst) {
             const int bs = (st + 1) * C;
-            stage_issue_f32(R, tile, t0, bs, min(C, nrows - bs), ldsf + ((st + 1) & 1) * CW,
+            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf + ((st + 1) & 1) * CW,
                             wave, lane);
         }
 #pragma unroll
         for (int d = 0; d < kFP; ++d) {
             const int64_t list = list0 + int64_t(d) * nst + st;
             int32_t ends_i;
-            const sgpr16 es = table16_1(R.off + list * C, R.cls + list, ends_i);
+            const sgpr16 es = table16_1(off_tab + list * C, cls_tab + list, ends_i);
             const uint32_t ends = uint32_t(ends_i);
             int ent[16];
 #pragma unroll
@@ -1494,39 +1513,179 @@ __global__ __launch_bounds__(256) void k_bin_fused_u8(const uint8_t *__restrict_
     }
 }
 
-dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t stream)
+// ---------------------------------------------------------------------------
+// Power-of-two levels (ds = 1, 2, 4, 8, 16) of rows of any length and any
+// byte alignment, for many beams in one launch.  A block takes one segment
+// of kBinSeg samples of one row: it copies the segment's bytes into LDS with
+// aligned 4-byte loads from the aligned-down address (no load starts past
+// the input's end), and each thread realigns its 16 samples with
+// v_alignbyte and forms the levels as k_bin_fused_u8 does.  A row's last,
+// partial group writes only the bins that lie inside the row.
+// ---------------------------------------------------------------------------
+
+constexpr int kBinSeg = 4096;
+constexpr int kBinThreads = kBinSeg / 16;
+
+struct BinJob {
+    int64_t in_off;           // bytes into the input buffer: row 0 of this beam
+    int64_t nsamp;
+    int64_t ws_off[5];        // bytes into the workspace of level ds = 2^k, or -1
+    int64_t pitch[5];         // samples per row of each level
+    int64_t block_start;      // first block of this job in the launch
+    int32_t nchans;
+    int32_t nseg;             // segments per row
+};
+
+// Level K's bins of one 16-sample group: 16 >> K bins, two per word (K < 4)
+// or one (K = 4).  A whole group is stored with one vector store; the row's
+// last, partial group stores only the bins that lie inside the row.
+template <int K>
+__device__ __forceinline__ void store_level(const BinJob &J, char *ws, int64_t row, int64_t g0,
+                                            bool full, const uint32_t *v)
 {
-    // Levels ds = 1, 2, 4, 8, 16 in one pass over the raw input when the
-    // rows allow 16-byte loads; every other level from its source level (or
-    // the raw input), in increasing downsample order.
-    std::vector<bool> done(p.levels.size(), false);
-    if (p.nsamp % 16 == 0 && reinterpret_cast<uintptr_t>(d_in) % 16 == 0) {
-        FusedLevels L;
-        std::memset(&L, 0, sizeof(L));
-        bool any = false;
-        for (size_t i = 0; i < p.levels.size(); ++i) {
-            const dd::BinLevel &lv = p.levels[i];
-            for (int k = 0; k < 5; ++k)
-                if (lv.ds == (1 << k)) {
-                    L.dst[k] = reinterpret_cast<uint16_t *>(d_ws + lv.ws_offset);
-                    L.pitch[k] = lv.pitch;
-                    done[i] = any = true;
-                }
+    if (J.ws_off[K] < 0)
+        return;
+    uint16_t *o = reinterpret_cast<uint16_t *>(ws + J.ws_off[K]) + row * J.pitch[K] + (g0 >> K);
+    if (full) {
+        if constexpr (K == 0) {
+            reinterpret_cast<uint4 *>(o)[0] = make_uint4(v[0], v[1], v[2], v[3]);
+            reinterpret_cast<uint4 *>(o)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+        } else if constexpr (K == 1) {
+            *reinterpret_cast<uint4 *>(o) = make_uint4(v[0], v[1], v[2], v[3]);
+        } else if constexpr (K == 2) {
+            *reinterpret_cast<uint2 *>(o) = make_uint2(v[0], v[1]);
+        } else if constexpr (K == 3) {
+            *reinterpret_cast<uint32_t *>(o) = v[0];
+        } else {
+            *o = uint16_t(v[0]);
         }
-        if (any) {
-            const int64_t ng = p.nsamp / 16;
-            const dim3 grid(unsigned(std::min<int64_t>((ng + 255) / 256, 1024)),
-                            unsigned(std::min<int32_t>(p.nchans, 65535)));
-            hipLaunchKernelGGL(k_bin_fused_u8, grid, dim3(256), 0, stream, d_in, p.nsamp, L,
-                               p.nchans);
-            dd_status st = launch_check("k_bin_fused_u8");
-            if (st != DD_OK)
-                return st;
-        }
+        return;
     }
+    const int64_t nbin = J.nsamp >> K;
+#pragma unroll
+    for (int i = 0; i < (16 >> K); ++i)
+        if ((g0 >> K) + i < nbin)
+            o[i] = K == 4 ? uint16_t(v[0]) : uint16_t((i & 1) ? v[i >> 1] >> 16 : v[i >> 1] & 0xffffu);
+}
+
+__device__ __forceinline__ void bin_pow2_block(const BinJob &J, int64_t b, const uint8_t *in,
+                                               const uint8_t *in_end, char *ws, uint32_t *lds)
+{
+    const int64_t row = b / J.nseg;
+    const int seg = int(b - row * J.nseg);
+    const int64_t t_seg = int64_t(seg) * kBinSeg;
+    const uint8_t *p = in + J.in_off + row * J.nsamp + t_seg;
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(p);
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(pa & ~uintptr_t(3));
+    const uint32_t sh = uint32_t(pa & 3);
+    // (a 4-byte load that starts before the input's end cannot cross a page
+    // the input does not touch)
+    for (int i = threadIdx.x; i <= kBinSeg / 4; i += kBinThreads)
+        lds[i] = reinterpret_cast<const uint8_t *>(a + i) < in_end ? a[i] : 0u;
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int64_t g0 = t_seg + 16 * t;
+    if (g0 < J.nsamp) {
+        uint32_t w[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            w[k] = lds[4 * t + k];
+        uint32_t x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            x[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+        uint32_t l1[8], l2[4], l4[2], l8, l16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            l1[2 * i] = (x[i] & 0xffu) | ((x[i] & 0xff00u) << 8);
+            l1[2 * i + 1] = ((x[i] >> 16) & 0xffu) | ((x[i] >> 8) & 0xff0000u);
+            l2[i] = (x[i] & 0x00ff00ffu) + ((x[i] >> 8) & 0x00ff00ffu);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t u = (l2[2 * i] & 0xffffu) + (l2[2 * i] >> 16);
+            const uint32_t v = (l2[2 * i + 1] & 0xffffu) + (l2[2 * i + 1] >> 16);
+            l4[i] = u | (v << 16);
+        }
+        {
+            const uint32_t u = (l4[0] & 0xffffu) + (l4[0] >> 16);
+            const uint32_t v = (l4[1] & 0xffffu) + (l4[1] >> 16);
+            l8 = u | (v << 16);
+            l16 = u + v;
+        }
+        const bool full = g0 + 16 <= J.nsamp;
+        store_level<0>(J, ws, row, g0, full, l1);
+        store_level<1>(J, ws, row, g0, full, l2);
+        store_level<2>(J, ws, row, g0, full, l4);
+        store_level<3>(J, ws, row, g0, full, &l8);
+        store_level<4>(J, ws, row, g0, full, &l16);
+    }
+    __syncthreads();                                // the next block reuses the LDS
+}
+
+// One job by value (a single plan's input), blocks in a grid-stride loop.
+__global__ __launch_bounds__(kBinThreads) void k_bin_pow2_u8(const BinJob job, const uint8_t *in,
+                                                             const uint8_t *in_end, char *ws,
+                                                             int64_t nblocks)
+{
+    __shared__ uint32_t lds[kBinSeg / 4 + 4];
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x)
+        bin_pow2_block(job, b, in, in_end, ws, lds);
+}
+
+// Many jobs (the beams of a batch), in device memory ordered by
+// block_start; each block finds its job by bisection.
+__global__ __launch_bounds__(kBinThreads) void k_bin_pow2_u8_batch(const BinJob *__restrict__ jobs,
+                                                                   int njobs, const uint8_t *in,
+                                                                   const uint8_t *in_end, char *ws,
+                                                                   int64_t nblocks)
+{
+    __shared__ uint32_t lds[kBinSeg / 4 + 4];
+    for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].block_start <= b)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BinJob &J = jobs[lo];
+        bin_pow2_block(J, b - J.block_start, in, in_end, ws, lds);
+    }
+}
+
+// The power-of-two levels a plan has, as a job (ws offsets relative to the
+// plan's workspace, input at in_off); returns whether it has any.
+bool pow2_job(const Plan &p, int64_t in_off, size_t ws_off, BinJob &J)
+{
+    J.in_off = in_off;
+    J.nsamp = p.nsamp;
+    J.nchans = p.nchans;
+    J.nseg = int32_t((p.nsamp + kBinSeg - 1) / kBinSeg);
+    J.block_start = 0;
+    bool any = false;
+    for (int k = 0; k < 5; ++k) {
+        J.ws_off[k] = -1;
+        J.pitch[k] = 0;
+    }
+    for (const dd::BinLevel &lv : p.levels)
+        for (int k = 0; k < 5; ++k)
+            if (lv.ds == (1 << k)) {
+                J.ws_off[k] = int64_t(ws_off + lv.ws_offset);
+                J.pitch[k] = lv.pitch;
+                any = true;
+            }
+    return any;
+}
+
+// Levels that are not powers of two up to 16, each from its source level
+// (or the raw input), in increasing downsample order.
+dd_status bin_u8_rest(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t stream)
+{
     for (size_t i = 0; i < p.levels.size(); ++i) {
         const dd::BinLevel &lv = p.levels[i];
-        if (done[i])
+        if (lv.ds <= 16 && (lv.ds & (lv.ds - 1)) == 0)
             continue;
         uint16_t *dst = reinterpret_cast<uint16_t *>(d_ws + lv.ws_offset);
         const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 1023) / 1024, 1024)),
@@ -1545,6 +1704,42 @@ dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t str
             return st;
     }
     return DD_OK;
+}
+
+dd_status bin_u8(const Plan &p, const uint8_t *d_in, char *d_ws, hipStream_t stream)
+{
+    // Levels ds = 1, 2, 4, 8, 16 in one pass over the raw input: 16-byte
+    // loads when the rows allow them, else through LDS realignment; every
+    // other level from its source level (or the raw input).
+    BinJob J;
+    if (pow2_job(p, 0, 0, J)) {
+        if (p.nsamp % 16 == 0 && reinterpret_cast<uintptr_t>(d_in) % 16 == 0) {
+            FusedLevels L;
+            std::memset(&L, 0, sizeof(L));
+            for (int k = 0; k < 5; ++k)
+                if (J.ws_off[k] >= 0) {
+                    L.dst[k] = reinterpret_cast<uint16_t *>(d_ws + J.ws_off[k]);
+                    L.pitch[k] = J.pitch[k];
+                }
+            const int64_t ng = p.nsamp / 16;
+            const dim3 grid(unsigned(std::min<int64_t>((ng + 255) / 256, 1024)),
+                            unsigned(std::min<int32_t>(p.nchans, 65535)));
+            hipLaunchKernelGGL(k_bin_fused_u8, grid, dim3(256), 0, stream, d_in, p.nsamp, L,
+                               p.nchans);
+            dd_status st = launch_check("k_bin_fused_u8");
+            if (st != DD_OK)
+                return st;
+        } else {
+            const int64_t nblocks = int64_t(p.nchans) * J.nseg;
+            const uint8_t *end = d_in + int64_t(p.nchans) * p.nsamp;
+            hipLaunchKernelGGL(k_bin_pow2_u8, dim3(unsigned(std::min<int64_t>(nblocks, 1 << 20))),
+                               dim3(kBinThreads), 0, stream, J, d_in, end, d_ws, nblocks);
+            dd_status st = launch_check("k_bin_pow2_u8");
+            if (st != DD_OK)
+                return st;
+        }
+    }
+    return bin_u8_rest(p, d_in, d_ws, stream);
 }
 
 // A variant-3 range's fields apart from its input and output pointers.
@@ -2002,6 +2197,9 @@ struct BatchDevice {
     void *mem = nullptr;
     std::vector<const void *> descs;       // per group
     std::vector<const int64_t *> starts;   // per group
+    const BinJob *bin_jobs = nullptr;      // beams with power-of-two levels
+    int32_t nbin_jobs = 0;
+    int64_t bin_blocks = 0;
 };
 
 struct BatchState {
@@ -2070,6 +2268,20 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
             D.widen_every = ri.widen_every;
         }
     }
+    // binning jobs: every beam's power-of-two levels, one launch
+    std::vector<BinJob> jobs;
+    int64_t bin_blocks = 0;
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+        BinJob J;
+        if (!pow2_job(*b.plans[i], b.in_off[i], b.ws_off[i], J))
+            continue;
+        J.block_start = bin_blocks;
+        bin_blocks += int64_t(J.nchans) * J.nseg;
+        jobs.push_back(J);
+    }
+    const size_t off_jobs = grow(std::max<size_t>(1, jobs.size()) * sizeof(BinJob));
+    if (!jobs.empty())
+        std::memcpy(img.data() + off_jobs, jobs.data(), jobs.size() * sizeof(BinJob));
     BatchDevice bd;
     e = hipMalloc(&bd.mem, img.size() + 256);
     if (e != hipSuccess) {
@@ -2082,6 +2294,9 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
         (void)hipFree(bd.mem);
         return hip_fail(e, "hipMemcpy of the batch descriptors");
     }
+    bd.bin_jobs = reinterpret_cast<const BinJob *>(static_cast<const char *>(bd.mem) + off_jobs);
+    bd.nbin_jobs = int32_t(jobs.size());
+    bd.bin_blocks = bin_blocks;
     for (size_t g = 0; g < b.groups.size(); ++g) {
         bd.descs.push_back(static_cast<const char *>(bd.mem) + off_desc[g]);
         bd.starts.push_back(
@@ -2097,9 +2312,21 @@ constexpr int kPersistPerXcd = 64;
 dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
                         int32_t *d_out, char *d_ws, hipStream_t stream)
 {
+    // every beam's power-of-two levels in one launch, then the other levels
+    // beam by beam
+    if (bd.nbin_jobs > 0) {
+        const uint8_t *in = reinterpret_cast<const uint8_t *>(d_in);
+        hipLaunchKernelGGL(k_bin_pow2_u8_batch,
+                           dim3(unsigned(std::min<int64_t>(bd.bin_blocks, 1 << 20))),
+                           dim3(kBinThreads), 0, stream, bd.bin_jobs, bd.nbin_jobs, in,
+                           in + b.in_bytes, d_ws, bd.bin_blocks);
+        dd_status st = launch_check("k_bin_pow2_u8_batch");
+        if (st != DD_OK)
+            return st;
+    }
     for (size_t i = 0; i < b.plans.size(); ++i) {
-        dd_status st = bin_u8(*b.plans[i], reinterpret_cast<const uint8_t *>(d_in + b.in_off[i]),
-                              d_ws + b.ws_off[i], stream);
+        dd_status st = bin_u8_rest(*b.plans[i], reinterpret_cast<const uint8_t *>(d_in + b.in_off[i]),
+                                   d_ws + b.ws_off[i], stream);
         if (st != DD_OK)
             return st;
     }
