@@ -71,7 +71,7 @@ __device__ __forceinline__ int32_t table1(const int32_t *p)
 struct DeviceTables {
     int32_t *offT = nullptr;     // start of the one allocation holding every table
     int32_t *baseT = nullptr;
-    int32_t *qcnt = nullptr;     // integer variant 3: pattern counts; float32: clsF
+    int32_t *qcnt = nullptr;     // integer variant 3 only
     int32_t *qoff = nullptr;
     int32_t *offC = nullptr;
 };
@@ -115,11 +115,11 @@ dd_status device_tables(const Plan &p, DeviceTables **out)
     }
     DeviceTables t;
     // integer plans use offT/baseT (variant 3: baseT, qcntT, qoffT, offCT),
-    // float plans offF/baseF/clsF; one allocation, each table 256-byte aligned
+    // float plans offF/baseF; one allocation, each table 256-byte aligned
     const std::vector<int32_t> empty;
     const bool u8 = p.dtype == DD_U8;
     const std::vector<int32_t> *parts[5] = {u8 ? &p.offT : &p.offF, u8 ? &p.baseT : &p.baseF,
-                                            !u8 ? &p.clsF : p.subband ? &p.qcntT : &empty,
+                                            p.subband ? &p.qcntT : &empty,
                                             p.subband ? &p.qoffT : &empty,
                                             p.subband ? &p.offCT : &empty};
     size_t at[5], total = 0;
@@ -868,8 +868,7 @@ __global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ 
 
 struct SumArgs {
     const float *src;         // rows, `pitch` floats apart
-    const int32_t *off;       // [nout_tiles][kF32OutTile][nstages][stage_rows] sorted entries
-    const int32_t *cls;       // [nout_tiles][kF32OutTile][nstages] class ends
+    const int32_t *off;       // [nout_tiles][nstages][kF32OutTile][tab_stride] output lists
     const int32_t *base;      // [nout_tiles][nrows]
     float *dst;               // output rows, `dst_pitch` floats apart
     int64_t pitch;
@@ -883,7 +882,7 @@ struct SumArgs {
     int32_t stage_rows;
     int32_t row_words;
     int32_t nstages;
-    int32_t pad_;
+    int32_t tab_stride;
 };
 
 struct SumBatch {
@@ -893,7 +892,6 @@ struct SumBatch {
     int32_t nprob;
 };
 
-typedef int sgpr16 __attribute__((ext_vector_type(16)));
 
 // The fields of a problem the stage loop reads, held in registers (read
 // through the kernel-argument reference they would be loaded again after
@@ -901,14 +899,27 @@ typedef int sgpr16 __attribute__((ext_vector_type(16)));
 struct StageSrc {
     const float *src;
     const int32_t *base;
+    const int32_t *tab;       // [nout_tiles][nstages][kF32OutTile][tab_stride]
     int64_t pitch;
     int32_t nrows;
     int32_t row_words;
+    int32_t nstages;
+    int32_t tab_stride;
 };
 
 __device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int64_t t0, int bs,
-                                                int bn, float *buf, int wave, int lane)
+                                                int bn, float *buf, int wave, int lane, int st,
+                                                float *tbuf)
 {
+    {
+        // the stage's output lists, 16 bytes per lane
+        const int chunks = kFTileA * S.tab_stride / 4;
+        const int q = wave * kWave + lane;
+        if (wave * kWave < chunks && q < chunks) {
+            const int32_t *g = S.tab + (int64_t(tile) * S.nstages + st) * kFTileA * S.tab_stride + 4 * q;
+            __builtin_amdgcn_global_load_lds(g, tbuf + wave * (4 * kWave), 16, 0, 0);
+        }
+    }
     const int Wr = S.row_words;
     const int chunks = Wr >> 2;
     const int ipr = (chunks + kWave - 1) / kWave;
@@ -954,35 +965,25 @@ __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcn
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// Sixteen table entries (those of one output and stage; the table is padded
-// so the load stays inside it) and the word at q, by two scalar loads and
-// one wait.
-__device__ __forceinline__ sgpr16 table16_1(const int32_t *p, const int32_t *q, int32_t &w)
+// One output's list of a stage (16 entries and the class-ends word) from
+// LDS, waited for in the same instruction block.  Written out because the
+// compiler, seeing LDS reads it cannot tell apart from the next stage's
+// direct loads in flight, would put a wait for those loads before them and
+// so undo the overlap of the staging with the sums.
+__device__ __forceinline__ void lds_list(const float *p, const float *pe, f4v &a, f4v &b, f4v &c,
+                                         f4v &d, float &e)
 {
-    const uint64_t a = reinterpret_cast<uint64_t>(p);
-    const uint64_t b = reinterpret_cast<uint64_t>(q);
-    const uint32_t alo = __builtin_amdgcn_readfirstlane(uint32_t(a));
-    const uint32_t ahi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
-    const uint32_t blo = __builtin_amdgcn_readfirstlane(uint32_t(b));
-    const uint32_t bhi = __builtin_amdgcn_readfirstlane(uint32_t(b >> 32));
-    const uint64_t pa = (uint64_t(ahi) << 32) | alo;
-    const uint64_t pb = (uint64_t(bhi) << 32) | blo;
-    sgpr16 v;
-    asm volatile("s_load_dwordx16 %0, %2, 0x0\n\ts_load_dword %1, %3, 0x0\n\ts_waitcnt lgkmcnt(0)"
-                 : "=&s"(v), "=&s"(w)
-                 : "s"(pa), "s"(pb));
-    return v;
-}
-
-// A wave-uniform value copied into a VGPR by an instruction the compiler
-// cannot rematerialise: the entries of a stage then stay in VGPRs while the
-// class loops index them, instead of being copied again from SGPRs before
-// every indexed read.
-__device__ __forceinline__ int to_vgpr(int s)
-{
-    int v;
-    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
-    return v;
+    const uint32_t la = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
+    const uint32_t le = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(pe));
+    asm volatile("ds_read_b128 %0, %5\n\t"
+                 "ds_read_b128 %1, %5 offset:16\n\t"
+                 "ds_read_b128 %2, %5 offset:32\n\t"
+                 "ds_read_b128 %3, %5 offset:48\n\t"
+                 "ds_read_b32 %4, %6\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "=&v"(e)
+                 : "v"(la), "v"(le)
+                 : "memory");
 }
 
 // Lane l receives lane l + 1's v (lane 63 receives 0); the compiler folds
@@ -1065,11 +1066,9 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int CW = C * Wr;
     const int nrows = R.nrows;
     const int nst = R.nstages;
-    // the lists of this wave's outputs: [tile][output][stage]
-    const int64_t list0 = int64_t(aw0) * nst;
-    const StageSrc S = {R.src, R.base, R.pitch, nrows, Wr};
-    const int32_t *const off_tab = R.off;
-    const int32_t *const cls_tab = R.cls;
+    const StageSrc S = {R.src, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_stride};
+    const int TS = R.tab_stride;
+    const int CWt = CW + kFTileA * TS + 16;     // floats of one stage buffer: rows, then lists
 
     // acc[d][k*4 + j]: output aw0 + d at tile sample 4*(lane + 63k) + j
     float acc[kFP][kFW];
@@ -1079,26 +1078,35 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         for (int k = 0; k < kFW; ++k)
             acc[d][k] = 0.0f;
 
-    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane);
+    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane, 0, ldsf + CW);
     for (int st = 0; st < nst; ++st) {
-        const float *A = ldsf + (st & 1) * CW;
+        const float *A = ldsf + (st & 1) * CWt;
+        const float *T = A + CW;
         wait_loads();
         lds_barrier();
         if (st + 1 < nst) {
             const int bs = (st + 1) * C;
-            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf + ((st + 1) & 1) * CW,
-                            wave, lane);
+            float *nb = ldsf + ((st + 1) & 1) * CWt;
+            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), nb, wave, lane, st + 1, nb + CW);
         }
 #pragma unroll
         for (int d = 0; d < kFP; ++d) {
-            const int64_t list = list0 + int64_t(d) * nst + st;
-            int32_t ends_i;
-            const sgpr16 es = table16_1(off_tab + list * C, cls_tab + list, ends_i);
-            const uint32_t ends = uint32_t(ends_i);
+            // this output's list from LDS: its entries, then the class ends
+            // in the list's last word
+            const float *Lp = T + (wave * kFP + d) * TS;
+            f4v q0, q1, q2, q3;
+            float ef;
+            lds_list(Lp, Lp + (TS - 1), q0, q1, q2, q3, ef);
+            const uint32_t ends = uint32_t(__builtin_amdgcn_readfirstlane(__float_as_int(ef)));
+            const f4v qs[4] = {q0, q1, q2, q3};
             int ent[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                ent[k] = to_vgpr(es[k]);
+            for (int k = 0; k < 4; ++k) {
+                ent[4 * k] = __float_as_int(qs[k].x);
+                ent[4 * k + 1] = __float_as_int(qs[k].y);
+                ent[4 * k + 2] = __float_as_int(qs[k].z);
+                ent[4 * k + 3] = __float_as_int(qs[k].w);
+            }
             int i = 0;
             add_class<0>(acc[d], A, ent, i, int(ends & 0xFF), lane);
             add_class<1>(acc[d], A, ent, i, int((ends >> 8) & 0xFF), lane);
@@ -1878,7 +1886,6 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     std::memset(&R, 0, sizeof(R));
     R.src = src;
     R.off = t.offT + sp.off_offset;
-    R.cls = t.qcnt + sp.cls_offset;
     R.base = t.baseT + sp.base_offset;
     R.dst = dst;
     R.pitch = pitch;
@@ -1892,6 +1899,7 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     R.stage_rows = sp.stage_rows;
     R.row_words = sp.row_words;
     R.nstages = sp.nstages;
+    R.tab_stride = sp.tab_stride;
     return R;
 }
 

@@ -80,9 +80,9 @@ void parallel_for(int64_t n, int64_t work_per_item, F fn)
 // Tables of one float32 shift-and-sum problem (see plan.h).  S(a, b) gives
 // the delay of row b for output a; it must be >= 0.
 template <typename SFn>
-dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S,
+dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S_,
                             std::vector<int32_t> &offF, std::vector<int32_t> &baseF,
-                            std::vector<int32_t> &clsF, int64_t *blocks, size_t *lds,
+                            int64_t *blocks, size_t *lds,
                             std::string *err, const char *what, int32_t want_stage)
 {
     sp.nrows = nrows;
@@ -97,9 +97,9 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         const int32_t a0 = tile * kF32OutTile;
         const int32_t a1 = std::min(nouts, a0 + kF32OutTile);
         for (int32_t b = 0; b < nrows; ++b) {
-            int32_t lo = S(a0, b), hi = lo;
+            int32_t lo = S_(a0, b), hi = lo;
             for (int32_t a = a0 + 1; a < a1; ++a) {
-                const int32_t v = S(a, b);
+                const int32_t v = S_(a, b);
                 lo = std::min(lo, v);
                 hi = std::max(hi, v);
             }
@@ -114,7 +114,10 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
     int32_t stage = want_stage > 0 ? std::max(1, std::min(want_stage, kF32MaxStage)) : kF32MaxStage;
     if (stage > 1)
         stage &= ~1;
-    auto bytes_for = [&](int32_t st) { return size_t(8) * size_t(st) * size_t(sp.row_words); };
+    auto stride_for = [&](int32_t st) { return (st + 1 + 3) / 4 * 4; };
+    auto bytes_for = [&](int32_t st) {
+        return size_t(8) * (size_t(st) * size_t(sp.row_words) + size_t(kF32OutTile) * stride_for(st) + 16);
+    };
     while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
         stage = stage > 2 ? stage - 2 : 1;
     if (bytes_for(stage) > kMaxLdsBytes) {
@@ -124,6 +127,7 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
     }
     sp.stage_rows = stage;
     sp.nstages = (nrows + stage - 1) / stage;
+    sp.tab_stride = stride_for(stage);
     *lds = std::max(*lds, bytes_for(stage));
     sp.block_start = *blocks;
     *blocks += sp.ntime_tiles * sp.nout_tiles;
@@ -134,21 +138,21 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
             const int32_t m = mins[size_t(tile) * nrows + b];
             baseF[sp.base_offset + size_t(tile) * nrows + b] = m - (m & 3);
         }
-    // Per (tile, output, stage): the stage's rows ordered by the class o & 3
-    // of their delay in the window, so the kernel adds each class with its
-    // own fixed register pattern.  The kernel reads a stage's entries 16 at
-    // a time: the table ends with 16 entries of padding.
-    const size_t nlists = size_t(sp.nout_tiles) * kF32OutTile * size_t(sp.nstages);
+    // Per (tile, stage, output): the stage's rows ordered by the class o & 3
+    // of their delay (stable), then in the list's last word the ends of the
+    // classes; the kernel stages each (tile, stage) block in LDS beside the
+    // rows.
+    const int32_t S = sp.tab_stride;
+    const size_t nlists = size_t(sp.nout_tiles) * size_t(sp.nstages) * kF32OutTile;
+    offF.resize((offF.size() + 3) / 4 * 4, 0);
     sp.off_offset = offF.size();
-    offF.resize(offF.size() + nlists * size_t(stage) + 16, 0);
-    sp.cls_offset = clsF.size();
-    clsF.resize(clsF.size() + nlists, 0);
+    offF.resize(offF.size() + nlists * size_t(S), 0);
     for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
-        for (int32_t al = 0; al < kF32OutTile; ++al) {
-            const int32_t av = std::min(tile * kF32OutTile + al, nouts - 1);
-            for (int32_t st = 0; st < sp.nstages; ++st) {
-                const size_t list = (size_t(tile) * kF32OutTile + al) * sp.nstages + st;
-                int32_t *ent = &offF[sp.off_offset + list * stage];
+        for (int32_t st = 0; st < sp.nstages; ++st)
+            for (int32_t al = 0; al < kF32OutTile; ++al) {
+                const int32_t av = std::min(tile * kF32OutTile + al, nouts - 1);
+                const size_t list = (size_t(tile) * sp.nstages + st) * kF32OutTile + al;
+                int32_t *ent = &offF[sp.off_offset + list * S];
                 const int32_t b0 = st * stage, bn = std::min(stage, nrows - b0);
                 int32_t n = 0;
                 uint32_t ends = 0;
@@ -156,15 +160,14 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
                     for (int32_t j = 0; j < bn; ++j) {
                         const int32_t b = b0 + j;
                         const int32_t m = mins[size_t(tile) * nrows + b];
-                        const int32_t o = (m & 3) + S(av, b) - m;
+                        const int32_t o = (m & 3) + S_(av, b) - m;
                         if ((o & 3) == cls)
                             ent[n++] = j * sp.row_words + 4 * (o >> 2);
                     }
                     ends |= uint32_t(n) << (8 * cls);
                 }
-                clsF[sp.cls_offset + list] = int32_t(ends);
+                ent[S - 1] = int32_t(ends);
             }
-        }
     return DD_OK;
 }
 
@@ -191,7 +194,6 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     p->levels.clear();
     p->offF.clear();
     p->baseF.clear();
-    p->clsF.clear();
     int64_t blocks = 0, ablocks = 0;
     size_t lds = 0, alds = 0;
     for (int32_t r = 0; r < int32_t(p->ranges.size()); ++r) {
@@ -199,7 +201,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
         auto Sf = [&](int32_t a, int32_t b) { return sh[size_t(a) * nchans + b]; };
         dd_status st = build_sum_problem(ri.fwd, nchans, ri.ndms, ri.nout, Sf, p->offF, p->baseF,
-                                         p->clsF, &blocks, &lds, err, "forward", want_stage);
+                                         &blocks, &lds, err, "forward", want_stage);
         if (st != DD_OK)
             return st;
     }
@@ -209,7 +211,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t P = ri.max_shift;
         auto Sa = [&](int32_t a, int32_t b) { return P - sh[size_t(b) * nchans + a]; };
         dd_status st = build_sum_problem(ri.adj, ri.ndms, nchans, ri.nbin, Sa, p->offF, p->baseF,
-                                         p->clsF, &ablocks, &alds, err, "adjoint", want_stage);
+                                         &ablocks, &alds, err, "adjoint", want_stage);
         if (st != DD_OK)
             return st;
     }

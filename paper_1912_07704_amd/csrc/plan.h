@@ -77,17 +77,18 @@ struct SumProblem {
     int64_t ntime_tiles = 0;
     int64_t block_start = 0;
     int32_t nstages = 0;        // ceil(nrows / stage_rows)
+    int32_t tab_stride = 0;     // ints per output list: roundup(stage_rows + 1, 4)
     // With m = min over the output tile of S[.][b], e = m & 3 and
     // o = e + S[a][b] - m (the delay inside the staged window):
     size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e
-    size_t off_offset = 0;      // offF: [nout_tiles][kF32OutTile][nstages][stage_rows]:
-                                // for output a and stage s, the stage's rows
-                                // ordered by o & 3 (stable), each entry
-                                // slot * row_words + 4 * (o >> 2) (slot = the
-                                // row's place in the stage's LDS buffer)
-    size_t cls_offset = 0;      // clsF: [nout_tiles][kF32OutTile][nstages]:
-                                // where each class o & 3 = 0, 1, 2, 3 ends in
-                                // that list, one byte each (low byte first)
+    size_t off_offset = 0;      // offF: [nout_tiles][nstages][kF32OutTile][tab_stride]:
+                                // per output and stage, the stage's rows
+                                // ordered by the class o & 3 (stable), each
+                                // entry slot * row_words + 4 * (o >> 2) (slot
+                                // = the row's place in the stage's LDS
+                                // buffer); the last word holds the ends of
+                                // the classes 0, 1, 2, 3 (one byte each, low
+                                // byte first)
 };
 
 // One 16-bit copy of the input, binned by ds (ds = 1: the samples widened
@@ -198,7 +199,6 @@ struct Plan {
     // then adjoint problems), and the adjoint's reduction buffer.
     std::vector<int32_t> offF;
     std::vector<int32_t> baseF;
-    std::vector<int32_t> clsF;
     int64_t adj_blocks = 0;
     size_t adj_lds_bytes = 0;
     int32_t dw_chunks = 0;                 // time chunks of the weight-gradient reduction

@@ -35,7 +35,11 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
 {
     const int C = sp.stage_rows, Wr = sp.row_words, nst = sp.nstages, nrows = sp.nrows;
     const long lds_floats = long(P.dtype == DD_F32 ? std::max(P.lds_bytes, P.adj_lds_bytes) : 0) / 4;
-    CHECK(long(2) * C * Wr <= lds_floats, "[%s] stage buffers %d x %d past LDS %ld", name, C, Wr, lds_floats);
+    const int TS = sp.tab_stride;
+    CHECK(TS % 4 == 0 && TS >= C + 1, "[%s] list stride %d for %d rows", name, TS, C);
+    CHECK(long(2) * (long(C) * Wr + long(kF32OutTile) * TS + 16) <= lds_floats,
+          "[%s] stage buffers (%d x %d rows + lists) past LDS %ld", name, C, Wr, lds_floats);
+    CHECK(sp.off_offset % 4 == 0, "[%s] lists not 16-byte aligned", name);
     CHECK(Wr % 4 == 0, "[%s] row_words %d", name, Wr);
     CHECK(nst == (nrows + C - 1) / C, "[%s] nstages", name);
     const long nblocks = sp.ntime_tiles * sp.nout_tiles;
@@ -68,17 +72,22 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
             for (int al = 0; al < kF32OutTile; ++al) {
                 const int a = tile * kF32OutTile + al;
                 const int av = std::min(a, sp.nouts - 1);
-                const size_t list = (size_t(tile) * kF32OutTile + al) * nst + st;
-                CHECK(sp.off_offset + list * C + 16 <= P.offF.size(), "[%s] 16-entry load past offF", name);
-                CHECK(sp.cls_offset + list < P.clsF.size(), "[%s] clsF index", name);
-                const uint32_t ends = uint32_t(P.clsF[sp.cls_offset + list]);
+                // the stage's lists are staged whole ([nstages][outputs][TS] per
+                // tile); each output reads 16 words of its list and its last
+                // word (the LDS block holds 16 words past the last list)
+                const size_t block = (size_t(tile) * nst + st) * kF32OutTile * TS;
+                CHECK(sp.off_offset + block + size_t(kF32OutTile) * TS <= P.offF.size(),
+                      "[%s] list block past offF", name);
+                CHECK(al * TS + 16 <= kF32OutTile * TS + 16, "[%s] list read past the LDS block", name);
+                const size_t list = sp.off_offset + block + size_t(al) * TS;
+                const uint32_t ends = uint32_t(P.offF[list + TS - 1]);
                 int e[4] = {int(ends & 0xFF), int((ends >> 8) & 0xFF), int((ends >> 16) & 0xFF), int(ends >> 24)};
                 CHECK(e[0] <= e[1] && e[1] <= e[2] && e[2] <= e[3] && e[3] == bn, "[%s] class ends %d %d %d %d bn %d", name, e[0], e[1], e[2], e[3], bn);
                 std::vector<int> seen(bn, 0);
                 int i = 0;
                 for (int cls = 0; cls < 4; ++cls)
                     for (; i < e[cls]; ++i) {
-                        const int ent = P.offF[sp.off_offset + list * C + i];
+                        const int ent = P.offF[list + i];
                         const int slot = ent / Wr, q4 = ent - slot * Wr;
                         CHECK(slot >= 0 && slot < bn && q4 % 4 == 0, "[%s] entry %d", name, ent);
                         if (!(slot >= 0 && slot < bn)) continue;
