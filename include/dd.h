@@ -135,14 +135,18 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *                partial sums allow).
  *   dm_tile      DD_U8 trial DMs per workgroup: 32 (4 wavefronts) or 64 (8)
  *                for variants 1 and 2 (default 64); for variant 3, 192 (the
- *                default) or 128 (16 wavefronts, 256-sample time tiles), or
- *                96 or 64 (8 wavefronts, 512-sample time tiles); any of
- *                these for variant 0.
+ *                default) or 128 (16 wavefronts), or 96 or 64 (8
+ *                wavefronts); any of these for variant 0.
+ *   time_tile    DD_U8 output samples per workgroup: 256 or 512 for variants
+ *                1 and 2 (default 512) and for variant 3 at DM tiles 96 and
+ *                64 (default 512); 256 only for variant 3 at DM tiles 192 and
+ *                128.  DD_ERR_INVALID for other values.
  */
 typedef struct {
     int32_t variant;
     int32_t stage_chans;
     int32_t dm_tile;
+    int32_t time_tile;
 } dd_options;
 
 dd_status dd_plan_create_ex(const double *freqs_mhz, int32_t nchans, double tsamp_s,

@@ -41,15 +41,16 @@ class RangeInfo:
 
 class _Options(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("stage_chans", ctypes.c_int32),
-                ("dm_tile", ctypes.c_int32)]
+                ("dm_tile", ctypes.c_int32), ("time_tile", ctypes.c_int32)]
 
 
 class Plan:
     """Immutable dedispersion plan (wraps dd_plan_create_ex / dd_plan_destroy).
-    `variant` and `stage_chans` fix the strategy (0 = library default)."""
+    `variant`, `stage_chans`, `dm_tile` and `time_tile` fix the strategy
+    (0 = library default)."""
 
     def __init__(self, freqs_mhz, tsamp_s: float, nsamp: int, ranges, dtype: str = "u8",
-                 variant: int = 0, stage_chans: int = 0, dm_tile: int = 0):
+                 variant: int = 0, stage_chans: int = 0, dm_tile: int = 0, time_tile: int = 0):
         L = lib()
         f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         rg = (_Range * len(ranges))(*[_Range(float(a), float(b), float(c), int(d))
@@ -59,7 +60,7 @@ class Plan:
         self.nchans = int(f.size)
         self.nsamp = int(nsamp)
         self.tsamp = float(tsamp_s)
-        opts = _Options(int(variant), int(stage_chans), int(dm_tile))
+        opts = _Options(int(variant), int(stage_chans), int(dm_tile), int(time_tile))
         check(L.dd_plan_create_ex(f.ctypes.data_as(ctypes.c_void_p), f.size, float(tsamp_s),
                                   int(nsamp), rg, len(ranges), _DTYPES[dtype], ctypes.byref(opts),
                                   ctypes.byref(self._h)), "dd_plan_create_ex")

@@ -50,18 +50,19 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
             int32_t g = 0;
             while (g < int32_t(b->groups.size()) &&
                    !(b->groups[g].subband == p->subband && b->groups[g].dedup == p->dedup &&
-                     b->groups[g].dm_tile == p->dm_tile))
+                     b->groups[g].dm_tile == p->dm_tile && b->groups[g].time_tile == p->time_tile))
                 ++g;
             if (g == int32_t(b->groups.size())) {
                 if (g == kBatchMaxGroups) {
                     *err = "a batch runs at most " + std::to_string(kBatchMaxGroups) +
-                           " kernels (variant, DM tile)";
+                           " kernels (variant, DM tile, time tile)";
                     return DD_ERR_INVALID;
                 }
                 BatchGroup G;
                 G.subband = p->subband;
                 G.dedup = p->dedup;
                 G.dm_tile = p->dm_tile;
+                G.time_tile = p->time_tile;
                 G.waves = p->waves;
                 b->groups.push_back(G);
             }

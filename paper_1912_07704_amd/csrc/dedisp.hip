@@ -29,9 +29,7 @@ using dd::RangeInfo;
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = dd::kWaves;
 constexpr int kBlock = dd::kWaves * kWave;
-constexpr int kNW = dd::kWaveWords;
 constexpr int kDW = dd::kDmPerWave;
-constexpr int kTileT = dd::kTimeTile;
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round-robin
 constexpr int kCusPerXcd = 32;
 
@@ -195,9 +193,9 @@ __global__ __launch_bounds__(256) void k_bin_u16(const Tin *__restrict__ src, in
 // ---------------------------------------------------------------------------
 // Integer shift-and-sum.
 //
-// A workgroup owns one (range, time tile of kTileT samples, DM tile of
+// A workgroup owns one (range, time tile of 128*NW samples, DM tile of
 // kTileD trials).  Wave w handles kDW consecutive DMs; lane l handles the
-// sample pairs t0 + 2*(l + 64k) + {0, 1}, k < kNW, so a wave's LDS reads of
+// sample pairs t0 + 2*(l + 64k) + {0, 1}, k < NW, so a wave's LDS reads of
 // one word index are 64 consecutive dwords (no bank conflict).
 //
 // The range reads a 16-bit copy of the input (binned by its downsample).
@@ -283,14 +281,14 @@ __device__ __forceinline__ void stage_issue(const RA &R, int nchans, int tile, i
 // DM tile minor).  `lds` holds two stages of two copies each.
 // DEDUP: a channel's words are re-read from LDS only when a DM's offset
 // differs from the previous DM's (consecutive DMs share a delay often).
-template <bool DEDUP, int WAVES>
+template <bool DEDUP, int WAVES, int NW>
 __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, uint32_t *lds)
 {
     constexpr int kTileDW = WAVES * kDW;
     const int64_t tt = lb / R.ndm_tiles;
     const int tile = int(lb - tt * R.ndm_tiles);
     const int d0 = tile * kTileDW;
-    const int64_t t0 = tt * kTileT;
+    const int64_t t0 = tt * (2 * kWave * NW);
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -303,12 +301,12 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
     const int CW = C * Wr;              // words of one copy of a stage
     const int nst = (nchans + C - 1) / C;
 
-    uint32_t acc16[kDW][kNW];
-    int32_t acc32[kDW][kNW][2];
+    uint32_t acc16[kDW][NW];
+    int32_t acc32[kDW][NW][2];
 #pragma unroll
     for (int dd = 0; dd < kDW; ++dd)
 #pragma unroll
-        for (int k = 0; k < kNW; ++k) {
+        for (int k = 0; k < NW; ++k) {
             acc16[dd][k] = 0u;
             acc32[dd][k][0] = 0;
             acc32[dd][k][1] = 0;
@@ -344,21 +342,21 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
                 const int offb[kDW] = {bv[0], bv[1], bv[2], bv[3], bv[4], bv[5], bv[6], bv[7]};
                 const uint32_t *rowb = rowa + Wr;
                 if constexpr (DEDUP) {
-                    uint32_t va[kNW], vb[kNW];
+                    uint32_t va[NW], vb[NW];
 #pragma unroll
                     for (int dd = 0; dd < kDW; ++dd) {
                         if (dd == 0 || offa[dd] != offa[dd - 1]) {
 #pragma unroll
-                            for (int k = 0; k < kNW; ++k)
+                            for (int k = 0; k < NW; ++k)
                                 va[k] = rowa[offa[dd] + kWave * k];
                         }
                         if (dd == 0 || offb[dd] != offb[dd - 1]) {
 #pragma unroll
-                            for (int k = 0; k < kNW; ++k)
+                            for (int k = 0; k < NW; ++k)
                                 vb[k] = rowb[offb[dd] + kWave * k];
                         }
 #pragma unroll
-                        for (int k = 0; k < kNW; ++k)
+                        for (int k = 0; k < NW; ++k)
                             acc16[dd][k] += va[k] + vb[k];
                     }
                 } else {
@@ -367,7 +365,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
                         const uint32_t *pa = rowa + offa[dd];
                         const uint32_t *pb = rowb + offb[dd];
 #pragma unroll
-                        for (int k = 0; k < kNW; ++k)
+                        for (int k = 0; k < NW; ++k)
                             acc16[dd][k] += pa[kWave * k] + pb[kWave * k];
                     }
                 }
@@ -376,7 +374,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
                 for (int dd = 0; dd < kDW; ++dd) {
                     const uint32_t *pa = rowa + offa[dd];
 #pragma unroll
-                    for (int k = 0; k < kNW; ++k)
+                    for (int k = 0; k < NW; ++k)
                         acc16[dd][k] += pa[kWave * k];
                 }
             }
@@ -386,7 +384,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
 #pragma unroll
             for (int dd = 0; dd < kDW; ++dd)
 #pragma unroll
-                for (int k = 0; k < kNW; ++k) {
+                for (int k = 0; k < NW; ++k) {
                     acc32[dd][k][0] += int32_t(acc16[dd][k] & 0xffffu);
                     acc32[dd][k][1] += int32_t(acc16[dd][k] >> 16);
                     acc16[dd][k] = 0u;
@@ -401,7 +399,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
             break;
         int32_t *row = R.out + int64_t(d) * R.nout;
 #pragma unroll
-        for (int k = 0; k < kNW; ++k) {
+        for (int k = 0; k < NW; ++k) {
             const int64_t t = t0 + 2 * (lane + kWave * k);
             if (t < R.nout)
                 row[t] = acc32[dd][k][0];
@@ -412,7 +410,7 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
 }
 
 
-template <bool DEDUP, int WAVES>
+template <bool DEDUP, int WAVES, int NW>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_dedisp_u8(const FwdArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -427,7 +425,7 @@ __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4
     for (int i = 1; i < a.nranges; ++i)
         if (L >= a.r[i].block_start)
             r = i;
-    dedisp_tile_u8<DEDUP, WAVES>(a.r[r], L - a.r[r].block_start, lds);
+    dedisp_tile_u8<DEDUP, WAVES, NW>(a.r[r], L - a.r[r].block_start, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -829,8 +827,11 @@ k_dedisp_u8_sb(const SbArgs a)
 
 constexpr int kFW = dd::kF32Words;
 constexpr int kFP = dd::kF32PerWave;
-constexpr int kFTileT = dd::kF32TimeTile;      // 504 samples computed per tile
-constexpr int kFSpan = dd::kF32TileSpan;        // 512 samples the lanes cover
+constexpr int kFTileT = dd::kF32TimeTile;      // samples computed per tile
+constexpr int kFSpan = dd::kF32TileSpan;        // samples the lanes cover
+// offset of accumulator k's sample from 4 * lane: granule k / 4 of the
+// lane (63 granules apart), float k % 4 of it
+__device__ __forceinline__ constexpr int ks(int k) { return 4 * (kWave - 1) * (k >> 2) + (k & 3); }
 constexpr int kFTileA = dd::kF32OutTile;
 
 __global__ __launch_bounds__(256) void k_level_f32(const float *__restrict__ src, int64_t src_pitch,
@@ -953,6 +954,9 @@ __device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int
 // one LDS row per wave; the window sums of the gradient likewise.
 enum { kWrite = 0, kBoxLoss = 1, kBoxGrad = 2 };
 
+// LDS rows of kFSpan floats per wave that a boxcar epilogue uses
+__host__ __device__ constexpr int box_rows(int mode) { return mode == kBoxGrad ? 2 : 1; }
+
 struct BoxArgs {
     float *partial;           // kBoxLoss: one float per workgroup
     int64_t t_stride;         // samples between consecutive time tiles
@@ -1016,26 +1020,41 @@ __device__ __forceinline__ void add_window(float *acc, const f4v g)
 
 // The rows of one class (delay mod 4 = R) of one output in one stage:
 // entries [i, end) of its list, each the LDS float offset of the row's
-// first granule.  Two rows per step.
+// first granule; lane l adds granules l + 63g (g < kFG) of each.  Two rows
+// per step when kFG is 2, one when it is 4.
+constexpr int kFG = dd::kF32Words / 4;          // granules per lane and output
+
 template <int R>
 __device__ __forceinline__ void add_class(float *acc, const float *A, const int (&ent)[16], int &i,
                                           int end, int lane)
 {
-    for (; i + 1 < end; i += 2) {
-        const f4v *p = reinterpret_cast<const f4v *>(A + ent[i]) + lane;
-        const f4v *q = reinterpret_cast<const f4v *>(A + ent[i + 1]) + lane;
-        const f4v p0 = p[0], p1 = p[63], q0 = q[0], q1 = q[63];
-        add_window<R>(acc, p0);
-        add_window<R>(acc + 4, p1);
-        add_window<R>(acc, q0);
-        add_window<R>(acc + 4, q1);
+    if constexpr (kFG <= 2) {
+        for (; i + 1 < end; i += 2) {
+            const f4v *p = reinterpret_cast<const f4v *>(A + ent[i]) + lane;
+            const f4v *q = reinterpret_cast<const f4v *>(A + ent[i + 1]) + lane;
+            f4v pv[kFG], qv[kFG];
+#pragma unroll
+            for (int g = 0; g < kFG; ++g) {
+                pv[g] = p[(kWave - 1) * g];
+                qv[g] = q[(kWave - 1) * g];
+            }
+#pragma unroll
+            for (int g = 0; g < kFG; ++g)
+                add_window<R>(acc + 4 * g, pv[g]);
+#pragma unroll
+            for (int g = 0; g < kFG; ++g)
+                add_window<R>(acc + 4 * g, qv[g]);
+        }
     }
-    if (i < end) {
+    for (; i < end; ++i) {
         const f4v *p = reinterpret_cast<const f4v *>(A + ent[i]) + lane;
-        const f4v p0 = p[0], p1 = p[63];
-        add_window<R>(acc, p0);
-        add_window<R>(acc + 4, p1);
-        ++i;
+        f4v pv[kFG];
+#pragma unroll
+        for (int g = 0; g < kFG; ++g)
+            pv[g] = p[(kWave - 1) * g];
+#pragma unroll
+        for (int g = 0; g < kFG; ++g)
+            add_window<R>(acc + 4 * g, pv[g]);
     }
 }
 
@@ -1115,8 +1134,14 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         }
     }
 
-    // lane 63 only supplied the next-lane heads: its sums are not outputs
+    // lane 63 only supplied the next-lane heads: its sums are not outputs.
+    // Accumulator k of a lane holds tile sample 4*lane + ks(k); bounds on
+    // the series are taken as 32-bit bounds on the tile sample.
     const bool lane_ok = lane < kWave - 1;
+    const int tb = 4 * lane;
+    const int64_t nt = R.nt;
+    const int t_lo = int(min<int64_t>(max<int64_t>(-t0, 0), kFSpan));   // tg >= 0
+    const int t_end = int(min<int64_t>(max<int64_t>(nt - t0, -64), kFSpan + 64)); // tg < nt
     if constexpr (MODE == kWrite) {
         if (lane_ok) {
 #pragma unroll
@@ -1124,72 +1149,82 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                 const int ao = aw0 + d;
                 if (ao >= R.nouts)
                     break;
-                float *row = R.dst + int64_t(ao) * R.dst_pitch;
+                float *row = R.dst + int64_t(ao) * R.dst_pitch + t0;
 #pragma unroll
                 for (int k = 0; k < kFW; ++k) {
-                    const int64_t t = t0 + 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
-                    if (t >= 0 && t < R.nt)
+                    const int t = tb + ks(k);
+                    if (t >= t_lo && t < t_end)
                         row[t] = acc[d][k];
                 }
             }
         }
     } else {
         lds_barrier();                          // staging rows are no longer read
-        float *rowR = ldsf + wave * (2 * kFSpan);
-        float *rowS = rowR + kFSpan;
-        const int64_t nt = R.nt;
+        // per wave: one exchange row (the doubling of B_w and the window
+        // sums take turns on it, each pass ending in a wait for the wave's
+        // LDS accesses) and, for the gradient, the running sum over widths,
+        // of which each lane touches only its own samples
+        float *rowR = ldsf + wave * (box_rows(MODE) * kFSpan);
+        float *rowS = rowR;
+        float *rowG = rowR + kFSpan;
+        const int t_str = int(bx.t_stride);
+        const int t_lead = int(bx.t_lead);
         float part = 0.0f;
+        // one output at a time, its boxcar sums formed in place of its
+        // accumulators (the loop is unrolled so that they stay in registers)
+#pragma unroll
         for (int d = 0; d < kFP; ++d) {
             const int ao = aw0 + d;
             const bool dm_ok = ao < R.nouts && lane_ok;
-            float b[kFW], gsum[kFW];
+            float *b = acc[d];
+            if constexpr (MODE == kBoxGrad)
 #pragma unroll
-            for (int k = 0; k < kFW; ++k) {
-                b[k] = acc[d][k];
-                gsum[k] = 0.0f;
-            }
+                for (int k = 0; k < kFW; ++k)
+                    rowG[tb + ks(k)] = 0.0f;
             for (int w = 1; w <= bx.max_width; w *= 2) {
+                // windows [t, t + w) inside the series
+                const int t_hi = t_end - w;
                 if constexpr (MODE == kBoxLoss) {
+                    if (dm_ok)
 #pragma unroll
-                    for (int k = 0; k < kFW; ++k) {
-                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
-                        const int64_t tg = t0 + t;
-                        if (dm_ok && t < bx.t_stride && tg >= 0 && tg + w <= nt)
-                            part += b[k] * b[k];
-                    }
+                        for (int k = 0; k < kFW; ++k) {
+                            const int t = tb + ks(k);
+                            if (t < t_str && t >= t_lo && t <= t_hi)
+                                part += b[k] * b[k];
+                        }
                 } else {
                     float c[kFW];
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int64_t tg = t0 + 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
-                        c[k] = (dm_ok && tg >= 0 && tg + w <= nt) ? b[k] : 0.0f;
+                        const int t = tb + ks(k);
+                        c[k] = (dm_ok && t >= t_lo && t <= t_hi) ? b[k] : 0.0f;
                     }
                     for (int h = 1; h < w; h *= 2) {
                         if (lane_ok)
 #pragma unroll
                             for (int k = 0; k < kFW; ++k)
-                                rowS[4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3)] = c[k];
+                                rowS[tb + ks(k)] = c[k];
                         lds_wave_sync();
 #pragma unroll
                         for (int k = 0; k < kFW; ++k) {
-                            const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
+                            const int t = tb + ks(k);
                             c[k] += (t >= h && t - h < kFTileT) ? rowS[t - h] : 0.0f;
                         }
                         lds_wave_sync();
                     }
 #pragma unroll
                     for (int k = 0; k < kFW; ++k)
-                        gsum[k] += c[k];
+                        rowG[tb + ks(k)] += c[k];
                 }
                 if (w < bx.max_width) {
                     if (lane_ok)
 #pragma unroll
                         for (int k = 0; k < kFW; ++k)
-                            rowR[4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3)] = b[k];
+                            rowR[tb + ks(k)] = b[k];
                     lds_wave_sync();
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
+                        const int t = tb + ks(k);
                         b[k] += t + w < kFTileT ? rowR[t + w] : 0.0f;
                     }
                     lds_wave_sync();
@@ -1197,19 +1232,18 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
             }
             if constexpr (MODE == kBoxGrad) {
                 if (dm_ok) {
-                    float *row = R.dst + int64_t(ao) * R.dst_pitch;
+                    float *row = R.dst + int64_t(ao) * R.dst_pitch + t0;
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
-                        const int t = 4 * (lane + (k >> 2) * (kWave - 1)) + (k & 3);
-                        const int64_t tg = t0 + t;
-                        if (t >= bx.t_lead && t < bx.t_lead + bx.t_stride && tg >= 0 && tg < nt)
-                            row[tg] = 2.0f * gsum[k];
+                        const int t = tb + ks(k);
+                        if (t >= t_lead && t < t_lead + t_str && t >= t_lo && t < t_end)
+                            row[t] = 2.0f * rowG[t];
                     }
                 }
             }
         }
         if constexpr (MODE == kBoxLoss) {
-            float *red = ldsf + kWavesPerBlock * 2 * kFSpan;
+            float *red = ldsf + kWavesPerBlock * box_rows(MODE) * kFSpan;
             red[tid] = part;
             __syncthreads();
             for (int h = kBlock / 2; h > 0; h >>= 1) {
@@ -1335,7 +1369,7 @@ struct QueueBounds {
 };
 static_assert(dd::kBatchQueues == kXcds, "one queue per XCD");
 
-template <bool DEDUP, int WAVES>
+template <bool DEDUP, int WAVES, int NW>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
                   int ndesc, const QueueBounds qb, const char *ws, int32_t *out,
@@ -1381,7 +1415,7 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
         R.stage_chans = D.stage_chans;
         R.row_words = D.row_words;
         R.widen_every = D.widen_every;
-        dedisp_tile_u8<DEDUP, WAVES>(R, L - D.item_start, lds);
+        dedisp_tile_u8<DEDUP, WAVES, NW>(R, L - D.item_start, lds);
     }
 }
 
@@ -1775,6 +1809,39 @@ void fill_sb_range(const Plan &p, const DeviceTables &t, const RangeInfo &ri, Sb
     R.tb_words = ri.sb_tb_words;
 }
 
+// The direct kernel of a strategy: variant (re-read test), wavefronts and
+// time tile (2 or 4 words of two samples per lane).
+const void *direct_kernel(bool dedup, int waves, int time_tile)
+{
+    const bool w4 = waves == 4, t2 = time_tile == 2 * kWave * 2;
+    if (dedup)
+        return w4 ? (t2 ? reinterpret_cast<const void *>(k_dedisp_u8<true, 4, 2>)
+                        : reinterpret_cast<const void *>(k_dedisp_u8<true, 4, 4>))
+                  : (t2 ? reinterpret_cast<const void *>(k_dedisp_u8<true, 8, 2>)
+                        : reinterpret_cast<const void *>(k_dedisp_u8<true, 8, 4>));
+    return w4 ? (t2 ? reinterpret_cast<const void *>(k_dedisp_u8<false, 4, 2>)
+                    : reinterpret_cast<const void *>(k_dedisp_u8<false, 4, 4>))
+              : (t2 ? reinterpret_cast<const void *>(k_dedisp_u8<false, 8, 2>)
+                    : reinterpret_cast<const void *>(k_dedisp_u8<false, 8, 4>));
+}
+
+// The sub-band kernel of a DM tile and time tile: 16 wavefronts of 12 or 8
+// DMs at 256-sample tiles, or 8 wavefronts of 12 or 8 DMs at 256 or 512.
+const void *subband_kernel(int dm_tile, int time_tile)
+{
+    const bool t2 = time_tile == 2 * kWave * 2;
+    switch (dm_tile) {
+    case 192: return reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 12, 2>);
+    case 128: return reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 8, 2>);
+    case 96:
+        return t2 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 12, 2>)
+                  : reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 12, 4>);
+    default:
+        return t2 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 8, 2>)
+                  : reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 8, 4>);
+    }
+}
+
 dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const char *d_ws,
                     hipStream_t stream)
 {
@@ -1794,10 +1861,7 @@ dd_status sum_u8_sb(const Plan &p, const DeviceTables &t, int32_t *d_out, const 
     const int64_t grid = a.per_xcd * kXcds;
     // dm_tile 192 and 128: 16 wavefronts of 12 or 8 DMs x 2 words; 96 and
     // 64: 8 wavefronts of 12 or 8 DMs x 4 words (the plan's time tile matches)
-    const void *fn = p.dm_tile == 192 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 12, 2>)
-                     : p.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<16, 8, 2>)
-                     : p.dm_tile == 96 ? reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 12, 4>)
-                                       : reinterpret_cast<const void *>(k_dedisp_u8_sb<8, 8, 4>);
+    const void *fn = subband_kernel(p.dm_tile, p.time_tile);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(dd::kMaxLdsBytes));
     void *args[] = {&a};
@@ -1838,13 +1902,7 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
         R.widen_every = ri.widen_every;
     }
     const int64_t grid = a.per_xcd * kXcds;
-    const void *fn = nullptr;
-    if (p.waves == 4)
-        fn = p.dedup ? reinterpret_cast<const void *>(k_dedisp_u8<true, 4>)
-                     : reinterpret_cast<const void *>(k_dedisp_u8<false, 4>);
-    else
-        fn = p.dedup ? reinterpret_cast<const void *>(k_dedisp_u8<true, 8>)
-                     : reinterpret_cast<const void *>(k_dedisp_u8<false, 8>);
+    const void *fn = direct_kernel(p.dedup, p.waves, p.time_tile);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               int(dd::kMaxLdsBytes));
     void *args[] = {&a};
@@ -2020,9 +2078,9 @@ int64_t box_batch(const Plan &p, const DeviceTables &t, const char *d_ws, float 
     return blocks;
 }
 
-size_t box_lds(const Plan &p)
+size_t box_lds(const Plan &p, int mode)
 {
-    return std::max(p.lds_bytes, size_t(kWavesPerBlock * 2 * kFSpan + kBlock) * sizeof(float));
+    return std::max(p.lds_bytes, size_t(kWavesPerBlock * box_rows(mode) * kFSpan + kBlock) * sizeof(float));
 }
 
 dd_status boxcar_loss_f32(const Plan &p, const DeviceTables &t, const float *d_in, int32_t nbeams,
@@ -2044,7 +2102,7 @@ dd_status boxcar_loss_f32(const Plan &p, const DeviceTables &t, const float *d_i
         bx.t_stride = dd::kBoxLossStride;
         bx.t_lead = 0;
         bx.max_width = max_width;
-        st = launch_sum_mode<kBoxLoss>(a, blocks, box_lds(p), bx, stream);
+        st = launch_sum_mode<kBoxLoss>(a, blocks, box_lds(p, kBoxLoss), bx, stream);
         if (st != DD_OK)
             return st;
         hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, stream, partial, int(blocks),
@@ -2079,7 +2137,7 @@ dd_status boxcar_backward_f32(const Plan &p, const DeviceTables &t, const float 
         bx.t_stride = dd::kBoxGradStride;
         bx.t_lead = dd::kBoxLead;
         bx.max_width = max_width;
-        st = launch_sum_mode<kBoxGrad>(a, blocks, box_lds(p), bx, stream);
+        st = launch_sum_mode<kBoxGrad>(a, blocks, box_lds(p, kBoxGrad), bx, stream);
         if (st != DD_OK)
             return st;
         st = adjoint_f32(p, t, gout, d_in + xoff, d_w, d_dx ? d_dx + xoff : nullptr,
@@ -2317,6 +2375,35 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
 // Persistent workgroups per XCD: two per CU of its 32.
 constexpr int kPersistPerXcd = 64;
 
+const void *direct_batch_kernel(bool dedup, int waves, int time_tile)
+{
+    const bool w4 = waves == 4, t2 = time_tile == 2 * kWave * 2;
+    if (dedup)
+        return w4 ? (t2 ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4, 2>)
+                        : reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4, 4>))
+                  : (t2 ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8, 2>)
+                        : reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8, 4>));
+    return w4 ? (t2 ? reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4, 2>)
+                    : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4, 4>))
+              : (t2 ? reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8, 2>)
+                    : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8, 4>));
+}
+
+const void *subband_batch_kernel(int dm_tile, int time_tile)
+{
+    const bool t2 = time_tile == 2 * kWave * 2;
+    switch (dm_tile) {
+    case 192: return reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 12, 2>);
+    case 128: return reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 8, 2>);
+    case 96:
+        return t2 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 2>)
+                  : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 4>);
+    default:
+        return t2 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 2>)
+                  : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
+    }
+}
+
 dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
                         int32_t *d_out, char *d_ws, hipStream_t stream)
 {
@@ -2354,17 +2441,10 @@ dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d
         // of its 32; variant 3 fills a CU's LDS with one workgroup.
         unsigned per_xcd = unsigned(kPersistPerXcd * (8 / G.waves));
         if (G.subband) {
-            fn = G.dm_tile == 192  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 12, 2>)
-                 : G.dm_tile == 128 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<16, 8, 2>)
-                 : G.dm_tile == 96  ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 12, 4>)
-                                    : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
+            fn = subband_batch_kernel(G.dm_tile, G.time_tile);
             per_xcd = unsigned(kCusPerXcd);
-        } else if (G.waves == 4) {
-            fn = G.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 4>)
-                         : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 4>);
         } else {
-            fn = G.dedup ? reinterpret_cast<const void *>(k_dedisp_u8_batch<true, 8>)
-                         : reinterpret_cast<const void *>(k_dedisp_u8_batch<false, 8>);
+            fn = direct_batch_kernel(G.dedup, G.waves, G.time_tile);
         }
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(dd::kMaxLdsBytes - 64));

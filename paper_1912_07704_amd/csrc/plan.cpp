@@ -108,9 +108,10 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         }
     }
     sp.span = span;
-    // a delay o <= span + 3 inside the window; lane 63 of the second half
-    // reads the granule at 4*(o >> 2) + 4*126, up to float 4*(o >> 2) + 507
-    sp.row_words = (span + 3 + 4 * 127 + 3) / 4 * 4;
+    // a delay o <= span + 3 inside the window; lane 63 reads its last
+    // granule at 4*(o >> 2) + 4*63*G (G granules per lane), up to float
+    // 4*(o >> 2) + 252*G + 3
+    sp.row_words = (span + 3 + 252 * (kF32Words / 4) + 3 + 1 + 3) / 4 * 4;
     int32_t stage = want_stage > 0 ? std::max(1, std::min(want_stage, kF32MaxStage)) : kF32MaxStage;
     if (stage > 1)
         stage &= ~1;
@@ -415,8 +416,11 @@ dd_status build_subband(Plan *p, int32_t want_stage, std::string *err)
     // dm_tile 128 and 192: 16 wavefronts of 8 or 12 DMs, 2 words (4 samples)
     // per lane; 64 and 96: 8 wavefronts of 8 or 12 DMs, 4 words per lane.
     const bool wide = dmt >= 128;
-    const int32_t T = wide ? kTimeTile / 2 : kTimeTile;
-    p->time_tile = T;
+    const int32_t T = p->time_tile;
+    if (wide && T != kTimeTile / 2) {
+        *err = fmt("variant 3 at ", dmt, "-DM tiles runs ", kTimeTile / 2, "-sample time tiles only");
+        return DD_ERR_INVALID;
+    }
     p->waves = wide ? 2 * kWaves : kWaves;
     int64_t blocks = 0;
     size_t lds = 0;
@@ -628,7 +632,7 @@ dd_status build_direct(Plan *p, int32_t want_stage, std::string *err)
                 span = std::max(span, s1[c] - s0[c]);
         }
         ri.span = span;
-        const int32_t imax = 64 * kWaveWords + 2 + ((span + 1) >> 1);
+        const int32_t imax = p->time_tile / 2 + 2 + ((span + 1) >> 1);
         ri.row_words = (imax + 2 + 3) / 4 * 4;
         const int32_t cap = dtype == DD_U8 ? int32_t(65535 / (255 * ri.ds)) : kMaxStageChans;
         int32_t stage = std::max(1, std::min(want_stage > 0 ? want_stage : kMaxStageChans, cap));
@@ -650,7 +654,7 @@ dd_status build_direct(Plan *p, int32_t want_stage, std::string *err)
         ri.stage_chans = stage;
         ri.widen_every = std::max(1, cap / stage);
         lds = std::max(lds, bytes_for(stage));
-        ri.ntime_tiles = (ri.nout + kTimeTile - 1) / kTimeTile;
+        ri.ntime_tiles = (ri.nout + p->time_tile - 1) / p->time_tile;
         ri.ndm_tiles = (ri.ndms + dmt - 1) / dmt;
         ri.ndms_pad = ri.ndm_tiles * dmt;
         ri.block_start = blocks;
@@ -715,6 +719,11 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
     const int32_t want_variant = opts ? opts->variant : 0;
     const int32_t want_stage = opts ? opts->stage_chans : 0;
     const int32_t want_dm_tile = opts ? opts->dm_tile : 0;
+    const int32_t want_time_tile = opts ? opts->time_tile : 0;
+    if (want_time_tile != 0 && want_time_tile != kTimeTile / 2 && want_time_tile != kTimeTile) {
+        *err = fmt("options: time_tile must be 0, ", kTimeTile / 2, " or ", kTimeTile);
+        return DD_ERR_INVALID;
+    }
     if (want_variant < 0 || want_variant > 3 || want_stage < 0) {
         *err = "options: variant must be 0 to 3 and stage_chans >= 0";
         return DD_ERR_INVALID;
@@ -884,7 +893,11 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             p->subband = variant == 3;
             p->dm_tile = dm_tile;
             p->waves = dm_tile / kDmPerWave;
-            p->time_tile = kTimeTile;
+            // variant 3 at 192- and 128-DM tiles: 256-sample tiles; else the
+            // requested time tile, 512 by default
+            p->time_tile = want_time_tile ? want_time_tile
+                           : (variant == 3 && dm_tile >= 128) ? kTimeTile / 2
+                                                              : kTimeTile;
             return p->subband ? build_subband(p, want_stage, e) : build_direct(p, want_stage, e);
         };
         if (want_variant != 0)

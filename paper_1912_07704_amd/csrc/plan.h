@@ -45,25 +45,25 @@ constexpr size_t kWsAlign = 256;
 // gradient with P zeros on both sides, S = P - s).  A workgroup owns
 // kF32OutTile outputs (kF32PerWave per wave) by kF32TimeTile samples.
 // Samples come from LDS in aligned 4-float granules (one 16-byte read
-// each): lane l holds granules l and l + 63 of the tile, i.e. samples
-// 4(l + 63k) + j (k < 2, j < 4).  A delay that is not a multiple of 4 takes
+// each): lane l holds granules l + 63g (g < kF32Words/4) of the tile, i.e.
+// samples 4(l + 63g) + j (j < 4).  A delay that is not a multiple of 4 takes
 // the granule's tail from the lane itself and its head from the next lane
-// (a cross-lane move fused into the add); lane 63 only supplies that head,
-// so a tile is 63 granules x 2 = 504 samples wide and the lanes span 512.
-constexpr int kF32Words = 8;                     // samples per lane
+// (a cross-lane move fused into the add); lane 63 only supplies those heads,
+// so a tile is 63 granules x 4 = 1008 samples wide and the lanes span 1024.
+constexpr int kF32Words = 16;                    // samples per lane
 constexpr int kF32PerWave = 4;
-constexpr int kF32TileSpan = 64 * kF32Words;     // 512: samples the lanes cover
-constexpr int kF32TimeTile = 63 * kF32Words;     // 504: samples a tile computes
+constexpr int kF32TileSpan = 64 * kF32Words;     // 1024: samples the lanes cover
+constexpr int kF32TimeTile = 63 * kF32Words;     // 1008: samples a tile computes
 constexpr int kF32OutTile = kWaves * kF32PerWave;
 constexpr int kF32MaxStage = 16;
 // Boxcar loss tiles: the loss tile counts windows starting in its first
 // kBoxLossStride samples; the gradient tile writes dL/dout for its samples
 // [kBoxLead, kBoxLead + kBoxGradStride).  Both keep the 31-sample reach of
-// the widest (32-sample) window inside the 504-sample tile.
+// the widest (32-sample) window inside the 1008-sample tile.
 constexpr int kBoxMaxWidth = 32;
-constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 472
+constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 976
 constexpr int kBoxLead = kBoxMaxWidth;                                // 32
-constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 440
+constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 944
 
 struct SumProblem {
     int32_t nrows = 0;          // b: rows summed
@@ -229,7 +229,7 @@ void set_error(const std::string &msg);
 void clear_error();
 
 // A batch of integer plans (beams) summed by persistent launches, one per
-// group of plans that share a kernel (variant family, DM tile).  Inputs and
+// group of plans that share a kernel (variant family, DM tile, time tile).  Inputs and
 // outputs of all beams share one buffer each, at fixed offsets.
 struct BatchDescHost {
     int32_t beam = 0;
@@ -245,6 +245,7 @@ struct BatchGroup {
     bool subband = false;                  // variant 3 (else the direct kernel)
     bool dedup = false;                    // direct kernel: variant 2
     int32_t dm_tile = kDmTile;
+    int32_t time_tile = kTimeTile;
     int32_t waves = kWaves;
     size_t lds_bytes = 0;
     size_t desc_begin = 0, desc_end = 0;   // its (beam, range) descriptors in Batch::descs

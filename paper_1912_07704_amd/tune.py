@@ -2,9 +2,9 @@
 strategy decides how input data are split and processed on the GPU).
 
 For one integer plan signature it times the shift-and-sum step of every
-candidate strategy -- kernel variant x DM tile (which fixes the time tile:
-256 samples for 16-wavefront workgroups, 512 for 8) x channels per LDS
-stage -- on the current device, checks that every candidate's output is
+candidate strategy -- kernel variant x DM tile x time tile (256 or 512
+output samples per workgroup) x channels per LDS stage -- on the current
+device, checks that every candidate's output is
 bit-identical to the first one's, and keeps the fastest.  Beams of one plan
 class (same band, sampling and DM plan, any length) share one tuned
 strategy (class_strategy).  Float32 plans tune the rows per LDS stage of
@@ -30,15 +30,18 @@ DD_ERR_EMPTY_OUTPUT = -3
 VARIANTS = (1, 2)
 DM_TILES = (64, 32)
 STAGES = (16, 8, 4)
-# variant 3 (exact sub-band reuse): its own DM tiles; stages of one or two
-# 8-channel sub-bands
-SUBBAND = [(192, 16), (192, 8), (128, 16), (128, 8), (96, 16), (64, 16)]
+TIME_TILES = (512, 256)
+# variant 3 (exact sub-band reuse): its own DM tiles and time tiles (256
+# samples only for the 16-wavefront tiles of 192 and 128 DMs); stages of one
+# or two 8-channel sub-bands
+SUBBAND = [(192, 16, 256), (192, 8, 256), (128, 16, 256), (128, 8, 256), (96, 16, 512),
+           (96, 16, 256), (64, 16, 512), (64, 16, 256)]
 
 
 def candidates():
-    c = [{"variant": v, "dm_tile": d, "stage_chans": s}
-         for v in VARIANTS for d in DM_TILES for s in STAGES]
-    c += [{"variant": 3, "dm_tile": d, "stage_chans": s} for d, s in SUBBAND]
+    c = [{"variant": v, "dm_tile": d, "stage_chans": s, "time_tile": t}
+         for v in VARIANTS for d in DM_TILES for s in STAGES for t in TIME_TILES]
+    c += [{"variant": 3, "dm_tile": d, "stage_chans": s, "time_tile": t} for d, s, t in SUBBAND]
     return c
 
 

@@ -97,9 +97,9 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
                         const int o = q4 + cls;      // delay in the window
                         CHECK(m + o == S(av, b), "[%s] a %d b %d: window %d + %d != delay %d", name, av, b, m, o, S(av, b));
                         // the lanes' granules
-                        double gr[64][2][4];
+                        double gr[64][kF32Words / 4][4];
                         for (int l = 0; l < 64; ++l)
-                            for (int k = 0; k < 2; ++k)
+                            for (int k = 0; k < kF32Words / 4; ++k)
                                 for (int j = 0; j < 4; ++j) {
                                     const long li = buf + ent + 4 * (l + 63 * k) + j;
                                     CHECK(li >= buf && li < buf + long(C) * Wr, "[%s] LDS read %ld", name, li);
@@ -113,12 +113,12 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
                                     gr[l][k][j] = lds[li];
                                 }
                         for (int l = 0; l < 64; ++l)
-                            for (int k = 0; k < 2; ++k)
+                            for (int k = 0; k < kF32Words / 4; ++k)
                                 for (int j = 0; j < 4; ++j) {
                                     double v;
                                     if (j + cls < 4) v = gr[l][k][j + cls];
                                     else v = l < 63 ? gr[l + 1][k][j + cls - 4] : 0.0;
-                                    acc[(size_t(al) * 64 + l) * 8 + 4 * k + j] += v;
+                                    acc[(size_t(al) * 64 + l) * kF32Words + 4 * k + j] += v;
                                 }
                     }
                 for (int j = 0; j < bn; ++j)
@@ -130,7 +130,7 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
             const int a = tile * kF32OutTile + al;
             if (a >= sp.nouts) continue;
             for (int l = 0; l < 63; ++l)
-                for (int k = 0; k < 2; ++k)
+                for (int k = 0; k < kF32Words / 4; ++k)
                     for (int j = 0; j < 4; ++j) {
                         const long t = t0 + 4 * (l + 63 * k) + j;
                         if (t >= sp.nt) continue;
@@ -139,7 +139,7 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
                             const long gi = src0 + long(b) * pitch + t + S(a, b);
                             want += src[gi];
                         }
-                        const double got = acc[(size_t(al) * 64 + l) * 8 + 4 * k + j];
+                        const double got = acc[(size_t(al) * 64 + l) * kF32Words + 4 * k + j];
                         CHECK(got == want, "[%s] a %d t %ld: %g != %g", name, a, t, got, want);
                         ++checked;
                     }

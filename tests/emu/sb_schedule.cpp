@@ -78,11 +78,13 @@ static uint32_t alignbyte(uint32_t hi, uint32_t lo, int sh) {
 
 enum { TAG_WIN = 1000000, TAG_TAB = 2000000, TAG_Q = 3000000 };
 
+static int g_time_tile = 0;     // the time tile the runs ask for (0 = the tile's default)
+
 int run(const std::vector<double> &freqs, double tsamp, int64_t nsamp, const std::vector<dd_range> &rg,
         int dm_tile, int stage, int seed, int block_stride, const char *name)
 {
     Plan P; std::string err;
-    dd_options o{3, stage, dm_tile};
+    dd_options o{3, stage, dm_tile, g_time_tile};
     dd_status stt = build_plan(freqs.data(), int(freqs.size()), tsamp, nsamp, rg.data(), int(rg.size()), DD_U8, &o, &P, &err);
     if (stt != DD_OK) { printf("[%s] plan: %d %s\n", name, int(stt), err.c_str()); return 0; }
     const int nch = P.nchans;
@@ -310,9 +312,17 @@ int main(int argc, char **argv)
     const char *which = argc > 1 ? argv[1] : "small";
     const int stride = argc > 2 ? std::max(1, atoi(argv[2])) : (strcmp(which, "small") ? 997 : 1);
     if (!strcmp(which, "small")) {
-        for (int dt : {192, 128, 96, 64}) {
+        // every DM tile at its default time tile, then the 8-wavefront tiles
+        // (96 and 64 DMs) at 256-sample time tiles
+        const int tiles[6][2] = {{192, 0}, {128, 0}, {96, 0}, {64, 0}, {96, 256}, {64, 256}};
+        for (const auto &tl : tiles) {
+            const int dt = tl[0];
+            g_time_tile = tl[1];
             char nm[64];
-            auto N = [&](const char *s) { snprintf(nm, sizeof nm, "%s-dt%d", s, dt); return nm; };
+            auto N = [&](const char *s) {
+                snprintf(nm, sizeof nm, "%s-dt%d-tt%d", s, dt, g_time_tile);
+                return nm;
+            };
             const std::vector<dd_range> fine = {{0, 30, 0.1, 1}, {30, 60, 0.2, 2}};
             run(band(1500, 1200, 128), 256e-6, 65536 / 4, {{0, 100, 1, 1}}, dt, 0, 1, stride, N("128ch"));
             run(band(1670, 1370, 300), 64e-6, 20000, fine, dt, 0, 10, stride, N("300ch"));

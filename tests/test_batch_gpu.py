@@ -38,7 +38,9 @@ def small_beams(seed, n, subband=False):
 # different kernels, one persistent launch per kernel), the direct kernel,
 # and variant 3 at each of its workgroup shapes
 STRATEGIES = {"auto": {}, "direct": {"variant": 1}, "v3-192": {"variant": 3},
-              "v3-128": {"variant": 3, "dm_tile": 128}, "v3-96": {"variant": 3, "dm_tile": 96}}
+              "v3-128": {"variant": 3, "dm_tile": 128}, "v3-96": {"variant": 3, "dm_tile": 96},
+              "direct-t256": {"variant": 1, "time_tile": 256},
+              "v3-64-t256": {"variant": 3, "dm_tile": 64, "time_tile": 256}}
 
 
 def make_plans(beams, opts):

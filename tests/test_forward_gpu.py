@@ -24,8 +24,9 @@ def say(*a):
 
 
 # the library default (variant 3 where its patterns fit the LDS, else the
-# direct kernel) and both direct variants
-STRATEGIES = {"default": {}, "v1": {"variant": 1}, "v2": {"variant": 2}}
+# direct kernel) and both direct variants at both time tiles
+STRATEGIES = {"default": {}, "v1": {"variant": 1}, "v2": {"variant": 2},
+              "v1-t256": {"variant": 1, "time_tile": 256}, "v2-t256": {"variant": 2, "time_tile": 256}}
 
 
 def gpu_forward(x, freqs, tsamp, ranges, out_extra=0, canary=-123456789, opts=None):
@@ -97,6 +98,34 @@ def test_random_shapes_bit_exact(seed, strategy):
     got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=64, opts=STRATEGIES[strategy])
     assert np.array_equal(got[: plan.out_elems], oracle_flat(x, freqs, tsamp, ranges))
     assert (got[plan.out_elems:] == -123456789).all()
+
+
+# variant 3 at every workgroup shape it accepts: (DM tile, time tile)
+SUBBAND_SHAPES = [(192, 256), (128, 256), (96, 512), (96, 256), (64, 512), (64, 256)]
+
+
+@pytest.mark.parametrize("dm_tile,time_tile", SUBBAND_SHAPES)
+def test_subband_shapes_bit_exact(dm_tile, time_tile):
+    """Random shapes through variant 3 at each of its workgroup shapes (the
+    shapes whose sub-band patterns exceed the LDS are skipped; at least a
+    few must fit)."""
+    ran = 0
+    for seed in range(12):
+        x, freqs, tsamp, ranges = random_case(100 + seed)
+        try:
+            plan = dd.Plan(freqs, tsamp, x.shape[1], ranges, "u8", variant=3, dm_tile=dm_tile,
+                           time_tile=time_tile)
+        except dd.DDError:
+            continue                                # patterns beyond the LDS
+        plan.close()
+        say("subband", dm_tile, time_tile, seed, x.shape, ranges)
+        got, plan = gpu_forward(x, freqs, tsamp, ranges, out_extra=64,
+                                opts={"variant": 3, "dm_tile": dm_tile, "time_tile": time_tile})
+        assert plan.strategy["time_tile"] == time_tile and plan.strategy["dm_tile"] == dm_tile
+        assert np.array_equal(got[: plan.out_elems], oracle_flat(x, freqs, tsamp, ranges))
+        assert (got[plan.out_elems:] == -123456789).all()
+        ran += 1
+    assert ran >= 3
 
 
 EDGES = {
