@@ -385,7 +385,8 @@ def bin_input(x, plan: Plan, ws, weights=None, stream=None):
 def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=True, ws=None,
             stream=None):
     """Gradients of sum(grad_out * forward(x, w)) for an f32 plan
-    (dd_adjoint).  Returns (dX or None, dw or None)."""
+    (dd_adjoint).  Returns (dX or None, dw or None).  grad_in may be a
+    contiguous device float32 [nchans, nsamp] tensor to write dX into."""
     import torch
     if plan.dtype != "f32":
         raise ValueError("the adjoint is defined for f32 plans")
@@ -398,7 +399,15 @@ def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=Tru
         _check_input(x, plan)
     _check_weights(weights, plan)
     dev = grad_out.device
-    dx = torch.empty((plan.nchans, plan.nsamp), dtype=torch.float32, device=dev) if grad_in else None
+    if isinstance(grad_in, torch.Tensor):
+        if (grad_in.dtype != torch.float32 or grad_in.device != dev or not grad_in.is_contiguous()
+                or tuple(grad_in.shape) != (plan.nchans, plan.nsamp)):
+            raise ValueError(f"grad_in must be a contiguous float32 [{plan.nchans}, {plan.nsamp}] "
+                             "tensor on grad_out's device")
+        dx = grad_in
+    else:
+        dx = (torch.empty((plan.nchans, plan.nsamp), dtype=torch.float32, device=dev)
+              if grad_in else None)
     dw = torch.empty(plan.nchans, dtype=torch.float32, device=dev) if grad_w else None
     if ws is None:
         ws = workspace(plan, dev)

@@ -834,36 +834,87 @@ constexpr int kFSpan = dd::kF32TileSpan;        // samples the lanes cover
 __device__ __forceinline__ constexpr int ks(int k) { return 4 * (kWave - 1) * (k >> 2) + (k & 3); }
 constexpr int kFTileA = dd::kF32OutTile;
 
+// One thread per 4 consecutive outputs.  VEC: the source rows and the
+// destination rows start on 16-byte boundaries, so a group's 4*factor
+// source floats are `factor` aligned float4 loads and its outputs one
+// float4 store; F (when nonzero) fixes the factor at compile time.
+template <bool VEC, int F>
 __global__ __launch_bounds__(256) void k_level_f32(const float *__restrict__ src, int64_t src_pitch,
                                                    const float *__restrict__ w,
                                                    float *__restrict__ dst, int64_t dst_pitch,
                                                    int64_t nbin, int factor, int nchans)
 {
+    const int f = F ? F : factor;
+    const int64_t ngroups = (nbin + 3) >> 2;
     for (int64_t c = blockIdx.y; c < nchans; c += gridDim.y) {
         const float *row = src + c * src_pitch;
         float *out = dst + c * dst_pitch;
         const float wc = w ? w[c] : 1.0f;
-        for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nbin;
-             t += int64_t(gridDim.x) * blockDim.x) {
-            const float *p = row + t * factor;
-            float s = 0.0f;
-            for (int k = 0; k < factor; ++k)
-                s += p[k];
-            out[t] = w ? wc * s : s;
+        for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < ngroups;
+             q += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t t = 4 * q;
+            float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (VEC && t + 4 <= nbin) {
+                const float4 *p = reinterpret_cast<const float4 *>(row + t * f);
+                if (F == 1) {
+                    const float4 v = p[0];
+                    s[0] = v.x;
+                    s[1] = v.y;
+                    s[2] = v.z;
+                    s[3] = v.w;
+                } else if (F == 2) {
+                    const float4 u = p[0], v = p[1];
+                    s[0] = u.x + u.y;
+                    s[1] = u.z + u.w;
+                    s[2] = v.x + v.y;
+                    s[3] = v.z + v.w;
+                } else {
+                    // other factors: sample by sample
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        for (int k = 0; k < f; ++k)
+                            s[j] += row[(t + j) * f + k];
+                }
+                if (w) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        s[j] *= wc;
+                }
+                *reinterpret_cast<float4 *>(out + t) = make_float4(s[0], s[1], s[2], s[3]);
+            } else {
+                for (int j = 0; j < 4 && t + j < nbin; ++j) {
+                    const float *p = row + (t + j) * f;
+                    float acc = 0.0f;
+                    for (int k = 0; k < f; ++k)
+                        acc += p[k];
+                    out[t + j] = w ? wc * acc : acc;
+                }
+            }
         }
     }
 }
 
+// The output gradient of one range with P zeros in front (and zeros up to
+// the row pitch): 4 consecutive padded samples per thread, one aligned
+// float4 store (the padded rows start on 16-byte boundaries, the gradient
+// rows need not).
 __global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ g, int64_t nout,
                                                       int64_t P, float *__restrict__ gpad,
                                                       int64_t gpitch, int nrows)
 {
+    const int64_t ngroups = gpitch >> 2;
     for (int64_t d = blockIdx.y; d < nrows; d += gridDim.y) {
         const float *row = g + d * nout;
         float *out = gpad + d * gpitch;
-        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < gpitch;
-             i += int64_t(gridDim.x) * blockDim.x)
-            out[i] = (i >= P && i < P + nout) ? row[i - P] : 0.0f;
+        for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < ngroups;
+             q += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t i = 4 * q;
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                v[j] = (i + j >= P && i + j < P + nout) ? row[i + j - P] : 0.0f;
+            *reinterpret_cast<float4 *>(out + i) = make_float4(v[0], v[1], v[2], v[3]);
+        }
     }
 }
 
@@ -1277,26 +1328,66 @@ struct FinArgs {
     int32_t nchunks;
 };
 
+// A thread handles 4 consecutive samples.  VEC: the rows of x and dX start
+// on 16-byte boundaries, so those are float4 accesses; G rows always do.
+// A range's bin index t / ds is stepped sample by sample after one division.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_adj_finalize(const FinArgs a)
 {
     __shared__ float red[256];
     const int64_t c = blockIdx.y;
     const int chunk = blockIdx.x;
-    const int64_t t_begin = int64_t(chunk) * a.chunk_len;
+    const int64_t t_begin = int64_t(chunk) * a.chunk_len;   // a multiple of 4
     const int64_t t_end = min(a.nsamp, t_begin + a.chunk_len);
     const float wc = a.w ? a.w[c] : 1.0f;
     float acc = 0.0f;
-    for (int64_t t = t_begin + threadIdx.x; t < t_end; t += 256) {
-        float g = 0.0f;
+    for (int64_t t = t_begin + 4 * int64_t(threadIdx.x); t < t_end; t += 4 * 256) {
+        const int n = int(min<int64_t>(4, t_end - t));
+        float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int r = 0; r < a.nranges; ++r) {
             const FinRange &R = a.r[r];
-            if (t < int64_t(R.ds) * R.nbin)
-                g += R.G[c * R.Gpitch + t / R.ds];
+            const float *Gr = R.G + c * R.Gpitch;
+            const int64_t lim = int64_t(R.ds) * R.nbin;      // samples inside a whole bin
+            if (R.ds == 1 && t + 4 <= lim) {
+                const float4 v = *reinterpret_cast<const float4 *>(Gr + t);
+                g[0] += v.x;
+                g[1] += v.y;
+                g[2] += v.z;
+                g[3] += v.w;
+            } else {
+                int64_t q = t < 0xFFFFFFFFll ? int64_t(uint32_t(t) / uint32_t(R.ds)) : t / R.ds;
+                int rr = int(t - q * R.ds);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (t + j < lim)
+                        g[j] += Gr[q];
+                    if (++rr == R.ds) {
+                        rr = 0;
+                        ++q;
+                    }
+                }
+            }
         }
-        if (a.dX)
-            a.dX[c * a.nsamp + t] = wc * g;
-        if (a.x)
-            acc += a.x[c * a.nsamp + t] * g;
+        float *dx = a.dX ? a.dX + c * a.nsamp + t : nullptr;
+        const float *xs = a.x ? a.x + c * a.nsamp + t : nullptr;
+        if (VEC && n == 4) {
+            if (dx)
+                *reinterpret_cast<float4 *>(dx) = make_float4(wc * g[0], wc * g[1], wc * g[2], wc * g[3]);
+            if (xs) {
+                const float4 xv = *reinterpret_cast<const float4 *>(xs);
+                acc += xv.x * g[0];
+                acc += xv.y * g[1];
+                acc += xv.z * g[2];
+                acc += xv.w * g[3];
+            }
+        } else {
+            for (int j = 0; j < n; ++j) {
+                if (dx)
+                    dx[j] = wc * g[j];
+                if (xs)
+                    acc += xs[j] * g[j];
+            }
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -1914,21 +2005,41 @@ dd_status sum_u8(const Plan &p, const DeviceTables &t, int32_t *d_out, const cha
 }
 
 
+// k_level_f32 for one level: the vector form when the source rows start on
+// 16-byte boundaries (the level buffers' rows always do), factors 1 and 2
+// compiled apart.
+void launch_level_f32(const float *src, int64_t src_pitch, const float *w, float *dst,
+                      int64_t dst_pitch, int64_t nbin, int factor, int nchans, hipStream_t stream)
+{
+    const dim3 grid(unsigned(std::min<int64_t>((nbin + 1023) / 1024, 1024)),
+                    unsigned(std::min<int32_t>(nchans, 65535)));
+    const bool vec = reinterpret_cast<uintptr_t>(src) % 16 == 0 && src_pitch % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(dst) % 16 == 0 && dst_pitch % 4 == 0;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, stream, src, src_pitch, w, dst, dst_pitch, nbin,
+                           factor, nchans);
+    };
+    if (!vec)
+        go(k_level_f32<false, 0>);
+    else if (factor == 1)
+        go(k_level_f32<true, 1>);
+    else if (factor == 2)
+        go(k_level_f32<true, 2>);
+    else
+        go(k_level_f32<true, 0>);
+}
+
 dd_status bin_f32(const Plan &p, const float *d_in, const float *d_w, char *d_ws, hipStream_t stream)
 {
     for (const dd::BinLevel &lv : p.levels) {
         float *dst = reinterpret_cast<float *>(d_ws + lv.ws_offset) + lv.lead;
-        const dim3 grid(unsigned(std::min<int64_t>((lv.nbin + 255) / 256, 1024)),
-                        unsigned(std::min<int32_t>(p.nchans, 65535)));
         if (lv.src < 0) {
-            hipLaunchKernelGGL(k_level_f32, grid, dim3(256), 0, stream, d_in, p.nsamp, d_w, dst,
-                               lv.pitch, lv.nbin, lv.factor, p.nchans);
+            launch_level_f32(d_in, p.nsamp, d_w, dst, lv.pitch, lv.nbin, lv.factor, p.nchans, stream);
         } else {
             const dd::BinLevel &sl = p.levels[lv.src];
             const float *src = reinterpret_cast<const float *>(d_ws + sl.ws_offset) + sl.lead;
-            hipLaunchKernelGGL(k_level_f32, grid, dim3(256), 0, stream, src, sl.pitch,
-                               static_cast<const float *>(nullptr), dst, lv.pitch, lv.nbin,
-                               lv.factor, p.nchans);
+            launch_level_f32(src, sl.pitch, nullptr, dst, lv.pitch, lv.nbin, lv.factor, p.nchans,
+                             stream);
         }
         dd_status st = launch_check("k_level_f32");
         if (st != DD_OK)
@@ -2010,7 +2121,7 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
     for (size_t i = 0; i < p.ranges.size(); ++i) {
         const RangeInfo &ri = p.ranges[i];
         float *gpad = reinterpret_cast<float *>(d_ws + ri.gpad_offset);
-        const dim3 grid(unsigned(std::min<int64_t>((ri.gpitch + 255) / 256, 1024)),
+        const dim3 grid(unsigned(std::min<int64_t>((ri.gpitch + 1023) / 1024, 1024)),
                         unsigned(std::min<int32_t>(ri.ndms, 65535)));
         hipLaunchKernelGGL(k_pad_rows_f32, grid, dim3(256), 0, stream, d_g + ri.out_offset,
                            ri.nout, int64_t(ri.max_shift), gpad, ri.gpitch, ri.ndms);
@@ -2041,8 +2152,13 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
     f.nsamp = p.nsamp;
     f.chunk_len = p.dw_chunk_len;
     f.nchunks = p.dw_chunks;
-    hipLaunchKernelGGL(k_adj_finalize, dim3(unsigned(p.dw_chunks), unsigned(p.nchans)), dim3(256),
-                       0, stream, f);
+    const bool vec = p.nsamp % 4 == 0 && reinterpret_cast<uintptr_t>(f.x) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(f.dX) % 16 == 0;
+    const dim3 fgrid(unsigned(p.dw_chunks), unsigned(p.nchans));
+    if (vec)
+        hipLaunchKernelGGL(k_adj_finalize<true>, fgrid, dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL(k_adj_finalize<false>, fgrid, dim3(256), 0, stream, f);
     st = launch_check("k_adj_finalize");
     if (st != DD_OK || !d_dw)
         return st;
