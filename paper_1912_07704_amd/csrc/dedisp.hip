@@ -1003,42 +1003,64 @@ __device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int
 //             for the tile's samples [t_lead, t_lead + t_stride).
 // Boxcar sums are formed by doubling, B_2w[t] = B_w[t] + B_w[t + w], through
 // one LDS row per wave; the window sums of the gradient likewise.
-enum { kWrite = 0, kBoxLoss = 1, kBoxGrad = 2 };
+//   kAdjFinal the adjoint of a plan with one range at full resolution: its
+//             outputs are the channels' G, so the epilogue writes
+//             dX[c][t] = w_c * G[c][t] and one partial per (channel, time
+//             tile) of dw_c = sum_t x[c][t] * G[c][t] (fixed-order sums);
+//             G itself is never stored.
+enum { kWrite = 0, kBoxLoss = 1, kBoxGrad = 2, kAdjFinal = 3 };
 
 // LDS rows of kFSpan floats per wave that a boxcar epilogue uses
 __host__ __device__ constexpr int box_rows(int mode) { return mode == kBoxGrad ? 2 : 1; }
 
 struct BoxArgs {
-    float *partial;           // kBoxLoss: one float per workgroup
+    float *partial;           // kBoxLoss: one float per workgroup; kAdjFinal:
+                              // [nouts][time tiles] weight-gradient partials
     int64_t t_stride;         // samples between consecutive time tiles
     int64_t t_lead;           // the first tile starts at sample -t_lead
     int32_t max_width;        // largest boxcar width (a power of two <= 32)
-    int32_t pad_;
+    int32_t ntime_tiles;      // kAdjFinal: time tiles per output (partials' row length)
+    const float *x;           // kAdjFinal: input rows (NULL: no weight gradient)
+    const float *w;           // kAdjFinal: channel weights (NULL: all 1)
+    float *dX;                // kAdjFinal: input-gradient rows (NULL: not wanted)
+    int64_t x_pitch;          // kAdjFinal: floats between rows of x and dX
 };
 
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// One output's list of a stage (16 entries and the class-ends word) from
-// LDS, waited for in the same instruction block.  Written out because the
-// compiler, seeing LDS reads it cannot tell apart from the next stage's
-// direct loads in flight, would put a wait for those loads before them and
-// so undo the overlap of the staging with the sums.
-__device__ __forceinline__ void lds_list(const float *p, const float *pe, f4v &a, f4v &b, f4v &c,
-                                         f4v &d, float &e)
+// One output's list of a stage (its entries and the class-ends word) from
+// LDS, waited for in the same instruction block: NL 16-byte reads of 4
+// entries each (2 when a stage has at most 8 rows, else 4).  Written out
+// because the compiler, seeing LDS reads it cannot tell apart from the next
+// stage's direct loads in flight, would put a wait for those loads before
+// them and so undo the overlap of the staging with the sums.
+template <int NL>
+__device__ __forceinline__ void lds_list(const float *p, const float *pe, f4v (&q)[NL], float &e)
 {
     const uint32_t la = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
     const uint32_t le = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(pe));
-    asm volatile("ds_read_b128 %0, %5\n\t"
-                 "ds_read_b128 %1, %5 offset:16\n\t"
-                 "ds_read_b128 %2, %5 offset:32\n\t"
-                 "ds_read_b128 %3, %5 offset:48\n\t"
-                 "ds_read_b32 %4, %6\n\t"
-                 "s_waitcnt lgkmcnt(0)"
-                 : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "=&v"(e)
-                 : "v"(la), "v"(le)
-                 : "memory");
+    if constexpr (NL == 2) {
+        asm volatile("ds_read_b128 %0, %3\n\t"
+                     "ds_read_b128 %1, %3 offset:16\n\t"
+                     "ds_read_b32 %2, %4\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(q[0]), "=&v"(q[1]), "=&v"(e)
+                     : "v"(la), "v"(le)
+                     : "memory");
+    } else {
+        static_assert(NL == 4, "lists are read as 2 or 4 granules");
+        asm volatile("ds_read_b128 %0, %5\n\t"
+                     "ds_read_b128 %1, %5 offset:16\n\t"
+                     "ds_read_b128 %2, %5 offset:32\n\t"
+                     "ds_read_b128 %3, %5 offset:48\n\t"
+                     "ds_read_b32 %4, %6\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(q[0]), "=&v"(q[1]), "=&v"(q[2]), "=&v"(q[3]), "=&v"(e)
+                     : "v"(la), "v"(le)
+                     : "memory");
+    }
 }
 
 // Lane l receives lane l + 1's v (lane 63 receives 0); the compiler folds
@@ -1075,8 +1097,8 @@ __device__ __forceinline__ void add_window(float *acc, const f4v g)
 // per step when kFG is 2, one when it is 4.
 constexpr int kFG = dd::kF32Words / 4;          // granules per lane and output
 
-template <int R>
-__device__ __forceinline__ void add_class(float *acc, const float *A, const int (&ent)[16], int &i,
+template <int R, int NE>
+__device__ __forceinline__ void add_class(float *acc, const float *A, const int (&ent)[NE], int &i,
                                           int end, int lane)
 {
     if constexpr (kFG <= 2) {
@@ -1109,7 +1131,9 @@ __device__ __forceinline__ void add_class(float *acc, const float *A, const int 
     }
 }
 
-template <int MODE>
+// NL: 16-byte granules per output list (2 when every problem's stage has at
+// most 8 rows, else 4).
+template <int MODE, int NL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
 {
@@ -1164,18 +1188,20 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
             // this output's list from LDS: its entries, then the class ends
             // in the list's last word
             const float *Lp = T + (wave * kFP + d) * TS;
-            f4v q0, q1, q2, q3;
+            f4v qs[NL];
             float ef;
-            lds_list(Lp, Lp + (TS - 1), q0, q1, q2, q3, ef);
+            lds_list<NL>(Lp, Lp + (TS - 1), qs, ef);
             const uint32_t ends = uint32_t(__builtin_amdgcn_readfirstlane(__float_as_int(ef)));
-            const f4v qs[4] = {q0, q1, q2, q3};
+            // 16 slots whatever NL: the compiler indexes an array this size
+            // by relative register moves (a shorter one became chains of
+            // selects per access)
             int ent[16];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                ent[4 * k] = __float_as_int(qs[k].x);
-                ent[4 * k + 1] = __float_as_int(qs[k].y);
-                ent[4 * k + 2] = __float_as_int(qs[k].z);
-                ent[4 * k + 3] = __float_as_int(qs[k].w);
+                ent[4 * k] = k < NL ? __float_as_int(qs[k].x) : 0;
+                ent[4 * k + 1] = k < NL ? __float_as_int(qs[k].y) : 0;
+                ent[4 * k + 2] = k < NL ? __float_as_int(qs[k].z) : 0;
+                ent[4 * k + 3] = k < NL ? __float_as_int(qs[k].w) : 0;
             }
             int i = 0;
             add_class<0>(acc[d], A, ent, i, int(ends & 0xFF), lane);
@@ -1193,7 +1219,38 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int64_t nt = R.nt;
     const int t_lo = int(min<int64_t>(max<int64_t>(-t0, 0), kFSpan));   // tg >= 0
     const int t_end = int(min<int64_t>(max<int64_t>(nt - t0, -64), kFSpan + 64)); // tg < nt
-    if constexpr (MODE == kWrite) {
+    if constexpr (MODE == kAdjFinal) {
+#pragma unroll
+        for (int d = 0; d < kFP; ++d) {
+            const int c = aw0 + d;
+            if (c >= R.nouts)
+                break;
+            const float wc = bx.w ? bx.w[c] : 1.0f;
+            float *dx = bx.dX ? bx.dX + int64_t(c) * bx.x_pitch + t0 : nullptr;
+            const float *xs = bx.x ? bx.x + int64_t(c) * bx.x_pitch + t0 : nullptr;
+            float part = 0.0f;
+            if (lane_ok) {
+#pragma unroll
+                for (int k = 0; k < kFW; ++k) {
+                    const int t = tb + ks(k);
+                    if (t >= t_lo && t < t_end) {
+                        if (dx)
+                            dx[t] = wc * acc[d][k];
+                        if (xs)
+                            part += xs[t] * acc[d][k];
+                    }
+                }
+            }
+            if (xs) {
+                // fixed-order butterfly over the wavefront's lanes
+#pragma unroll
+                for (int h = kWave / 2; h > 0; h >>= 1)
+                    part += __shfl_xor(part, h);
+                if (lane == 0)
+                    bx.partial[int64_t(c) * bx.ntime_tiles + tt] = part;
+            }
+        }
+    } else if constexpr (MODE == kWrite) {
         if (lane_ok) {
 #pragma unroll
             for (int d = 0; d < kFP; ++d) {
@@ -2078,14 +2135,25 @@ dd_status launch_sum_mode(SumBatch &a, int64_t blocks, size_t lds, const BoxArgs
 {
     a.nblocks = blocks;
     a.per_xcd = (blocks + kXcds - 1) / kXcds;
+    int32_t max_stage = 0;
+    for (int i = 0; i < a.nprob; ++i)
+        max_stage = std::max(max_stage, a.p[i].stage_rows);
+    const bool short_lists = max_stage <= 8;
+    const void *fn = short_lists ? reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2>)
+                                 : reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4>);
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_shiftsum_f32<MODE>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dd::kMaxLdsBytes));
+        for (const void *f : {reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2>),
+                              reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4>)})
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      int(dd::kMaxLdsBytes));
     });
-    hipLaunchKernelGGL(k_shiftsum_f32<MODE>, dim3(unsigned(a.per_xcd * kXcds)), dim3(kBlock), lds,
-                       stream, a, bx);
+    SumBatch a_arg = a;
+    BoxArgs bx_arg = bx;
+    void *args[] = {&a_arg, &bx_arg};
+    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(a.per_xcd * kXcds)), dim3(kBlock), args, lds, stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "k_shiftsum_f32");
     return launch_check("k_shiftsum_f32");
 }
 
@@ -2130,6 +2198,26 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
             return st;
         a.p[i] = sum_args(ri.adj, t, gpad, ri.gpitch,
                           reinterpret_cast<float *>(d_ws + ri.G_offset), ri.Gpitch);
+    }
+    if (p.adj_fused) {
+        // one range at full resolution: dX and the weight-gradient partials
+        // come from the adjoint kernel's epilogue
+        float *partial = reinterpret_cast<float *>(d_ws + p.dw_offset);
+        BoxArgs fin;
+        std::memset(&fin, 0, sizeof(fin));
+        fin.t_stride = kFTileT;
+        fin.partial = partial;
+        fin.ntime_tiles = p.dw_tiles;
+        fin.x = d_dw ? d_x : nullptr;
+        fin.w = d_w;
+        fin.dX = d_dx;
+        fin.x_pitch = p.nsamp;
+        dd_status st = launch_sum_mode<kAdjFinal>(a, p.adj_blocks, p.adj_lds_bytes, fin, stream);
+        if (st != DD_OK || !d_dw)
+            return st;
+        hipLaunchKernelGGL(k_reduce_rows, dim3(unsigned(p.nchans)), dim3(256), 0, stream, partial,
+                           p.dw_tiles, d_dw);
+        return launch_check("k_reduce_rows");
     }
     dd_status st = launch_sum(a, p.adj_blocks, p.adj_lds_bytes, stream);
     if (st != DD_OK)

@@ -260,8 +260,11 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     }
     p->dw_chunk_len = 4096;
     p->dw_chunks = int32_t((nsamp + p->dw_chunk_len - 1) / p->dw_chunk_len);
+    p->adj_fused = p->ranges.size() == 1 && p->ranges[0].ds == 1;
+    p->dw_tiles = p->adj_fused ? int32_t(p->ranges[0].adj.ntime_tiles) : 0;
     p->dw_offset = ws;
-    ws = align_up(ws + size_t(nchans) * size_t(p->dw_chunks) * sizeof(float), kWsAlign);
+    ws = align_up(ws + size_t(nchans) * size_t(std::max(p->dw_chunks, p->dw_tiles)) * sizeof(float),
+                  kWsAlign);
     // boxcar loss buffers
     p->gout_offset = ws;
     ws = align_up(ws + size_t(p->out_elems) * sizeof(float), kWsAlign);

@@ -203,7 +203,12 @@ struct Plan {
     size_t adj_lds_bytes = 0;
     int32_t dw_chunks = 0;                 // time chunks of the weight-gradient reduction
     int64_t dw_chunk_len = 0;
-    size_t dw_offset = 0;                  // workspace bytes: partials [nchans][dw_chunks]
+    size_t dw_offset = 0;                  // workspace bytes: partials [nchans][dw_chunks], or
+                                           // [nchans][dw_tiles] when the adjoint is fused
+    // One range at full resolution: the adjoint kernel forms dX and the
+    // weight-gradient partials itself, one per (channel, time tile).
+    bool adj_fused = false;
+    int32_t dw_tiles = 0;
     // boxcar loss (float32 plans): dL/dout of one beam, the loss partials of
     // one launch, and one beam's weight gradient.
     size_t gout_offset = 0;                // [out_elems] floats

@@ -116,6 +116,30 @@ def test_adjoint_random_shapes_vs_oracle():
         assert len(plan_o) == len(ranges)
 
 
+@pytest.mark.parametrize("nsamp,nch", [(5000, 70), (4001, 33), (1100, 1)])
+def test_adjoint_one_range_full_resolution_vs_oracle(nsamp, nch):
+    """Plans with one range at full resolution form dX and the weight
+    gradient in the adjoint kernel's epilogue (no G buffer, no finalising
+    pass): several time tiles with a ragged last one, output tiles of 32
+    channels with a partial last one, and a one-channel plan."""
+    x, freqs, tsamp, _, w = case(80 + nch, nch=nch, nsamp=nsamp)
+    ranges = [(0.0, 45.0, 1.0, 1)]
+    say("f32 fused adjoint", nsamp, nch)
+    plan = gpu_plan(freqs, tsamp, nsamp, ranges)
+    rng = np.random.default_rng(81)
+    g = rng.standard_normal(plan.out_elems).astype(np.float32)
+    xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    dx, dw = dd.adjoint(torch.from_numpy(g).cuda(), plan, x=xt, weights=wt)
+    dx_only, none = dd.adjoint(torch.from_numpy(g).cuda(), plan, weights=wt, grad_w=False)
+    torch.cuda.synchronize()
+    assert none is None and torch.equal(dx, dx_only)
+    wX, ww = cref.adjoint_f32(x, freqs, tsamp, ranges, g.astype(np.float64), w)
+    tX, tw = cref.adjoint_f32(np.abs(x), freqs, tsamp, ranges, np.abs(g).astype(np.float64),
+                              np.abs(w))
+    check_close(dx.cpu().numpy().astype(np.float64), wX, tX, "dX")
+    check_close(dw.cpu().numpy().astype(np.float64), ww, tw, "dw")
+
+
 def test_adjoint_identity():
     """<A x, y> == <x, A^T y>: the GPU forward and the GPU adjoint are
     transposes (sums formed in FP64 on the host from the float32 results)."""
