@@ -347,31 +347,40 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
                              float *d_grad_w, void *d_ws, size_t ws_bytes, void *stream);
 
 /*
- * Batches: many integer plans (beams of uneven channel counts, lengths and
- * DM plans) summed by persistent launches -- ONE per kernel the plans use
- * (variant family and DM tile; usually one) -- that take their work items
- * (beam, range, time tile, DM tile), most expensive first, from queues in
- * the workspace.  The launch sequence allocates nothing and contains no
- * memset, so it can be captured in a HIP graph (call dd_batch_prepare
- * first).  Results equal dd_forward of each plan bit for bit.
+ * Batches (paper, "Design of the API": a strategy decides how the input is
+ * split and processed on the GPU; here many beams share one).  Integer
+ * plans (beams of uneven channel counts, lengths and DM plans) are summed
+ * by persistent launches -- ONE per kernel the plans use (variant family,
+ * DM tile and time tile; usually one) -- that take their work items (beam,
+ * range, time tile, DM tile), most expensive first, from queues in the
+ * workspace.  Float32 plans are summed by ONE launch of the float32
+ * shift-and-sum over every (beam, range) problem, whose workgroups run the
+ * beams with most channels first (each beam's weighted levels are formed
+ * beam by beam before it).  The launch sequence allocates nothing and
+ * contains no memset, so it can be captured in a HIP graph (call
+ * dd_batch_prepare first).  Results equal dd_forward of each plan bit for
+ * bit (the float32 sums run in the same order).
  *
- * dd_batch_create   plans: [nbeams] DD_U8 plans (borrowed: they must
- *                   outlive the batch).  Plans that run the same kernel
- *                   form one group; a group's work items are dealt to one
- *                   queue per XCD in contiguous slices of equal cost (an
- *                   item weighs its beam's channel count).  Host-only.
- *                   Errors: DD_ERR_NULL, DD_ERR_INVALID (nbeams < 1),
- *                   DD_ERR_DTYPE, DD_ERR_NOMEM.
+ * dd_batch_create   plans: [nbeams] plans of one dtype (borrowed: they
+ *                   must outlive the batch).  Integer plans that run the
+ *                   same kernel form one group; a group's work items are
+ *                   dealt to one queue per XCD in contiguous slices of equal
+ *                   cost (an item weighs its beam's channel count); float32
+ *                   plans form one group.  Host-only.  Errors: DD_ERR_NULL,
+ *                   DD_ERR_INVALID (nbeams < 1), DD_ERR_DTYPE (mixed
+ *                   dtypes), DD_ERR_NOMEM.
  * dd_batch_info     in_bytes: size of the batch input buffer (each beam's
- *                   [nchans][nsamp] uint8 block at its in_offset);
- *                   out_elems: int32 elements of the batch output (each
- *                   beam's dd_forward layout at its out_offset); ws_bytes:
- *                   workspace; work_items: items of all its launches.
- *                   Any pointer may be NULL.
+ *                   [nchans][nsamp] uint8 or float32 block at its
+ *                   in_offset); out_elems: int32 (DD_U8) or float32
+ *                   (DD_F32) elements of the batch output (each beam's
+ *                   dd_forward layout at its out_offset); ws_bytes:
+ *                   workspace; work_items: items (float32: workgroups) of
+ *                   all its launches.  Any pointer may be NULL.
  * dd_batch_beam     byte offset of beam b's input and element offset of its
  *                   output (both 256-byte aligned).
  * dd_batch_groups   the number of kernel groups (one persistent launch each).
- * dd_batch_group    group g's kernel (variant 1, 2 or 3 and DM tile), its
+ * dd_batch_group    group g's kernel (variant 1, 2 or 3 and DM tile; for
+ *                   the float32 group variant 0 and its 32-output tile), its
  *                   work items, and the bounds of its per-XCD queues:
  *                   queue x holds items [queue_bounds[x], queue_bounds[x+1])
  *                   of the group (queue_bounds: 9 int64, or NULL).  Any
@@ -379,10 +388,16 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
  *                   range.
  * dd_batch_prepare  upload the batch's and its plans' device tables to the
  *                   current device.
- * dd_batch_forward  d_in: batch input (256-byte aligned); d_out: int32,
- *                   out_capacity elements; d_ws: workspace (256-byte
+ * dd_batch_forward  d_in: batch input (256-byte aligned); d_out: int32 or
+ *                   float32, out_capacity elements; d_ws: workspace (256-byte
  *                   aligned, ws_bytes >= dd_batch_info's).  Calls that
- *                   overlap in time need distinct workspaces.
+ *                   overlap in time need distinct workspaces.  Float32
+ *                   batches run with unit channel weights.
+ * dd_batch_forward_weighted  as dd_batch_forward, for DD_F32 batches, with
+ *                   d_weights: each beam's [nchans] float32 channel weights
+ *                   in beam order, concatenated (sum of nchans floats),
+ *                   or NULL for unit weights.  DD_ERR_DTYPE for an integer
+ *                   batch with weights.
  */
 typedef struct dd_batch dd_batch;
 
@@ -398,6 +413,9 @@ dd_status dd_batch_beam(const dd_batch *batch, int32_t beam, int64_t *in_offset,
 dd_status dd_batch_prepare(dd_batch *batch);
 dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
                            int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream);
+dd_status dd_batch_forward_weighted(const dd_batch *batch, const void *d_in, const float *d_weights,
+                                    void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
+                                    void *stream);
 
 /*
  * Streaming (paper, "Pipeline": the pipeline walks the input in chunks and

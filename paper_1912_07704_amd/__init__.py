@@ -135,12 +135,16 @@ class Plan:
 
 
 class Batch:
-    """Many u8 plans summed by persistent launches, one per kernel the plans
-    use (dd_batch_*).  The plans must stay alive as long as the batch."""
+    """Many plans of one dtype dedispersed together (dd_batch_*): u8 plans
+    by persistent launches, one per kernel the plans use; f32 plans by one
+    shift-and-sum launch over all beams.  The plans must stay alive as long
+    as the batch."""
 
     def __init__(self, plans):
         L = lib()
         self.plans = list(plans)
+        dts = {p.dtype for p in self.plans}
+        self.dtype = self.plans[0].dtype if len(dts) == 1 else None
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
         self._h = ctypes.c_void_p()
         check(L.dd_batch_create(arr, len(self.plans), ctypes.byref(self._h)), "dd_batch_create")
@@ -176,16 +180,31 @@ class Batch:
         check(lib().dd_batch_prepare(self.handle), "dd_batch_prepare")
 
     def pack(self, inputs, device=None):
-        """One batch input buffer holding every beam's [nchans, nsamp] uint8
-        block at its offset (inputs: numpy arrays or tensors)."""
+        """One batch input buffer (bytes) holding every beam's [nchans, nsamp]
+        block (uint8 or float32, the plans' dtype) at its byte offset
+        (inputs: numpy arrays or tensors)."""
         import torch
         buf = torch.zeros(max(1, self.in_bytes), dtype=torch.uint8, device=device or "cuda")
+        want = torch.uint8 if self.dtype == "u8" else torch.float32
         for p, off, x in zip(self.plans, self.in_offsets, inputs):
             t = torch.as_tensor(x).reshape(-1)
-            if t.numel() != p.nchans * p.nsamp or t.dtype != torch.uint8:
+            if t.numel() != p.nchans * p.nsamp or t.dtype != want:
                 raise ValueError("beam input has the wrong shape or dtype")
-            buf[off: off + t.numel()].copy_(t)
+            nb = t.numel() * t.element_size()
+            buf[off: off + nb].copy_(t.to(buf.device).view(torch.uint8))
         return buf
+
+    def pack_weights(self, weights, device=None):
+        """The batch weight buffer of an f32 batch: each beam's [nchans]
+        weights in beam order, concatenated."""
+        import torch
+        parts = []
+        for p, w in zip(self.plans, weights):
+            t = torch.as_tensor(w, dtype=torch.float32).reshape(-1)
+            if t.numel() != p.nchans:
+                raise ValueError("beam weights have the wrong length")
+            parts.append(t.to(device or "cuda"))
+        return torch.cat(parts).contiguous()
 
     def split(self, out):
         """Per-beam flat outputs (views)."""
@@ -203,17 +222,30 @@ class Batch:
             pass
 
 
-def dedisperse_batch(x, batch: Batch, out=None, ws=None, stream=None):
-    """Batched forward of every beam (dd_batch_forward); x is the packed
-    batch input.  Returns the flat int32 batch output."""
+def dedisperse_batch(x, batch: Batch, out=None, ws=None, stream=None, weights=None):
+    """Batched forward of every beam (dd_batch_forward, or
+    dd_batch_forward_weighted with `weights`, the packed f32 weight buffer);
+    x is the packed batch input (bytes).  Returns the flat batch output
+    (int32 for u8 plans, float32 for f32 plans)."""
     import torch
     if x.dtype != torch.uint8 or not x.is_cuda or not x.is_contiguous() or \
             x.numel() < batch.in_bytes:
-        raise ValueError("x must be the packed uint8 batch input on the device")
+        raise ValueError("x must be the packed batch input (bytes) on the device")
+    odt = torch.int32 if batch.dtype == "u8" else torch.float32
     if out is None:
-        out = torch.empty(batch.out_elems, dtype=torch.int32, device=x.device)
+        out = torch.empty(batch.out_elems, dtype=odt, device=x.device)
+    if out.dtype != odt or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {odt} tensor")
     if ws is None:
         ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device=x.device)
+    if weights is not None:
+        if (weights.dtype != torch.float32 or not weights.is_contiguous()
+                or weights.numel() != sum(p.nchans for p in batch.plans)):
+            raise ValueError("weights must be the packed float32 weights of every beam")
+        check(lib().dd_batch_forward_weighted(batch.handle, _ptr(x), _ptr(weights), _ptr(out),
+                                              out.numel(), _ptr(ws), ws.numel(),
+                                              _stream_ptr(stream)), "dd_batch_forward_weighted")
+        return out
     check(lib().dd_batch_forward(batch.handle, _ptr(x), _ptr(out), out.numel(), _ptr(ws),
                                  ws.numel(), _stream_ptr(stream)), "dd_batch_forward")
     return out

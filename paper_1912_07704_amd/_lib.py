@@ -37,6 +37,7 @@ SIGNATURES = {
     "dd_batch_group": (ctypes.c_int, [P, I32, P, P, P, P]),
     "dd_batch_prepare": (ctypes.c_int, [P]),
     "dd_batch_forward": (ctypes.c_int, [P, P, P, I64, P, SZ, P]),
+    "dd_batch_forward_weighted": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),
     "dd_stream_create": (ctypes.c_int, [P, I32, P]),
     "dd_stream_destroy": (None, [P]),
     "dd_stream_info": (ctypes.c_int, [P, P, P]),

@@ -1,6 +1,7 @@
-// Host core of the batched integer forward: buffer layout of the beams, the
-// kernel groups, and the order of each group's work items (most expensive
-// first, so the queues drain evenly).  Plain C++, no HIP.
+// Host core of the batched forward: buffer layout of the beams, the kernel
+// groups, and the order of each group's work items (most expensive first,
+// so the queues, or the float32 launch's workgroups, drain evenly).  Plain
+// C++, no HIP.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -24,33 +25,44 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
     }
     try {
         b->plans.assign(plans, plans + nbeams);
+        b->dtype = plans[0] ? plans[0]->dtype : DD_U8;
+        b->w_off.assign(size_t(nbeams), 0);
         b->in_off.assign(size_t(nbeams), 0);
         b->out_off.assign(size_t(nbeams), 0);
         b->ws_off.assign(size_t(nbeams), 0);
         b->groups.clear();
         std::vector<int32_t> group_of(size_t(nbeams), 0);
         size_t in = 0, out = 0, ws = kBatchCounterBytes;
+        int64_t wn = 0;
         for (int32_t i = 0; i < nbeams; ++i) {
             const Plan *p = plans[i];
             if (!p) {
                 *err = "plan " + std::to_string(i) + " is NULL";
                 return DD_ERR_NULL;
             }
-            if (p->dtype != DD_U8) {
-                *err = "batches hold DD_U8 plans only";
+            if (p->dtype != b->dtype) {
+                *err = "the plans of a batch share one dtype (plan " + std::to_string(i) +
+                       " differs from plan 0)";
                 return DD_ERR_DTYPE;
             }
+            const bool f32 = p->dtype == DD_F32;
             b->in_off[i] = int64_t(in);
-            in = align_up(in + size_t(p->nchans) * size_t(p->nsamp), 256);
+            in = align_up(in + size_t(p->nchans) * size_t(p->nsamp) * (f32 ? sizeof(float) : 1), 256);
             b->out_off[i] = int64_t(out);
             out = align_up(out + size_t(p->out_elems), 64);
+            b->w_off[i] = wn;
+            wn += p->nchans;
+            // a beam's part of the workspace: what its forward uses
             b->ws_off[i] = ws;
-            ws = align_up(ws + p->ws_bytes, 256);
-            // plans that run the same kernel share a group (one launch)
+            ws = align_up(ws + p->fwd_ws_bytes, 256);
+            // plans that run the same kernel share a group (one launch); all
+            // float32 plans run the generic shift-and-sum
             int32_t g = 0;
             while (g < int32_t(b->groups.size()) &&
-                   !(b->groups[g].subband == p->subband && b->groups[g].dedup == p->dedup &&
-                     b->groups[g].dm_tile == p->dm_tile && b->groups[g].time_tile == p->time_tile))
+                   !(f32 ? b->groups[g].f32
+                         : (!b->groups[g].f32 && b->groups[g].subband == p->subband &&
+                            b->groups[g].dedup == p->dedup && b->groups[g].dm_tile == p->dm_tile &&
+                            b->groups[g].time_tile == p->time_tile)))
                 ++g;
             if (g == int32_t(b->groups.size())) {
                 if (g == kBatchMaxGroups) {
@@ -59,6 +71,7 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                     return DD_ERR_INVALID;
                 }
                 BatchGroup G;
+                G.f32 = f32;
                 G.subband = p->subband;
                 G.dedup = p->dedup;
                 G.dm_tile = p->dm_tile;
@@ -71,6 +84,7 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
         }
         b->in_bytes = int64_t(in);
         b->out_elems = int64_t(out);
+        b->w_elems = wn;
         b->ws_bytes = ws;
         // Work items: every (beam, range) contributes time tiles x DM tiles
         // items of equal shape whose cost grows with the beam's channels.
@@ -86,7 +100,11 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                     BatchDescHost d;
                     d.beam = i;
                     d.range = r;
-                    d.nitems = plans[i]->ranges[r].ntime_tiles * plans[i]->ranges[r].ndm_tiles;
+                    const RangeInfo &ri = plans[i]->ranges[r];
+                    // float32: the forward problem's workgroups (time tiles x
+                    // output tiles); integer: time tiles x DM tiles
+                    d.nitems = G.f32 ? ri.fwd.ntime_tiles * ri.fwd.nout_tiles
+                                     : ri.ntime_tiles * ri.ndm_tiles;
                     b->descs.push_back(d);
                 }
             }

@@ -265,9 +265,9 @@ dd_status dd_batch_group(const dd_batch *batch, int32_t g, int32_t *variant, int
     }
     const dd::BatchGroup &G = batch->b.groups[size_t(g)];
     if (variant)
-        *variant = G.subband ? 3 : (G.dedup ? 2 : 1);
+        *variant = G.f32 ? 0 : G.subband ? 3 : (G.dedup ? 2 : 1);
     if (dm_tile)
-        *dm_tile = G.dm_tile;
+        *dm_tile = G.f32 ? dd::kF32OutTile : G.dm_tile;
     if (work_items)
         *work_items = G.nitems;
     if (queue_bounds)

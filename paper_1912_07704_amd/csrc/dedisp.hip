@@ -939,9 +939,16 @@ struct SumArgs {
 
 struct SumBatch {
     SumArgs p[DD_MAX_RANGES];
+    // a batch of beams: the problems' descriptors in device memory instead
+    // of p (ordered by block_start), their src and dst holding byte offsets
+    // from src_base and dst_base
+    const SumArgs *pd;
+    uintptr_t src_base;
+    uintptr_t dst_base;
     int64_t nblocks;
     int64_t per_xcd;
     int32_t nprob;
+    int32_t max_stage;        // largest stage_rows over the problems
 };
 
 
@@ -1132,8 +1139,9 @@ __device__ __forceinline__ void add_class(float *acc, const float *A, const int 
 }
 
 // NL: 16-byte granules per output list (2 when every problem's stage has at
-// most 8 rows, else 4).
-template <int MODE, int NL>
+// most 8 rows, else 4).  PD: the problems come from device descriptors (a
+// batch of beams), found by binary search on block_start.
+template <int MODE, int NL, bool PD>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
 {
@@ -1143,10 +1151,23 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     if (L >= a.nblocks)
         return;
     int r = 0;
-    for (int i = 1; i < a.nprob; ++i)
-        if (L >= a.p[i].block_start)
-            r = i;
-    const SumArgs &R = a.p[r];
+    if constexpr (PD) {
+        int hi = a.nprob - 1;
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (L >= a.pd[mid].block_start)
+                r = mid;
+            else
+                hi = mid - 1;
+        }
+    } else {
+        for (int i = 1; i < a.nprob; ++i)
+            if (L >= a.p[i].block_start)
+                r = i;
+    }
+    const SumArgs &R = PD ? a.pd[r] : a.p[r];
+    const float *src_rows = reinterpret_cast<const float *>(a.src_base + reinterpret_cast<uintptr_t>(R.src));
+    float *dst_rows = reinterpret_cast<float *>(a.dst_base + reinterpret_cast<uintptr_t>(R.dst));
     const int64_t lb = L - R.block_start;
     const int64_t tt = lb / R.nout_tiles;
     const int tile = int(lb - tt * R.nout_tiles);
@@ -1160,7 +1181,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int CW = C * Wr;
     const int nrows = R.nrows;
     const int nst = R.nstages;
-    const StageSrc S = {R.src, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_stride};
+    const StageSrc S = {src_rows, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_stride};
     const int TS = R.tab_stride;
     const int CWt = CW + kFTileA * TS + 16;     // floats of one stage buffer: rows, then lists
 
@@ -1257,7 +1278,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                 const int ao = aw0 + d;
                 if (ao >= R.nouts)
                     break;
-                float *row = R.dst + int64_t(ao) * R.dst_pitch + t0;
+                float *row = dst_rows + int64_t(ao) * R.dst_pitch + t0;
 #pragma unroll
                 for (int k = 0; k < kFW; ++k) {
                     const int t = tb + ks(k);
@@ -1340,7 +1361,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
             }
             if constexpr (MODE == kBoxGrad) {
                 if (dm_ok) {
-                    float *row = R.dst + int64_t(ao) * R.dst_pitch + t0;
+                    float *row = dst_rows + int64_t(ao) * R.dst_pitch + t0;
 #pragma unroll
                     for (int k = 0; k < kFW; ++k) {
                         const int t = tb + ks(k);
@@ -2129,22 +2150,26 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     return R;
 }
 
-template <int MODE>
+template <int MODE, bool PD = false>
 dd_status launch_sum_mode(SumBatch &a, int64_t blocks, size_t lds, const BoxArgs &bx,
                           hipStream_t stream)
 {
     a.nblocks = blocks;
     a.per_xcd = (blocks + kXcds - 1) / kXcds;
-    int32_t max_stage = 0;
-    for (int i = 0; i < a.nprob; ++i)
-        max_stage = std::max(max_stage, a.p[i].stage_rows);
-    const bool short_lists = max_stage <= 8;
-    const void *fn = short_lists ? reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2>)
-                                 : reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4>);
+    if (!PD) {
+        a.pd = nullptr;
+        a.src_base = a.dst_base = 0;
+        a.max_stage = 0;
+        for (int i = 0; i < a.nprob; ++i)
+            a.max_stage = std::max(a.max_stage, a.p[i].stage_rows);
+    }
+    const bool short_lists = a.max_stage <= 8;
+    const void *fn = short_lists ? reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2, PD>)
+                                 : reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4, PD>);
     static std::once_flag attr_once;
     std::call_once(attr_once, [] {
-        for (const void *f : {reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2>),
-                              reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4>)})
+        for (const void *f : {reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 2, PD>),
+                              reinterpret_cast<const void *>(k_shiftsum_f32<MODE, 4, PD>)})
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       int(dd::kMaxLdsBytes));
     });
@@ -2501,7 +2526,7 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
     for (size_t g = 0; g < b.groups.size(); ++g) {
         const dd::BatchGroup &G = b.groups[g];
         const size_t n = G.desc_end - G.desc_begin;
-        off_desc[g] = grow(n * (G.subband ? sizeof(SbBatchDesc) : sizeof(BatchDesc)));
+        off_desc[g] = grow(n * (G.f32 ? sizeof(SumArgs) : G.subband ? sizeof(SbBatchDesc) : sizeof(BatchDesc)));
         off_start[g] = grow(n * sizeof(int64_t));
         for (size_t k = 0; k < n; ++k) {
             const dd::BatchDescHost &d = b.descs[G.desc_begin + k];
@@ -2513,6 +2538,17 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
             const RangeInfo &ri = p.ranges[d.range];
             const dd::BinLevel &lv = p.levels[ri.level];
             reinterpret_cast<int64_t *>(img.data() + off_start[g])[k] = d.item_start;
+            if (G.f32) {
+                // src and dst as byte offsets from the call's workspace and
+                // output (added in the kernel)
+                const size_t src_off = b.ws_off[d.beam] + lv.ws_offset + size_t(lv.lead) * sizeof(float);
+                const size_t dst_off = size_t(b.out_off[d.beam] + ri.out_offset) * sizeof(float);
+                SumArgs R = sum_args(ri.fwd, *t, reinterpret_cast<const float *>(src_off), lv.pitch,
+                                     reinterpret_cast<float *>(dst_off), ri.nout);
+                R.block_start = d.item_start;
+                reinterpret_cast<SumArgs *>(img.data() + off_desc[g])[k] = R;
+                continue;
+            }
             if (G.subband) {
                 SbBatchDesc &S = reinterpret_cast<SbBatchDesc *>(img.data() + off_desc[g])[k];
                 fill_sb_range(p, *t, ri, S.R);
@@ -2541,7 +2577,7 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
     // binning jobs: every beam's power-of-two levels, one launch
     std::vector<BinJob> jobs;
     int64_t bin_blocks = 0;
-    for (size_t i = 0; i < b.plans.size(); ++i) {
+    for (size_t i = 0; i < b.plans.size() && b.dtype == DD_U8; ++i) {
         BinJob J;
         if (!pow2_job(*b.plans[i], b.in_off[i], b.ws_off[i], J))
             continue;
@@ -2606,6 +2642,34 @@ const void *subband_batch_kernel(int dm_tile, int time_tile)
         return t2 ? reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 2>)
                   : reinterpret_cast<const void *>(k_dedisp_u8_sb_batch<8, 8, 4>);
     }
+}
+
+// Float32 batch: every beam's weighted levels (k_level_f32, beam by beam),
+// then one shift-and-sum launch over all (beam, range) problems, the most
+// expensive beams' workgroups first.
+dd_status batch_forward_f32(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
+                            const float *d_w, float *d_out, char *d_ws, hipStream_t stream)
+{
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+        dd_status st = bin_f32(*b.plans[i], reinterpret_cast<const float *>(d_in + b.in_off[i]),
+                               d_w ? d_w + b.w_off[i] : nullptr, d_ws + b.ws_off[i], stream);
+        if (st != DD_OK)
+            return st;
+    }
+    const dd::BatchGroup &G = b.groups[0];
+    SumBatch a;
+    std::memset(&a, 0, sizeof(a));
+    a.pd = static_cast<const SumArgs *>(bd.descs[0]);
+    a.nprob = int32_t(G.desc_end - G.desc_begin);
+    a.src_base = reinterpret_cast<uintptr_t>(d_ws);
+    a.dst_base = reinterpret_cast<uintptr_t>(d_out);
+    for (const dd::Plan *p : b.plans)
+        for (const RangeInfo &ri : p->ranges)
+            a.max_stage = std::max(a.max_stage, ri.fwd.stage_rows);
+    BoxArgs bx;
+    std::memset(&bx, 0, sizeof(bx));
+    bx.t_stride = kFTileT;
+    return launch_sum_mode<kWrite, true>(a, G.nitems, G.lds_bytes, bx, stream);
 }
 
 dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
@@ -2834,8 +2898,11 @@ dd_status dd_batch_prepare(dd_batch *batch)
     return batch_device(batch->b, &bd);
 }
 
-dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
-                           int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream)
+namespace {
+
+dd_status batch_forward_any(const dd_batch *batch, const void *d_in, const float *d_weights,
+                            void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
+                            void *stream)
 {
     dd::clear_error();
     if (!batch || !d_in || !d_out || !d_ws) {
@@ -2843,6 +2910,10 @@ dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
         return DD_ERR_NULL;
     }
     const dd::Batch &b = batch->b;
+    if (d_weights && b.dtype != DD_F32) {
+        dd::set_error("per-channel weights apply to DD_F32 batches only");
+        return DD_ERR_DTYPE;
+    }
     if (out_capacity < b.out_elems) {
         dd::set_error("out_capacity " + std::to_string(out_capacity) + " < out_elems " +
                       std::to_string(b.out_elems));
@@ -2861,8 +2932,27 @@ dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
     dd_status st = batch_device(b, &bd);
     if (st != DD_OK)
         return st;
+    if (b.dtype == DD_F32)
+        return batch_forward_f32(b, *bd, static_cast<const char *>(d_in), d_weights,
+                                 static_cast<float *>(d_out), static_cast<char *>(d_ws),
+                                 static_cast<hipStream_t>(stream));
     return batch_forward(b, *bd, static_cast<const char *>(d_in), static_cast<int32_t *>(d_out),
                          static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+
+dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
+                           int64_t out_capacity, void *d_ws, size_t ws_bytes, void *stream)
+{
+    return batch_forward_any(batch, d_in, nullptr, d_out, out_capacity, d_ws, ws_bytes, stream);
+}
+
+dd_status dd_batch_forward_weighted(const dd_batch *batch, const void *d_in, const float *d_weights,
+                                    void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
+                                    void *stream)
+{
+    return batch_forward_any(batch, d_in, d_weights, d_out, out_capacity, d_ws, ws_bytes, stream);
 }
 
 dd_status dd_plan_prepare(dd_plan *plan)

@@ -277,6 +277,9 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     p->dwb_offset = ws;
     ws = align_up(ws + size_t(nchans) * sizeof(float), kWsAlign);
     p->ws_bytes = ws;
+    p->fwd_ws_bytes = 0;
+    for (const BinLevel &lv : p->levels)
+        p->fwd_ws_bytes = std::max(p->fwd_ws_bytes, lv.ws_offset + lv.bytes);
     return DD_OK;
 }
 
@@ -322,6 +325,7 @@ void build_levels(Plan *p)
                 ri.level = int32_t(j);
     }
     p->ws_bytes = ws;
+    p->fwd_ws_bytes = ws;
 }
 
 // Delay patterns of one sub-band (channels [c0, c0 + kb)) over the DMs

@@ -189,6 +189,7 @@ struct Plan {
     int64_t out_elems = 0;
     int64_t overlap = 0;
     size_t ws_bytes = 0;
+    size_t fwd_ws_bytes = 0;               // the part of the workspace the forward uses (its levels)
     int64_t blocks = 0;                    // workgroups of one forward launch
     size_t lds_bytes = 0;                  // dynamic LDS of the forward kernel
     bool dedup = true;                     // integer kernel variant (dd_options.variant)
@@ -247,6 +248,7 @@ constexpr int kBatchQueues = 8;                // one work queue per XCD
 constexpr int kBatchMaxGroups = 8;             // kernels per batch
 
 struct BatchGroup {
+    bool f32 = false;                      // float32 plans: the generic shift-and-sum
     bool subband = false;                  // variant 3 (else the direct kernel)
     bool dedup = false;                    // direct kernel: variant 2
     int32_t dm_tile = kDmTile;
@@ -261,12 +263,16 @@ struct BatchGroup {
 };
 
 struct Batch {
+    dd_dtype dtype = DD_U8;                // of every plan
     std::vector<const Plan *> plans;       // not owned
+    std::vector<int64_t> w_off;            // float32: floats into the batch weights (beam b's
+                                           // [nchans] weights)
     std::vector<int64_t> in_off;           // bytes into the batch input
-    std::vector<int64_t> out_off;          // elements into the batch output
+    std::vector<int64_t> out_off;          // elements (int32 or float32) into the batch output
     std::vector<size_t> ws_off;            // bytes into the workspace (beam's own part)
     int64_t in_bytes = 0;
     int64_t out_elems = 0;
+    int64_t w_elems = 0;                   // float32: weights of all beams
     size_t ws_bytes = 0;
     std::vector<BatchDescHost> descs;      // by group, most expensive items first in each
     std::vector<BatchGroup> groups;

@@ -1,6 +1,8 @@
-"""Batched integer forward: persistent launches (one per kernel) over many
-beams of uneven shape (direct kernel, variant 3 or both), bit-exact against
-each beam's own forward and the oracle, and replayable from a HIP graph."""
+"""Batched forward: integer batches by persistent launches (one per kernel)
+over many beams of uneven shape (direct kernel, variant 3 or both),
+bit-exact against each beam's own forward and the oracle; float32 batches by
+one shift-and-sum launch, bit-identical to each beam's own forward and within
+the float32 tolerance of the FP64 oracle; both replayable from a HIP graph."""
 import numpy as np
 import pytest
 
@@ -153,3 +155,93 @@ def test_batched_beams_full_size(strategy):
             t = rng.integers(0, ri.nout, 40)
             got = per[r][torch.from_numpy(d).cuda(), torch.from_numpy(t).cuda()].cpu().numpy()
             assert np.array_equal(got, O.dedisperse_at(x, op, r, d, t))
+
+
+def float_beams(seed, n):
+    """Float32 beams of uneven shape: channel counts, lengths, sampling, and
+    one to three ranges with downsampling, random channel weights."""
+    rng = np.random.default_rng(900 + seed)
+    beams = []
+    for b in range(n):
+        nch = int(rng.choice([7, 33, 64, 130]))
+        nsamp = int(rng.integers(2500, 9000))
+        tsamp = float(rng.choice([64e-6, 128e-6, 2.56e-4]))
+        freqs = synth.band_freqs(1500.0, float(rng.uniform(1200.0, 1450.0)), nch)
+        ranges = [(0.0, float(rng.integers(5, 60)), 1.0, 1)]
+        if b % 2:
+            ranges.append((ranges[0][1], ranges[0][1] + 20.0, 2.0, int(rng.choice([2, 3]))))
+        x = rng.standard_normal((nch, nsamp)).astype(np.float32)
+        w = rng.uniform(0.25, 2.0, nch).astype(np.float32)
+        beams.append((x, freqs, tsamp, ranges, w))
+    return beams
+
+
+def float_close(got, want, terms, what):
+    """Float32 against the FP64 oracle: 1e-5 normwise and elementwise
+    1e-5 * sum of |terms| (the float32 tolerance)."""
+    got = got.astype(np.float64)
+    err = np.abs(got - want)
+    assert err.max() <= 1e-5 * max(np.abs(want).max(), 1e-30), what
+    assert (err <= 1e-5 * terms + 1e-30).all(), what
+
+
+def test_float_batch_matches_single_plans_and_oracle():
+    """One shift-and-sum launch over every (beam, range) of a float32 batch
+    equals each beam's own weighted forward bit for bit (the same sums in
+    the same order) and the FP64 oracle within the float32 tolerance; the
+    unweighted call equals unit weights."""
+    beams = float_beams(0, 6)
+    say("float batch", [(x.shape, len(r)) for (x, _, _, r, _) in beams])
+    plans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in beams]
+    batch = dd.Batch(plans)
+    xin = batch.pack([b[0] for b in beams])
+    wts = batch.pack_weights([b[4] for b in beams])
+    out = dd.dedisperse_batch(xin, batch, weights=wts)
+    unit = dd.dedisperse_batch(xin, batch)
+    ones = dd.dedisperse_batch(xin, batch, weights=torch.ones_like(wts))
+    torch.cuda.synchronize()
+    # per beam: the alignment gaps between beams are never written
+    assert all(torch.equal(u, o) for u, o in zip(batch.split(unit), batch.split(ones)))
+    for (x, f, t, r, w), p, o in zip(beams, plans, batch.split(out)):
+        single = dd.dedisperse(torch.from_numpy(x).cuda(), p, weights=torch.from_numpy(w).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(o, single)
+        want = cref.dedisperse_f32(x, f, t, r, w)
+        terms = cref.dedisperse_f32(np.abs(x), f, t, r, np.abs(w))
+        float_close(o.cpu().numpy(), want, terms, f"beam {x.shape}")
+
+
+def test_float_batch_graph_replay():
+    """The float32 batch's launches replay from a HIP graph, with the
+    workspace scribbled and eager work between replays."""
+    beams = float_beams(1, 4)
+    say("float batch graph replay")
+    plans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in beams]
+    batch = dd.Batch(plans)
+    batch.prepare()
+    xin = batch.pack([b[0] for b in beams])
+    wts = batch.pack_weights([b[4] for b in beams])
+    ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
+    eager = dd.dedisperse_batch(xin, batch, ws=ws, weights=wts).clone()
+    out = torch.zeros(batch.out_elems, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        dd.dedisperse_batch(xin, batch, out=out, ws=ws, weights=wts)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dd.dedisperse_batch(xin, batch, out=out, ws=ws, weights=wts)
+    for i in range(3):
+        out.zero_()
+        ws.fill_(0x7F)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(batch.split(out), batch.split(eager)):
+            assert torch.equal(o, e), f"replay {i}"
+        other = dd.dedisperse(torch.from_numpy(beams[0][0]).cuda(), plans[0],
+                              weights=torch.from_numpy(beams[0][4]).cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(other, batch.split(eager)[0])

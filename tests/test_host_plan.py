@@ -253,6 +253,31 @@ def test_subband_variant_is_integer_only_and_batches_mix_kernels():
         b.close()
 
 
+def test_float_batches_layout_and_dtype_mixing():
+    """A batch holds plans of one dtype.  A float32 batch lays out each
+    beam's float32 input (4 bytes a sample) and output at 256-byte aligned
+    offsets, forms one kernel group (variant 0, 32-output tile) whose work
+    items are the forward workgroups of every beam, and sizes its workspace
+    for the beams' forwards only."""
+    w = synth.tiny()
+    pf = [dd.Plan(w.freqs, w.tsamp, n, w.ranges, "f32") for n in (w.nsamp, w.nsamp // 2 + 3)]
+    pu = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8")
+    with pytest.raises(dd.DDError) as e:
+        dd.Batch([pf[0], pu])
+    assert e.value.status == -6
+    b = dd.Batch(pf)
+    assert b.dtype == "f32" and len(b.groups) == 1
+    assert b.groups[0]["variant"] == 0 and b.groups[0]["dm_tile"] == 32
+    assert b.in_offsets[0] == 0 and b.in_offsets[1] >= 4 * pf[0].nchans * pf[0].nsamp
+    assert all(o % 256 == 0 for o in b.in_offsets) and all(o % 64 == 0 for o in b.out_offsets)
+    assert b.in_bytes >= b.in_offsets[1] + 4 * pf[1].nchans * pf[1].nsamp
+    assert b.out_elems >= b.out_offsets[1] + pf[1].out_elems
+    assert b.workspace_bytes < sum(p.workspace_bytes for p in pf)
+    tiles = sum(-(-r.nout // 1008) * -(-r.ndms // 32) for p in pf for r in p.ranges)
+    assert b.work_items == tiles
+    b.close()
+
+
 def test_default_strategy_prefers_exact_subband_reuse():
     """Variant 0 (the default) takes exact sub-band reuse at 192-DM tiles
     when the plan's delay patterns fit the LDS, else 128-DM tiles, else the
