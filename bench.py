@@ -319,7 +319,8 @@ def leg_batched(dd, synth, torch, plain_value, plain_rate, reps, tuner):
            "groups": [{k: g[k] for k in ("variant", "dm_tile", "work_items")}
                       for g in batch.groups],
            "work_items": batch.work_items,
-           "launches": "binning per beam + %d persistent" % len(batch.groups)}
+           "launches": "1 binning launch (every beam's power-of-two levels) + %d persistent"
+                       % len(batch.groups)}
     del xin, out, ws
     batch.close()
     return res

@@ -113,26 +113,35 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
                              [&](const BatchDescHost &x, const BatchDescHost &y) {
                                  return plans[x.beam]->nchans > plans[y.beam]->nchans;
                              });
+            // an item's cost: its channels plus a fixed part (staging of
+            // the first stage, tables, output stores) worth kItemOverheadChans
+            // channels, as the batch's kernels measure on beams of 1024 to
+            // 4096 channels
+            auto weight = [&](const BatchDescHost &d) {
+                return double(plans[d.beam]->nchans) + kItemOverheadChans;
+            };
             int64_t n = 0;
             double total = 0.0;
             for (size_t k = G.desc_begin; k < G.desc_end; ++k) {
                 BatchDescHost &d = b->descs[k];
                 d.item_start = n;
                 n += d.nitems;
-                total += double(d.nitems) * plans[d.beam]->nchans;
+                total += double(d.nitems) * weight(d);
             }
             G.nitems = n;
             b->nitems += n;
             // Queue x starts at the first item whose preceding cost reaches
             // x/8 of the group's total: contiguous slices (neighbouring tiles
             // share an XCD's L2) of equal cost, whatever the mix of channel
-            // counts.
+            // counts.  (A workgroup whose queue is empty takes items from the
+            // other queues, so an estimate off by a little costs only the
+            // L2 locality of the items it takes.)
             G.queue_bounds[0] = 0;
             double before = 0.0;
             int q = 1;
             for (size_t k = G.desc_begin; k < G.desc_end; ++k) {
                 const BatchDescHost &d = b->descs[k];
-                const double w = plans[d.beam]->nchans;
+                const double w = weight(d);
                 while (q < kBatchQueues &&
                        before + double(d.nitems) * w >= total * q / kBatchQueues) {
                     const double need = total * q / kBatchQueues - before;

@@ -1538,6 +1538,21 @@ struct QueueBounds {
 };
 static_assert(dd::kBatchQueues == kXcds, "one queue per XCD");
 
+// The next work item of a workgroup dealt to XCD x: from its own queue, and
+// once that is empty from the other XCDs' queues in turn (the cheapest items
+// of each sit at its end), or -1 when every queue is empty.  Counters only
+// grow, so an item is taken exactly once.
+__device__ __forceinline__ int64_t next_item(const QueueBounds &qb, int32_t *counters, int x)
+{
+    for (int k = 0; k < kXcds; ++k) {
+        const int q = (x + k) % kXcds;
+        const int64_t i = qb.b[q] + atomicAdd(&counters[q], 1);
+        if (i < qb.b[q + 1])
+            return i;
+    }
+    return -1;
+}
+
 template <bool DEDUP, int WAVES, int NW>
 __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict__ starts,
@@ -1549,16 +1564,13 @@ k_dedisp_u8_batch(const BatchDesc *__restrict__ descs, const int64_t *__restrict
     // 8-byte end.
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ int64_t s_item;
-    const int x = blockIdx.x % kXcds;
-    const int64_t q_begin = qb.b[x];
-    const int64_t q_end = qb.b[x + 1];
     for (;;) {
         if (threadIdx.x == 0)
-            s_item = q_begin + atomicAdd(&counters[x], 1);
+            s_item = next_item(qb, counters, blockIdx.x % kXcds);
         __syncthreads();
         const int64_t L = s_item;
         __syncthreads();
-        if (L >= q_end)
+        if (L < 0)
             break;
         int lo = 0, hi = ndesc - 1;
         while (lo < hi) {
@@ -1623,13 +1635,10 @@ k_dedisp_u8_sb_batch(const SbBatchDesc *__restrict__ descs, const int64_t *__res
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ int64_t s_item;
     for (;;) {
-        // thread 0 takes the next item of its XCD's queue (-1: queue empty),
-        // so that no queue bound stays live through the item
-        if (threadIdx.x == 0) {
-            const int x = blockIdx.x % kXcds;
-            const int64_t i = qb.b[x] + atomicAdd(&counters[x], 1);
-            s_item = i < qb.b[x + 1] ? i : -1;
-        }
+        // thread 0 takes the next item (-1: every queue empty), so that no
+        // queue bound stays live through the item
+        if (threadIdx.x == 0)
+            s_item = next_item(qb, counters, blockIdx.x % kXcds);
         __syncthreads();
         // the item is the same for the whole workgroup: keep it (and with it
         // the descriptor's fields) in scalar registers

@@ -245,6 +245,10 @@ struct BatchDescHost {
 };
 
 constexpr int kBatchQueues = 8;                // one work queue per XCD
+// fixed part of a batch item's cost, in channels: a 192-DM x 256-sample
+// variant-3 item of a 1024-channel beam takes as long as 1024 + ~330
+// channels' worth of a 4096-channel beam's item
+constexpr double kItemOverheadChans = 330.0;
 constexpr int kBatchMaxGroups = 8;             // kernels per batch
 
 struct BatchGroup {
