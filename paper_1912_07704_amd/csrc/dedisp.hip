@@ -809,11 +809,14 @@ k_dedisp_u8_sb(const SbArgs a)
 //                  dst[c][t] = w_c * sum_{k<f} src[c][f*t + k].
 // k_shiftsum_f32:  out[a][t] = sum_b rows[b][t + S[a][b]], the forward (a =
 //                  DM, b = channel) and the adjoint (a = channel, b = DM over
-//                  zero-padded output-gradient rows, S = P - s).  Staging as
-//                  in the integer kernel (direct global-to-LDS loads,
-//                  double-buffered), one float per sample.  Samples are read
-//                  as aligned 16-byte granules (lane l: granules l and
-//                  l + 63); a delay that is not a multiple of 4 takes the
+//                  zero-padded output-gradient rows, S = P - s).  Staging by
+//                  direct global-to-LDS loads into ONE stage buffer (two
+//                  buffers of half the rows ran slower: the stage loop is
+//                  bound by latency, which longer stages hide better, and a
+//                  CU's other workgroup computes while this one waits for
+//                  its loads), one float per sample.  Samples are read as
+//                  aligned 16-byte granules (lane l: granules l + 63g, g <
+//                  4); a delay that is not a multiple of 4 takes the
 //                  granule's head from the next lane by a cross-lane move
 //                  folded into the add.  Each output adds a stage's rows in a
 //                  fixed order, grouped by delay mod 4 (a table per output and
@@ -1183,7 +1186,6 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int nst = R.nstages;
     const StageSrc S = {src_rows, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_stride};
     const int TS = R.tab_stride;
-    const int CWt = CW + kFTileA * TS + 16;     // floats of one stage buffer: rows, then lists
 
     // acc[d][k*4 + j]: output aw0 + d at tile sample 4*(lane + 63k) + j
     float acc[kFP][kFW];
@@ -1195,15 +1197,10 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
 
     stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane, 0, ldsf + CW);
     for (int st = 0; st < nst; ++st) {
-        const float *A = ldsf + (st & 1) * CWt;
+        const float *A = ldsf;
         const float *T = A + CW;
         wait_loads();
         lds_barrier();
-        if (st + 1 < nst) {
-            const int bs = (st + 1) * C;
-            float *nb = ldsf + ((st + 1) & 1) * CWt;
-            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), nb, wave, lane, st + 1, nb + CW);
-        }
 #pragma unroll
         for (int d = 0; d < kFP; ++d) {
             // this output's list from LDS: its entries, then the class ends
@@ -1229,6 +1226,11 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
             add_class<1>(acc[d], A, ent, i, int((ends >> 8) & 0xFF), lane);
             add_class<2>(acc[d], A, ent, i, int((ends >> 16) & 0xFF), lane);
             add_class<3>(acc[d], A, ent, i, int(ends >> 24), lane);
+        }
+        if (st + 1 < nst) {
+            lds_barrier();          // every wave is done with this stage's rows and lists
+            const int bs = (st + 1) * C;
+            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf, wave, lane, st + 1, ldsf + CW);
         }
     }
 

@@ -116,8 +116,10 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
     if (stage > 1)
         stage &= ~1;
     auto stride_for = [&](int32_t st) { return (st + 1 + 3) / 4 * 4; };
+    // one stage buffer: the rows, then the output lists
     auto bytes_for = [&](int32_t st) {
-        return size_t(8) * (size_t(st) * size_t(sp.row_words) + size_t(kF32OutTile) * stride_for(st) + 16);
+        return sizeof(float) *
+               (size_t(st) * size_t(sp.row_words) + size_t(kF32OutTile) * stride_for(st) + 16);
     };
     while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
         stage = stage > 2 ? stage - 2 : 1;

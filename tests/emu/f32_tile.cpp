@@ -37,15 +37,15 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
     const long lds_floats = long(P.dtype == DD_F32 ? std::max(P.lds_bytes, P.adj_lds_bytes) : 0) / 4;
     const int TS = sp.tab_stride;
     CHECK(TS % 4 == 0 && TS >= C + 1, "[%s] list stride %d for %d rows", name, TS, C);
-    CHECK(long(2) * (long(C) * Wr + long(kF32OutTile) * TS + 16) <= lds_floats,
-          "[%s] stage buffers (%d x %d rows + lists) past LDS %ld", name, C, Wr, lds_floats);
+    CHECK(long(C) * Wr + long(kF32OutTile) * TS + 16 <= lds_floats,
+          "[%s] stage buffer (%d x %d rows + lists) past LDS %ld", name, C, Wr, lds_floats);
     CHECK(sp.off_offset % 4 == 0, "[%s] lists not 16-byte aligned", name);
     CHECK(Wr % 4 == 0, "[%s] row_words %d", name, Wr);
     CHECK(nst == (nrows + C - 1) / C, "[%s] nstages", name);
     const long nblocks = sp.ntime_tiles * sp.nout_tiles;
     long checked = 0;
-    std::vector<float> lds(size_t(2) * C * Wr);
-    std::vector<int> tag(size_t(2) * C * Wr);
+    std::vector<float> lds(size_t(C) * Wr);
+    std::vector<int> tag(size_t(C) * Wr);
     for (long lb = 0; lb < nblocks; lb = lb + block_stride < nblocks ? lb + block_stride : (lb == nblocks - 1 ? nblocks : nblocks - 1)) {
         const long tt = lb / sp.nout_tiles;
         const int tile = int(lb - tt * sp.nout_tiles);
@@ -53,7 +53,7 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
         std::vector<double> acc(size_t(kF32OutTile) * 64 * kF32Words, 0.0);
         for (int st = 0; st < nst; ++st) {
             const int b0 = st * C, bn = std::min(C, nrows - b0);
-            const long buf = long(st & 1) * C * Wr;
+            const long buf = 0;              // one stage buffer, refilled each stage
             std::fill(tag.begin() + buf, tag.begin() + buf + long(C) * Wr, -1);
             for (int j = 0; j < bn; ++j) {
                 const size_t bi = sp.base_offset + size_t(tile) * nrows + b0 + j;
