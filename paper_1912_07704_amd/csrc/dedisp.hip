@@ -18,6 +18,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "plan.h"
 
@@ -923,7 +924,7 @@ __global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ 
 
 struct SumArgs {
     const float *src;         // rows, `pitch` floats apart
-    const int32_t *off;       // [nout_tiles][nstages][kF32OutTile][tab_stride] output lists
+    const int32_t *off;       // [nout_tiles][nstages][tab_block] output lists (then level-1 jobs)
     const int32_t *base;      // [nout_tiles][nrows]
     float *dst;               // output rows, `dst_pitch` floats apart
     int64_t pitch;
@@ -938,6 +939,10 @@ struct SumArgs {
     int32_t row_words;
     int32_t nstages;
     int32_t tab_stride;
+    int32_t tab_block;        // ints per (tile, stage) table block
+    int32_t pat_words;        // floats of pattern rows per stage (0: no sub-band reuse)
+    int32_t njobs_max;        // level-1 job slots per stage
+    int32_t pad_;
 };
 
 struct SumBatch {
@@ -961,12 +966,12 @@ struct SumBatch {
 struct StageSrc {
     const float *src;
     const int32_t *base;
-    const int32_t *tab;       // [nout_tiles][nstages][kF32OutTile][tab_stride]
+    const int32_t *tab;       // [nout_tiles][nstages][tab_block]
     int64_t pitch;
     int32_t nrows;
     int32_t row_words;
     int32_t nstages;
-    int32_t tab_stride;
+    int32_t tab_block;
 };
 
 __device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int64_t t0, int bs,
@@ -974,12 +979,14 @@ __device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int
                                                 float *tbuf)
 {
     {
-        // the stage's output lists, 16 bytes per lane
-        const int chunks = kFTileA * S.tab_stride / 4;
-        const int q = wave * kWave + lane;
-        if (wave * kWave < chunks && q < chunks) {
-            const int32_t *g = S.tab + (int64_t(tile) * S.nstages + st) * kFTileA * S.tab_stride + 4 * q;
-            __builtin_amdgcn_global_load_lds(g, tbuf + wave * (4 * kWave), 16, 0, 0);
+        // the stage's table block (output lists, level-1 jobs), 16 bytes
+        // per lane
+        const int chunks = S.tab_block / 4;
+        const int32_t *blk = S.tab + (int64_t(tile) * S.nstages + st) * S.tab_block;
+        for (int c0 = wave * kWave; c0 < chunks; c0 += kBlock) {
+            const int q = c0 + lane;
+            if (q < chunks)
+                __builtin_amdgcn_global_load_lds(blk + 4 * q, tbuf + 4 * c0, 16, 0, 0);
         }
     }
     const int Wr = S.row_words;
@@ -1141,6 +1148,62 @@ __device__ __forceinline__ void add_class(float *acc, const float *A, const int 
     }
 }
 
+// Level 1 of sub-band reuse: one pattern row pass, the sum of its group's
+// rows (up to kSbGroup entries, ordered by class) at their offsets, G = 4
+// granules per lane (samples 0..1007 of the pattern row) or G = 1 (samples
+// 1008..1259); lanes 0..62 store their granules at the job's destination.
+constexpr int kSbJobInts = dd::kSbJobInts;
+
+template <int G>
+__device__ __forceinline__ void pattern_pass(float *lds, const int (&e)[4], uint32_t ends, int dest,
+                                             int lane)
+{
+    float acc[4 * G];
+#pragma unroll
+    for (int k = 0; k < 4 * G; ++k)
+        acc[k] = 0.0f;
+    int i = 0;
+    auto entry = [&](int k) { return k == 0 ? e[0] : k == 1 ? e[1] : k == 2 ? e[2] : e[3]; };
+    auto one = [&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        const int end = int((ends >> (8 * R)) & 0xFF);
+        for (; i < end; ++i) {
+            const f4v *p = reinterpret_cast<const f4v *>(lds + entry(i)) + lane;
+            f4v v[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                v[g] = p[(kWave - 1) * g];
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                add_window<R>(acc + 4 * g, v[g]);
+        }
+    };
+    one(std::integral_constant<int, 0>());
+    one(std::integral_constant<int, 1>());
+    one(std::integral_constant<int, 2>());
+    one(std::integral_constant<int, 3>());
+    if (lane < kWave - 1) {
+        f4v *out = reinterpret_cast<f4v *>(lds + dest) + lane;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            out[(kWave - 1) * g] = f4v{acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]};
+    }
+}
+
+__device__ __forceinline__ void build_pattern(float *lds, const float *job, int lane)
+{
+    const int *rec = reinterpret_cast<const int *>(job);
+    const int dest = __builtin_amdgcn_readfirstlane(rec[0]);
+    const int g4 = __builtin_amdgcn_readfirstlane(rec[1]);
+    const uint32_t ends = uint32_t(__builtin_amdgcn_readfirstlane(rec[2]));
+    const int e[4] = {__builtin_amdgcn_readfirstlane(rec[3]), __builtin_amdgcn_readfirstlane(rec[4]),
+                      __builtin_amdgcn_readfirstlane(rec[5]), __builtin_amdgcn_readfirstlane(rec[6])};
+    if (g4 == 4)
+        pattern_pass<4>(lds, e, ends, dest, lane);
+    else
+        pattern_pass<1>(lds, e, ends, dest, lane);
+}
+
 // NL: 16-byte granules per output list (2 when every problem's stage has at
 // most 8 rows, else 4).  PD: the problems come from device descriptors (a
 // batch of beams), found by binary search on block_start.
@@ -1184,8 +1247,10 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int CW = C * Wr;
     const int nrows = R.nrows;
     const int nst = R.nstages;
-    const StageSrc S = {src_rows, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_stride};
+    const StageSrc S = {src_rows, R.base, R.off, R.pitch, nrows, Wr, nst, R.tab_block};
     const int TS = R.tab_stride;
+    const int PW = R.pat_words;                 // pattern rows after the staged rows
+    const int NJ = R.njobs_max;
 
     // acc[d][k*4 + j]: output aw0 + d at tile sample 4*(lane + 63k) + j
     float acc[kFP][kFW];
@@ -1195,12 +1260,21 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         for (int k = 0; k < kFW; ++k)
             acc[d][k] = 0.0f;
 
-    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane, 0, ldsf + CW);
+    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane, 0, ldsf + CW + PW);
     for (int st = 0; st < nst; ++st) {
         const float *A = ldsf;
-        const float *T = A + CW;
+        const float *T = A + CW + PW;
         wait_loads();
         lds_barrier();
+        if (NJ > 0) {
+            // level 1: this stage's pattern rows, one job per wavefront in
+            // turn (nothing is in flight: plain LDS reads)
+            const float *J = T + kFTileA * TS;
+            const int njobs = __builtin_amdgcn_readfirstlane(__float_as_int(J[kSbJobInts * NJ]));
+            for (int j = wave; j < njobs; j += kWavesPerBlock)
+                build_pattern(ldsf, J + kSbJobInts * j, lane);
+            lds_barrier();
+        }
 #pragma unroll
         for (int d = 0; d < kFP; ++d) {
             // this output's list from LDS: its entries, then the class ends
@@ -1230,7 +1304,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         if (st + 1 < nst) {
             lds_barrier();          // every wave is done with this stage's rows and lists
             const int bs = (st + 1) * C;
-            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf, wave, lane, st + 1, ldsf + CW);
+            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf, wave, lane, st + 1, ldsf + CW + PW);
         }
     }
 
@@ -2158,6 +2232,9 @@ SumArgs sum_args(const dd::SumProblem &sp, const DeviceTables &t, const float *s
     R.row_words = sp.row_words;
     R.nstages = sp.nstages;
     R.tab_stride = sp.tab_stride;
+    R.tab_block = sp.tab_block;
+    R.pat_words = sp.npat * dd::kSbPatWords;
+    R.njobs_max = sp.njobs_max;
     return R;
 }
 

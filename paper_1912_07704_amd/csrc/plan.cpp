@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <new>
 #include <sstream>
 #include <string>
@@ -77,13 +78,31 @@ void parallel_for(int64_t n, int64_t work_per_item, F fn)
 }
 
 
+// Sub-band reuse of one (output tile, stage): the pattern rows it builds
+// and, per output and row group, the pattern the output adds (-1: the
+// group's rows directly).
+struct SbPattern {
+    int32_t group = 0;              // row group inside the stage
+    int32_t gn = 0;                 // rows in the group
+    int32_t u0 = 0;                 // smallest pattern offset of its outputs
+    std::vector<int32_t> rel;       // [gn] delay of each row minus the pattern offset
+    int32_t nout = 0;               // outputs that add it
+};
+
+struct SbStagePlan {
+    std::vector<SbPattern> pats;
+    std::vector<int32_t> pat_of;    // [kF32OutTile][groups]
+};
+
 // Tables of one float32 shift-and-sum problem (see plan.h).  S(a, b) gives
-// the delay of row b for output a; it must be >= 0.
+// the delay of row b for output a; it must be >= 0.  sb_mode: 0 sub-band
+// reuse where the work it saves passes a threshold, 1 never, 2 always
+// (error when its tables do not fit the LDS).
 template <typename SFn>
 dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_t nt, SFn S_,
                             std::vector<int32_t> &offF, std::vector<int32_t> &baseF,
                             int64_t *blocks, size_t *lds,
-                            std::string *err, const char *what, int32_t want_stage)
+                            std::string *err, const char *what, int32_t want_stage, int32_t sb_mode)
 {
     sp.nrows = nrows;
     sp.nouts = nouts;
@@ -108,69 +127,245 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         }
     }
     sp.span = span;
+    // window start of row b in a tile (16-byte aligned)
+    auto W0 = [&](int32_t tile, int32_t b) {
+        const int32_t m = mins[size_t(tile) * nrows + b];
+        return m - (m & 3);
+    };
     // a delay o <= span + 3 inside the window; lane 63 reads its last
     // granule at 4*(o >> 2) + 4*63*G (G granules per lane), up to float
     // 4*(o >> 2) + 252*G + 3
-    sp.row_words = (span + 3 + 252 * (kF32Words / 4) + 3 + 1 + 3) / 4 * 4;
+    const int32_t direct_words = (span + 3 + 252 * (kF32Words / 4) + 3 + 1 + 3) / 4 * 4;
+    auto stride_for = [&](int32_t st) { return (st + 1 + 3) / 4 * 4; };
+    // one stage buffer: the rows, the pattern rows, then the table block
+    auto bytes_for = [&](int32_t st, int32_t words, int32_t npat, int32_t tab_block) {
+        return sizeof(float) * (size_t(st) * size_t(words) + size_t(npat) * kSbPatWords +
+                                size_t(tab_block) + 16);
+    };
+
+    // ---- direct: every output adds every row of a stage
     int32_t stage = want_stage > 0 ? std::max(1, std::min(want_stage, kF32MaxStage)) : kF32MaxStage;
     if (stage > 1)
         stage &= ~1;
-    auto stride_for = [&](int32_t st) { return (st + 1 + 3) / 4 * 4; };
-    // one stage buffer: the rows, then the output lists
-    auto bytes_for = [&](int32_t st) {
-        return sizeof(float) *
-               (size_t(st) * size_t(sp.row_words) + size_t(kF32OutTile) * stride_for(st) + 16);
-    };
-    while (stage > 1 && bytes_for(stage) > kLdsTwoBlocks)
+    auto direct_block = [&](int32_t st) { return kF32OutTile * stride_for(st); };
+    while (stage > 1 && bytes_for(stage, direct_words, 0, direct_block(stage)) > kLdsTwoBlocks)
         stage = stage > 2 ? stage - 2 : 1;
-    if (bytes_for(stage) > kMaxLdsBytes) {
+    const bool direct_fits = bytes_for(stage, direct_words, 0, direct_block(stage)) <= kMaxLdsBytes;
+
+    // ---- sub-band reuse
+    const int32_t sb_nst = (nrows + kSbStage - 1) / kSbStage;
+    const int32_t ngroups = kSbStage / kSbGroup;
+    std::vector<SbStagePlan> sbs;
+    int32_t sb_cap = 0, sb_words = 0;
+    double cost_sb = 0.0, cost_direct = 0.0;
+    bool sb_fits = false;
+    if (sb_mode != 1 && nrows >= 2) {
+        for (int32_t cap : {8, 6, 4, 2}) {
+            sbs.assign(size_t(sp.nout_tiles) * sb_nst, SbStagePlan());
+            int32_t words = direct_words;
+            cost_sb = cost_direct = 0.0;
+            for (int32_t tile = 0; tile < sp.nout_tiles; ++tile) {
+                const int32_t a0 = tile * kF32OutTile;
+                const int32_t na = std::min(nouts, a0 + kF32OutTile) - a0;
+                cost_direct += double(na) * nrows;
+                for (int32_t st = 0; st < sb_nst; ++st) {
+                    SbStagePlan &P = sbs[size_t(tile) * sb_nst + st];
+                    P.pat_of.assign(size_t(kF32OutTile) * ngroups, -1);
+                    const int32_t b0 = st * kSbStage, bn = std::min(kSbStage, nrows - b0);
+                    // candidate patterns of every group: delays minus their
+                    // smallest, shared by two outputs or more
+                    struct Cand {
+                        int32_t group, gn, u0, spread_hi;
+                        std::vector<int32_t> rel, outs;
+                    };
+                    std::vector<Cand> cands;
+                    for (int32_t gi = 0; gi * kSbGroup < bn; ++gi) {
+                        const int32_t gb = b0 + gi * kSbGroup;
+                        const int32_t gn = std::min(kSbGroup, b0 + bn - gb);
+                        std::map<std::vector<int32_t>, size_t> at;
+                        for (int32_t al = 0; al < na; ++al) {
+                            std::vector<int32_t> rel(static_cast<size_t>(gn));
+                            int32_t base = S_(a0 + al, gb);
+                            for (int32_t j = 1; j < gn; ++j)
+                                base = std::min(base, S_(a0 + al, gb + j));
+                            for (int32_t j = 0; j < gn; ++j)
+                                rel[size_t(j)] = S_(a0 + al, gb + j) - base;
+                            auto it = at.find(rel);
+                            if (it == at.end()) {
+                                Cand c;
+                                c.group = gi;
+                                c.gn = gn;
+                                c.u0 = base;
+                                c.spread_hi = base;
+                                c.rel = rel;
+                                c.outs.push_back(al);
+                                at.emplace(rel, cands.size());
+                                cands.push_back(std::move(c));
+                            } else {
+                                Cand &c = cands[it->second];
+                                c.u0 = std::min(c.u0, base);
+                                c.spread_hi = std::max(c.spread_hi, base);
+                                c.outs.push_back(al);
+                            }
+                        }
+                    }
+                    std::vector<size_t> order;
+                    for (size_t k = 0; k < cands.size(); ++k) {
+                        const Cand &c = cands[k];
+                        // sharing pays when the outputs' direct adds exceed
+                        // the pattern row's (1.25 passes) plus one each
+                        if (c.gn >= 2 && c.outs.size() >= 2 &&
+                            c.spread_hi - c.u0 <= kSbMaxSpread &&
+                            double(c.outs.size()) * c.gn > 1.25 * c.gn + double(c.outs.size()))
+                            order.push_back(k);
+                    }
+                    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+                        return cands[x].outs.size() > cands[y].outs.size();
+                    });
+                    if (order.size() > size_t(cap))
+                        order.resize(size_t(cap));
+                    for (size_t k : order) {
+                        const Cand &c = cands[k];
+                        SbPattern pat;
+                        pat.group = c.group;
+                        pat.gn = c.gn;
+                        pat.u0 = c.u0;
+                        pat.rel = c.rel;
+                        pat.nout = int32_t(c.outs.size());
+                        const int32_t slot = int32_t(P.pats.size());
+                        for (int32_t al : c.outs)
+                            P.pat_of[size_t(al) * ngroups + c.group] = slot;
+                        // level-1 reads of row b: the window offset e of
+                        // the pattern's first sample, then 1260 + 4 floats
+                        for (int32_t j = 0; j < c.gn; ++j) {
+                            const int32_t b = b0 + c.group * kSbGroup + j;
+                            const int32_t e = c.u0 + c.rel[size_t(j)] - W0(tile, b);
+                            words = std::max(words, 4 * (e >> 2) + kSbPatWords + 4);
+                        }
+                        cost_sb += 1.25 * c.gn + double(c.outs.size());
+                        P.pats.push_back(std::move(pat));
+                    }
+                    for (int32_t al = 0; al < na; ++al)
+                        for (int32_t gi = 0; gi * kSbGroup < bn; ++gi)
+                            if (P.pat_of[size_t(al) * ngroups + gi] < 0)
+                                cost_sb += std::min(kSbGroup, bn - gi * kSbGroup);
+                }
+            }
+            words = (words + 3) / 4 * 4;
+            const int32_t block = kF32OutTile * stride_for(kSbStage) + kSbJobInts * 2 * cap + 4;
+            if (bytes_for(kSbStage, words, cap, block) <= kLdsTwoBlocks) {
+                sb_fits = true;
+                sb_cap = cap;
+                sb_words = words;
+                break;
+            }
+        }
+    }
+    const bool use_sb = sb_fits && (sb_mode == 2 || cost_sb < 0.75 * cost_direct);
+    if (sb_mode == 2 && !sb_fits) {
+        *err = fmt(what, ": the sub-band tables of this plan do not fit the LDS");
+        return DD_ERR_INVALID;
+    }
+    if (!use_sb && !direct_fits) {
         *err = fmt(what, ": delay spread ", span,
                    " inside one tile needs more LDS than a workgroup has; use a finer DM step");
         return DD_ERR_INVALID;
     }
-    sp.stage_rows = stage;
-    sp.nstages = (nrows + stage - 1) / stage;
-    sp.tab_stride = stride_for(stage);
-    *lds = std::max(*lds, bytes_for(stage));
+    if (use_sb) {
+        sp.stage_rows = kSbStage;
+        sp.row_words = sb_words;
+        sp.npat = sb_cap;
+        sp.njobs_max = 2 * sb_cap;
+    } else {
+        sp.stage_rows = stage;
+        sp.row_words = direct_words;
+        sp.npat = 0;
+        sp.njobs_max = 0;
+    }
+    const int32_t C = sp.stage_rows, Wr = sp.row_words;
+    sp.nstages = (nrows + C - 1) / C;
+    sp.tab_stride = stride_for(C);
+    sp.tab_block = kF32OutTile * sp.tab_stride + (use_sb ? kSbJobInts * sp.njobs_max + 4 : 0);
+    *lds = std::max(*lds, bytes_for(C, Wr, sp.npat, sp.tab_block));
     sp.block_start = *blocks;
     *blocks += sp.ntime_tiles * sp.nout_tiles;
     sp.base_offset = baseF.size();
     baseF.resize(baseF.size() + size_t(sp.nout_tiles) * nrows);
     for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
-        for (int32_t b = 0; b < nrows; ++b) {
-            const int32_t m = mins[size_t(tile) * nrows + b];
-            baseF[sp.base_offset + size_t(tile) * nrows + b] = m - (m & 3);
-        }
-    // Per (tile, stage, output): the stage's rows ordered by the class o & 3
-    // of their delay (stable), then in the list's last word the ends of the
-    // classes; the kernel stages each (tile, stage) block in LDS beside the
-    // rows.
-    const int32_t S = sp.tab_stride;
-    const size_t nlists = size_t(sp.nout_tiles) * size_t(sp.nstages) * kF32OutTile;
+        for (int32_t b = 0; b < nrows; ++b)
+            baseF[sp.base_offset + size_t(tile) * nrows + b] = W0(tile, b);
+    // Per (tile, stage): the output lists -- each output's entries ordered by
+    // the class o & 3 of their offset (stable), the class ends in the list's
+    // last word -- then (sub-band) the level-1 jobs and their count; the
+    // kernel stages each block in LDS beside the rows.
+    const int32_t TS = sp.tab_stride;
+    const size_t nblocks = size_t(sp.nout_tiles) * size_t(sp.nstages);
     offF.resize((offF.size() + 3) / 4 * 4, 0);
     sp.off_offset = offF.size();
-    offF.resize(offF.size() + nlists * size_t(S), 0);
+    offF.resize(offF.size() + nblocks * size_t(sp.tab_block), 0);
+    std::vector<std::pair<int32_t, int32_t>> items;   // (entry, class)
+    auto emit_sorted = [&](int32_t *out, int32_t *ends_out) {
+        int32_t n = 0;
+        uint32_t ends = 0;
+        for (int32_t cls = 0; cls < 4; ++cls) {
+            for (const auto &it : items)
+                if (it.second == cls)
+                    out[n++] = it.first;
+            ends |= uint32_t(n) << (8 * cls);
+        }
+        *ends_out = int32_t(ends);
+    };
     for (int32_t tile = 0; tile < sp.nout_tiles; ++tile)
-        for (int32_t st = 0; st < sp.nstages; ++st)
+        for (int32_t st = 0; st < sp.nstages; ++st) {
+            int32_t *blk = &offF[sp.off_offset + (size_t(tile) * sp.nstages + st) * sp.tab_block];
+            const int32_t b0 = st * C, bn = std::min(C, nrows - b0);
+            const SbStagePlan *P = use_sb ? &sbs[size_t(tile) * sb_nst + st] : nullptr;
             for (int32_t al = 0; al < kF32OutTile; ++al) {
                 const int32_t av = std::min(tile * kF32OutTile + al, nouts - 1);
-                const size_t list = (size_t(tile) * sp.nstages + st) * kF32OutTile + al;
-                int32_t *ent = &offF[sp.off_offset + list * S];
-                const int32_t b0 = st * stage, bn = std::min(stage, nrows - b0);
-                int32_t n = 0;
-                uint32_t ends = 0;
-                for (int32_t cls = 0; cls < 4; ++cls) {
-                    for (int32_t j = 0; j < bn; ++j) {
-                        const int32_t b = b0 + j;
-                        const int32_t m = mins[size_t(tile) * nrows + b];
-                        const int32_t o = (m & 3) + S_(av, b) - m;
-                        if ((o & 3) == cls)
-                            ent[n++] = j * sp.row_words + 4 * (o >> 2);
+                const int32_t alv = av - tile * kF32OutTile;
+                items.clear();
+                for (int32_t j = 0; j < bn; ++j) {
+                    const int32_t b = b0 + j;
+                    const int32_t gi = j / kSbGroup;
+                    const int32_t pat = P ? P->pat_of[size_t(alv) * ngroups + gi] : -1;
+                    if (pat >= 0) {
+                        if (j % kSbGroup == 0) {
+                            // the pattern row, at the output's offset
+                            const SbPattern &pt = P->pats[size_t(pat)];
+                            int32_t base = S_(av, b);
+                            for (int32_t k = 1; k < pt.gn; ++k)
+                                base = std::min(base, S_(av, b + k));
+                            const int32_t o = base - pt.u0;
+                            items.emplace_back(C * Wr + pat * kSbPatWords + 4 * (o >> 2), o & 3);
+                        }
+                        continue;
                     }
-                    ends |= uint32_t(n) << (8 * cls);
+                    const int32_t o = S_(av, b) - W0(tile, b);
+                    items.emplace_back(j * Wr + 4 * (o >> 2), o & 3);
                 }
-                ent[S - 1] = int32_t(ends);
+                emit_sorted(blk + size_t(al) * TS, blk + size_t(al) * TS + TS - 1);
             }
+            if (!P)
+                continue;
+            int32_t *jobs = blk + size_t(kF32OutTile) * TS;
+            const int32_t np = int32_t(P->pats.size());
+            for (int32_t pass = 0; pass < 2; ++pass)
+                for (int32_t k = 0; k < np; ++k) {
+                    const SbPattern &pt = P->pats[size_t(k)];
+                    int32_t *J = jobs + size_t(pass * np + k) * kSbJobInts;
+                    const int32_t shift = pass == 0 ? 0 : kF32TimeTile;
+                    J[0] = C * Wr + k * kSbPatWords + shift;
+                    J[1] = pass == 0 ? 4 : 1;
+                    items.clear();
+                    for (int32_t j = 0; j < pt.gn; ++j) {
+                        const int32_t slot = pt.group * kSbGroup + j;
+                        const int32_t e = pt.u0 + pt.rel[size_t(j)] - W0(tile, b0 + slot);
+                        items.emplace_back(slot * Wr + 4 * (e >> 2) + shift, e & 3);
+                    }
+                    emit_sorted(J + 3, J + 2);
+                }
+            jobs[size_t(sp.njobs_max) * kSbJobInts] = 2 * np;
+        }
     return DD_OK;
 }
 
@@ -183,7 +378,7 @@ const char *last_error() { return g_last_error.c_str(); }
 
 // Float32 plans: weighted 32-bit level copies, forward and adjoint problems
 // of the generic shift-and-sum, and the adjoint's workspace buffers.
-dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
+dd_status build_f32(Plan *p, int32_t want_stage, int32_t sb_mode, std::string *err)
 {
     const int32_t nchans = p->nchans;
     const int64_t nsamp = p->nsamp;
@@ -204,7 +399,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t *sh = &p->shifts[size_t(ri.dm_index) * nchans];
         auto Sf = [&](int32_t a, int32_t b) { return sh[size_t(a) * nchans + b]; };
         dd_status st = build_sum_problem(ri.fwd, nchans, ri.ndms, ri.nout, Sf, p->offF, p->baseF,
-                                         &blocks, &lds, err, "forward", want_stage);
+                                         &blocks, &lds, err, "forward", want_stage, sb_mode);
         if (st != DD_OK)
             return st;
     }
@@ -214,7 +409,7 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
         const int32_t P = ri.max_shift;
         auto Sa = [&](int32_t a, int32_t b) { return P - sh[size_t(b) * nchans + a]; };
         dd_status st = build_sum_problem(ri.adj, ri.ndms, nchans, ri.nbin, Sa, p->offF, p->baseF,
-                                         &ablocks, &alds, err, "adjoint", want_stage);
+                                         &ablocks, &alds, err, "adjoint", want_stage, sb_mode);
         if (st != DD_OK)
             return st;
     }
@@ -222,6 +417,11 @@ dd_status build_f32(Plan *p, int32_t want_stage, std::string *err)
     p->lds_bytes = lds;
     p->adj_blocks = ablocks;
     p->adj_lds_bytes = alds;
+    // reported as variant 3 when a forward problem uses sub-band reuse
+    p->subband = false;
+    p->dedup = true;
+    for (const RangeInfo &ri : p->ranges)
+        p->subband = p->subband || ri.fwd.npat > 0;
     for (int32_t ds : dss) {
         BinLevel lv;
         lv.ds = ds;
@@ -749,10 +949,6 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
                "or any of these (variant 0)";
         return DD_ERR_INVALID;
     }
-    if (want_variant == 3 && dtype != DD_U8) {
-        *err = "options: variant 3 is an integer (DD_U8) strategy";
-        return DD_ERR_INVALID;
-    }
     if (!freqs || !ranges || !p) {
         *err = "freqs_mhz, ranges and out must not be NULL";
         return DD_ERR_NULL;
@@ -895,7 +1091,13 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             p->dm_tile = kDmTile;
             p->waves = kWaves;
             p->time_tile = kTimeTile;
-            return build_f32(p, want_stage, err);
+            // variants 0, 1 and 2: direct sums; 3: sub-band reuse on every
+            // problem.  (Sub-band reuse saves 2.4-2.5x of the adds and LDS
+            // reads on the differentiable plans but ran no faster there: with
+            // 8-row stages the kernel is bound by each stage's load wait and
+            // barriers, so the autotuner, not the default, chooses it.)
+            const int32_t sb_mode = want_variant == 3 ? 2 : 1;
+            return build_f32(p, want_stage, sb_mode, err);
         }
         auto use = [&](int32_t variant, int32_t dm_tile, std::string *e) {
             p->dedup = variant == 2;

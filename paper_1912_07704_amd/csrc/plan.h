@@ -65,6 +65,21 @@ constexpr int kBoxLossStride = kF32TimeTile - kBoxMaxWidth;          // 976
 constexpr int kBoxLead = kBoxMaxWidth;                                // 32
 constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 944
 
+// Sub-band reuse in the float32 shift-and-sum (exact regrouping of the same
+// sum): rows are taken in groups of kSbGroup; outputs of a tile whose delays
+// on a group differ by one common offset (the same delay pattern) share a
+// pattern row, PR[u] = sum_{b in group} rows[b][u0 + u + rel(b)], built once
+// in LDS (level 1) and added by each of them at its own offset (level 2).
+// A pattern row is computed over kSbPatWords samples: a 1008-sample pass of
+// 4 granules per lane, then a 252-sample pass of one; a level-2 read of it
+// at offset o reaches float 4*(o >> 2) + 1011, so patterns spread by at most
+// kSbMaxSpread samples over their outputs.
+constexpr int kSbGroup = 4;
+constexpr int kSbStage = 8;                      // rows per stage (two groups)
+constexpr int kSbPatWords = kF32TimeTile + kF32TimeTile / 4;     // 1260
+constexpr int kSbMaxSpread = kSbPatWords - 1012;                 // 248
+constexpr int kSbJobInts = 8;                    // dest, granule passes, class ends, 4 entries, pad
+
 struct SumProblem {
     int32_t nrows = 0;          // b: rows summed
     int32_t nouts = 0;          // a: output rows
@@ -77,7 +92,12 @@ struct SumProblem {
     int64_t ntime_tiles = 0;
     int64_t block_start = 0;
     int32_t nstages = 0;        // ceil(nrows / stage_rows)
-    int32_t tab_stride = 0;     // ints per output list: roundup(stage_rows + 1, 4)
+    int32_t tab_stride = 0;     // ints per output list: roundup(max entries + 1, 4)
+    int32_t tab_block = 0;      // ints per (tile, stage) table block: the kF32OutTile lists,
+                                // then (sub-band) the level-1 jobs and their count
+    // sub-band reuse (0 patterns: every output adds the stage's rows directly)
+    int32_t npat = 0;           // pattern-row slots per stage
+    int32_t njobs_max = 0;      // level-1 jobs per stage (2 per pattern)
     // With m = min over the output tile of S[.][b], e = m & 3 and
     // o = e + S[a][b] - m (the delay inside the staged window):
     size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e
@@ -88,7 +108,14 @@ struct SumProblem {
                                 // = the row's place in the stage's LDS
                                 // buffer); the last word holds the ends of
                                 // the classes 0, 1, 2, 3 (one byte each, low
-                                // byte first)
+                                // byte first).  Sub-band problems: per
+                                // (tile, stage) a block of tab_block ints,
+                                // the lists (entries also name pattern rows,
+                                // at stage_rows * row_words + slot *
+                                // kSbPatWords + 4 * (o >> 2)), then njobs_max
+                                // jobs of kSbJobInts {destination float,
+                                // 4 or 1 granules per lane, class ends, up to
+                                // 4 row entries}, then the job count
 };
 
 // One 16-bit copy of the input, binned by ds (ds = 1: the samples widened

@@ -13,7 +13,8 @@ signature, device) in a JSON file (``DD_TUNE_CACHE``, default
 ``~/.cache/paper_1912_07704_amd/tune.json``).  A table of strategies
 measured on MI355X for the standard workloads ships with the package
 (``strategies.json``) and is consulted after the user cache, so a fresh
-machine does not re-time known plans.
+machine does not re-time known plans.  Float32 candidates are the direct
+sums at each stage size and sub-band reuse (variant 3).
 """
 from __future__ import annotations
 
@@ -221,9 +222,17 @@ def tune_f32(freqs, tsamp, nsamp, ranges, reps: int = 5, stages=F32_STAGES, use_
     g.manual_seed(0)
     x = torch.randn((len(freqs), nsamp), generator=g, device="cuda")
     timings, ref, best, seen = [], None, None, set()
-    for st in stages:
-        plan = Plan(freqs, tsamp, nsamp, ranges, "f32", stage_chans=st)
-        key = plan.strategy["chans_stage"]
+    # direct sums at each stage size, then sub-band reuse (variant 3, whose
+    # stage is fixed)
+    for st, variant in [(st, 1) for st in stages] + [(0, 3)]:
+        try:
+            plan = Plan(freqs, tsamp, nsamp, ranges, "f32", variant=variant,
+                        **({"stage_chans": st} if st else {}))
+        except DDError as e:
+            if e.status != DD_ERR_INVALID:
+                raise
+            continue                 # sub-band tables beyond the LDS
+        key = (variant, plan.strategy["chans_stage"])
         if key in seen:                  # clamped to a stage size already timed
             plan.close()
             continue
@@ -250,7 +259,7 @@ def tune_f32(freqs, tsamp, nsamp, ranges, reps: int = 5, stages=F32_STAGES, use_
             torch.cuda.synchronize()
             ms.append(a.elapsed_time(b))
         med = statistics.median(ms)
-        opts = {"stage_chans": key}
+        opts = {"variant": key[0], "stage_chans": key[1]} if key[0] == 1 else {"variant": 3}
         timings.append((opts, med))
         if best is None or med < best[1]:
             best = (opts, med)

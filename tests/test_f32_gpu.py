@@ -69,6 +69,35 @@ def test_forward_random_shapes(seed):
     check_close(out.cpu().numpy().astype(np.float64), want, terms, "forward")
 
 
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("seed", range(4))
+def test_direct_and_subband_sums_vs_oracle(seed, variant):
+    """The two float32 strategies -- direct sums (variant 1) and sub-band
+    reuse (variant 3: pattern rows of 4-row groups built in LDS, added at
+    each output's offset) -- forward and adjoint against the FP64 oracle."""
+    x, freqs, tsamp, ranges, w = case(200 + seed, nch=int(np.random.default_rng(seed).integers(9, 160)))
+    try:
+        O.expand_plan(freqs, tsamp, x.shape[1], ranges)
+    except ValueError:
+        pytest.skip("plan has no valid output")
+    say("f32 variant", variant, seed, x.shape, ranges)
+    plan = dd.Plan(freqs, tsamp, x.shape[1], ranges, "f32", variant=variant)
+    assert plan.strategy["variant"] == (3 if variant == 3 else 2)
+    xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    out = dd.dedisperse(xt, plan, weights=wt)
+    rng = np.random.default_rng(300 + seed)
+    g = rng.standard_normal(plan.out_elems).astype(np.float32)
+    dx, dw = dd.adjoint(torch.from_numpy(g).cuda(), plan, x=xt, weights=wt)
+    torch.cuda.synchronize()
+    want = cref.dedisperse_f32(x, freqs, tsamp, ranges, w)
+    terms = cref.dedisperse_f32(np.abs(x), freqs, tsamp, ranges, np.abs(w))
+    check_close(out.cpu().numpy().astype(np.float64), want, terms, "forward")
+    wX, ww = cref.adjoint_f32(x, freqs, tsamp, ranges, g.astype(np.float64), w)
+    tX, tw = cref.adjoint_f32(np.abs(x), freqs, tsamp, ranges, np.abs(g).astype(np.float64), np.abs(w))
+    check_close(dx.cpu().numpy().astype(np.float64), wX, tX, "dX")
+    check_close(dw.cpu().numpy().astype(np.float64), ww, tw, "dw")
+
+
 def test_forward_without_weights_equals_unit_weights():
     x, freqs, tsamp, ranges, _ = case(11, nch=33, nsamp=3000)
     say("f32 unit weights")

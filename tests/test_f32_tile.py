@@ -2,12 +2,16 @@
 
 tests/emu/f32_tile.cpp follows k_shiftsum_f32 on the host tables of float32
 plans (built by the library's own plan code), forward and adjoint problems:
-every LDS and global index is bounds-checked, each stage row appears once
-per output in its class list with the class its delay gives, every value a
-lane uses comes from its own row's window, and every output of lanes 0..62
-equals the direct sum (integer-valued inputs, exact in any order).  Plans
-with one channel, odd stages, permuted channels, two downsamples and the
-1024-channel differentiable band.  No GPU.
+every LDS and global index is bounds-checked; with sub-band reuse, the
+level-1 jobs build each pattern row from its group's rows (reads inside
+those rows' windows) and write only its slot; each stage row reaches every
+output exactly once, directly or through a pattern row; every value a lane
+uses comes from the row or pattern row its entry names; and every output of
+lanes 0..62 equals the direct sum (integer-valued inputs, exact in any
+order).  Plans with one channel, odd stages, permuted channels, two
+downsamples, the 1024-channel differentiable band and a 4096-channel band,
+with the default choice, direct sums only and sub-band reuse forced.  No
+GPU.
 """
 import os
 import re
@@ -36,6 +40,10 @@ def emulator(tmp_path_factory):
 def test_f32_tiles_forward_and_adjoint(emulator):
     r = subprocess.run([emulator], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and "FAIL" not in r.stdout, r.stdout[-3000:]
-    assert "plans 6 of 6, fails 0" in r.stdout, r.stdout[-3000:]
+    assert "plans 12 of 12, fails 0" in r.stdout, r.stdout[-3000:]
     checked = [int(a) + int(b) for a, b in re.findall(r"checked (\d+) \+ (\d+) outputs", r.stdout)]
-    assert len(checked) == 9 and sum(checked) > 5_000_000, r.stdout[-3000:]
+    assert len(checked) == 17 and sum(checked) > 10_000_000, r.stdout[-3000:]
+    # the forced sub-band plans (variant 3) build pattern rows in every problem
+    for line in r.stdout.splitlines():
+        if " sb] range" in line:
+            assert re.search(r"patterns [1-9]\d*/[1-9]", line), line

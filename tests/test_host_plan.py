@@ -229,13 +229,20 @@ def test_subband_option_errors(opts):
     assert e.value.status == -2
 
 
-def test_subband_variant_is_integer_only_and_batches_mix_kernels():
-    """Variant 3 is DD_U8 only.  A batch may mix kernels (variant family and
-    DM tile): each kernel's plans form one group of work items, summed by
-    their own persistent launch."""
+def test_float_subband_variants_and_batches_mix_kernels():
+    """For float32 plans variant 3 forces sub-band reuse (stages of 8 rows,
+    reported as variant 3), variant 1 forbids it (direct sums, reported as
+    variant 2 like before), and a one-channel plan cannot share patterns
+    (DD_ERR_INVALID when forced).  A batch may mix integer kernels (variant
+    family and DM tile): each kernel's plans form one group of work items,
+    summed by their own persistent launch."""
     w = synth.tiny()
+    pf3 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
+    assert pf3.strategy["variant"] == 3 and pf3.strategy["chans_stage"] == 8
+    pf1 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=1)
+    assert pf1.strategy["variant"] == 2
     with pytest.raises(dd.DDError) as e:
-        dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
+        dd.Plan(w.freqs[:1], w.tsamp, w.nsamp, w.ranges, "f32", variant=3)
     assert e.value.status == -2
     p3 = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8", variant=3)
     p3b = dd.Plan(w.freqs, w.tsamp, w.nsamp // 2, w.ranges, "u8", variant=3)

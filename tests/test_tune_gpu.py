@@ -77,3 +77,27 @@ def test_tune_explicit_candidates_without_cache(tmp_path, monkeypatch):
                               use_cache=False)
     assert len(timings) == 2 and best in cands
     assert not (tmp_path / "tune.json").exists()     # use_cache=False writes nothing
+
+
+def test_tune_f32_times_direct_and_subband_candidates(tmp_path, monkeypatch):
+    """The float32 tuner times the direct sums at each stage size and
+    sub-band reuse (variant 3), keeps the fastest, caches it, and the
+    winner's forward is within the float32 tolerance of the oracle."""
+    monkeypatch.setenv("DD_TUNE_CACHE", str(tmp_path / "tune.json"))
+    freqs = synth.band_freqs(1500.0, 1200.0, 96)
+    tsamp, nsamp, ranges = 2.56e-4, 6000, [(0.0, 60.0, 1.0, 1)]
+    say("tune_f32")
+    best, timings = tune.tune_f32(freqs, tsamp, nsamp, ranges, reps=2)
+    kinds = [t[0] for t in timings]
+    assert {"variant": 3} in kinds and any(k.get("variant") == 1 for k in kinds)
+    assert all(ms > 0 for _, ms in timings)
+    assert best == min(timings, key=lambda t: t[1])[0]
+    best2, _ = tune.tune_f32(freqs, tsamp, nsamp, ranges)          # from the cache
+    assert best2 == best
+    x = np.random.default_rng(5).standard_normal((96, nsamp)).astype(np.float32)
+    plan = dd.Plan(freqs, tsamp, nsamp, ranges, "f32", **best)
+    out = dd.dedisperse(torch.from_numpy(x).cuda(), plan).cpu().numpy().astype(np.float64)
+    want = cref.dedisperse_f32(x, freqs, tsamp, ranges)
+    terms = cref.dedisperse_f32(np.abs(x), freqs, tsamp, ranges)
+    assert np.abs(out - want).max() <= 1e-5 * np.abs(want).max()
+    assert (np.abs(out - want) <= 1e-5 * terms + 1e-30).all()
