@@ -974,39 +974,47 @@ struct StageSrc {
     int32_t tab_block;
 };
 
-__device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int64_t t0, int bs,
-                                                int bn, float *buf, int wave, int lane, int st,
-                                                float *tbuf)
+// The window starts of a stage's rows, lane j holding row bs + j's: one
+// vector load, issued a stage ahead so that its latency passes during the
+// sums (which issue no vector memory operations of their own).
+__device__ __forceinline__ int32_t stage_bases(const StageSrc &S, int tile, int bs, int bn, int lane)
 {
+    return lane < bn ? S.base[int64_t(tile) * S.nrows + bs + lane] : 0;
+}
+
+__device__ __forceinline__ void stage_issue_f32(const StageSrc &S, int tile, int64_t t0, int bs,
+                                                int bn, int32_t mv, float *buf, int wave, int lane,
+                                                int st, float *tbuf)
+{
+    // Wavefront w stages rows w and w + 8 of the stage (at most 16 rows).
+    // Their window starts are read out of mv before any of the stage's
+    // direct loads is issued, so that waiting for mv waits for nothing else
+    // (the previous stage's loads were waited for before its sums).
+    const int32_t m0 = __builtin_amdgcn_readlane(mv, wave);
+    const int32_t m1 = __builtin_amdgcn_readlane(mv, wave + kWavesPerBlock);
+    const int Wr = S.row_words;
+    const int chunks = Wr >> 2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = wave + h * kWavesPerBlock;
+        if (j >= bn)
+            break;
+        const float *row = S.src + int64_t(bs + j) * S.pitch + t0 + (h ? m1 : m0);
+        for (int c0 = 0; c0 < chunks; c0 += kWave) {
+            const int q = c0 + lane;
+            if (q < chunks)
+                __builtin_amdgcn_global_load_lds(row + 4 * q, buf + j * Wr + 4 * c0, 16, 0, 0);
+        }
+    }
     {
         // the stage's table block (output lists, level-1 jobs), 16 bytes
         // per lane
-        const int chunks = S.tab_block / 4;
+        const int tchunks = S.tab_block / 4;
         const int32_t *blk = S.tab + (int64_t(tile) * S.nstages + st) * S.tab_block;
-        for (int c0 = wave * kWave; c0 < chunks; c0 += kBlock) {
+        for (int c0 = wave * kWave; c0 < tchunks; c0 += kBlock) {
             const int q = c0 + lane;
-            if (q < chunks)
+            if (q < tchunks)
                 __builtin_amdgcn_global_load_lds(blk + 4 * q, tbuf + 4 * c0, 16, 0, 0);
-        }
-    }
-    const int Wr = S.row_words;
-    const int chunks = Wr >> 2;
-    const int ipr = (chunks + kWave - 1) / kWave;
-    int jl = -1;
-    int32_t m = 0;
-    for (int i = wave; i < bn * ipr; i += kWavesPerBlock) {
-        const int j = i / ipr;
-        const int part = i - j * ipr;
-        const int q = part * kWave + lane;
-        // (a scalar load, once per row: a vector load's wait would also wait
-        // for the staging loads in flight)
-        if (j != jl) {
-            m = table1(S.base + int64_t(tile) * S.nrows + bs + j);
-            jl = j;
-        }
-        if (q < chunks) {
-            const float *g = S.src + int64_t(bs + j) * S.pitch + t0 + m + 4 * q;
-            __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
         }
     }
 }
@@ -1260,12 +1268,15 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         for (int k = 0; k < kFW; ++k)
             acc[d][k] = 0.0f;
 
-    stage_issue_f32(S, tile, t0, 0, min(C, nrows), ldsf, wave, lane, 0, ldsf + CW + PW);
+    stage_issue_f32(S, tile, t0, 0, min(C, nrows), stage_bases(S, tile, 0, min(C, nrows), lane), ldsf,
+                    wave, lane, 0, ldsf + CW + PW);
     for (int st = 0; st < nst; ++st) {
         const float *A = ldsf;
         const float *T = A + CW + PW;
         wait_loads();
         lds_barrier();
+        const int bs_next = (st + 1) * C;
+        const int32_t mv_next = st + 1 < nst ? stage_bases(S, tile, bs_next, min(C, nrows - bs_next), lane) : 0;
         if (NJ > 0) {
             // level 1: this stage's pattern rows, one job per wavefront in
             // turn (nothing is in flight: plain LDS reads)
@@ -1303,8 +1314,8 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
         }
         if (st + 1 < nst) {
             lds_barrier();          // every wave is done with this stage's rows and lists
-            const int bs = (st + 1) * C;
-            stage_issue_f32(S, tile, t0, bs, min(C, nrows - bs), ldsf, wave, lane, st + 1, ldsf + CW + PW);
+            stage_issue_f32(S, tile, t0, bs_next, min(C, nrows - bs_next), mv_next, ldsf, wave, lane, st + 1,
+                            ldsf + CW + PW);
         }
     }
 

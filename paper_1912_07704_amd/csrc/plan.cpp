@@ -261,7 +261,10 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
             }
         }
     }
-    const bool use_sb = sb_fits && (sb_mode == 2 || cost_sb < 0.75 * cost_direct);
+    // (on the differentiable plans, 2.4-2.5x less work ran the forward
+    // 1.11x and the adjoint 1.01x faster: the 8-row stages pay more for
+    // their loads and barriers)
+    const bool use_sb = sb_fits && (sb_mode == 2 || cost_sb < (2.0 / 3.0) * cost_direct);
     if (sb_mode == 2 && !sb_fits) {
         *err = fmt(what, ": the sub-band tables of this plan do not fit the LDS");
         return DD_ERR_INVALID;
@@ -1091,12 +1094,10 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             p->dm_tile = kDmTile;
             p->waves = kWaves;
             p->time_tile = kTimeTile;
-            // variants 0, 1 and 2: direct sums; 3: sub-band reuse on every
-            // problem.  (Sub-band reuse saves 2.4-2.5x of the adds and LDS
-            // reads on the differentiable plans but ran no faster there: with
-            // 8-row stages the kernel is bound by each stage's load wait and
-            // barriers, so the autotuner, not the default, chooses it.)
-            const int32_t sb_mode = want_variant == 3 ? 2 : 1;
+            // variant 0: sub-band reuse on the problems where it saves at
+            // least a third of the work; 1 or 2: direct sums only; 3:
+            // sub-band reuse on every problem
+            const int32_t sb_mode = want_variant == 0 ? 0 : want_variant == 3 ? 2 : 1;
             return build_f32(p, want_stage, sb_mode, err);
         }
         auto use = [&](int32_t variant, int32_t dm_tile, std::string *e) {
