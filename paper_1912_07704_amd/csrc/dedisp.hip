@@ -922,6 +922,21 @@ __global__ __launch_bounds__(256) void k_pad_rows_f32(const float *__restrict__ 
     }
 }
 
+// The padding of one range's gradient rows: samples [0, P) and
+// [P + nout, gpitch) of each row set to 0 (the boxcar backward writes the
+// gradient between them itself).
+__global__ __launch_bounds__(256) void k_zero_pads(float *__restrict__ gpad, int64_t gpitch, int64_t P,
+                                                   int64_t nout, int nrows)
+{
+    const int64_t tail = gpitch - P - nout;
+    for (int64_t d = blockIdx.y; d < nrows; d += gridDim.y) {
+        float *row = gpad + d * gpitch;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < P + tail;
+             i += int64_t(gridDim.x) * blockDim.x)
+            row[i < P ? i : P + nout + (i - P)] = 0.0f;
+    }
+}
+
 struct SumArgs {
     const float *src;         // rows, `pitch` floats apart
     const int32_t *off;       // [nout_tiles][nstages][tab_block] output lists (then level-1 jobs)
@@ -942,7 +957,10 @@ struct SumArgs {
     int32_t tab_block;        // ints per (tile, stage) table block
     int32_t pat_words;        // floats of pattern rows per stage (0: no sub-band reuse)
     int32_t njobs_max;        // level-1 job slots per stage
-    int32_t pad_;
+    int32_t w_off;            // kAdjFinal: this problem's first weight (floats from BoxArgs::w)
+    int64_t x_off;            // kAdjFinal: this problem's x and dX rows (floats from BoxArgs::x, dX)
+    int64_t x_pitch;          // kAdjFinal: floats between rows of x and dX
+    int64_t part_off;         // kAdjFinal: its weight-gradient partials (floats from BoxArgs::partial)
 };
 
 struct SumBatch {
@@ -1040,15 +1058,15 @@ __host__ __device__ constexpr int box_rows(int mode) { return mode == kBoxGrad ?
 
 struct BoxArgs {
     float *partial;           // kBoxLoss: one float per workgroup; kAdjFinal:
-                              // [nouts][time tiles] weight-gradient partials
+                              // per problem (at its part_off), [nouts][time tiles]
+                              // weight-gradient partials
     int64_t t_stride;         // samples between consecutive time tiles
     int64_t t_lead;           // the first tile starts at sample -t_lead
     int32_t max_width;        // largest boxcar width (a power of two <= 32)
-    int32_t ntime_tiles;      // kAdjFinal: time tiles per output (partials' row length)
+    int32_t pad_;
     const float *x;           // kAdjFinal: input rows (NULL: no weight gradient)
     const float *w;           // kAdjFinal: channel weights (NULL: all 1)
     float *dX;                // kAdjFinal: input-gradient rows (NULL: not wanted)
-    int64_t x_pitch;          // kAdjFinal: floats between rows of x and dX
 };
 
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
@@ -1328,14 +1346,15 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
     const int t_lo = int(min<int64_t>(max<int64_t>(-t0, 0), kFSpan));   // tg >= 0
     const int t_end = int(min<int64_t>(max<int64_t>(nt - t0, -64), kFSpan + 64)); // tg < nt
     if constexpr (MODE == kAdjFinal) {
+        const int64_t ntt = (R.nt + kFTileT - 1) / kFTileT;    // the partials' row length
 #pragma unroll
         for (int d = 0; d < kFP; ++d) {
             const int c = aw0 + d;
             if (c >= R.nouts)
                 break;
-            const float wc = bx.w ? bx.w[c] : 1.0f;
-            float *dx = bx.dX ? bx.dX + int64_t(c) * bx.x_pitch + t0 : nullptr;
-            const float *xs = bx.x ? bx.x + int64_t(c) * bx.x_pitch + t0 : nullptr;
+            const float wc = bx.w ? bx.w[R.w_off + c] : 1.0f;
+            float *dx = bx.dX ? bx.dX + R.x_off + int64_t(c) * R.x_pitch + t0 : nullptr;
+            const float *xs = bx.x ? bx.x + R.x_off + int64_t(c) * R.x_pitch + t0 : nullptr;
             float part = 0.0f;
             if (lane_ok) {
 #pragma unroll
@@ -1355,7 +1374,7 @@ k_shiftsum_f32(const SumBatch a, const BoxArgs bx)
                 for (int h = kWave / 2; h > 0; h >>= 1)
                     part += __shfl_xor(part, h);
                 if (lane == 0)
-                    bx.partial[int64_t(c) * bx.ntime_tiles + tt] = part;
+                    bx.partial[R.part_off + int64_t(c) * ntt + tt] = part;
             }
         }
     } else if constexpr (MODE == kWrite) {
@@ -2304,6 +2323,9 @@ dd_status sum_f32(const Plan &p, const DeviceTables &t, float *d_out, const char
     return launch_sum(a, p.blocks, p.lds_bytes, stream);
 }
 
+// The adjoint.  d_g: the output gradient in the plan's output layout, copied
+// into the padded rows of the workspace; or NULL when the padded rows hold
+// it already (the boxcar backward writes them itself).
 dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, const float *d_x,
                       const float *d_w, float *d_dx, float *d_dw, char *d_ws, hipStream_t stream)
 {
@@ -2313,13 +2335,15 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
     for (size_t i = 0; i < p.ranges.size(); ++i) {
         const RangeInfo &ri = p.ranges[i];
         float *gpad = reinterpret_cast<float *>(d_ws + ri.gpad_offset);
-        const dim3 grid(unsigned(std::min<int64_t>((ri.gpitch + 1023) / 1024, 1024)),
-                        unsigned(std::min<int32_t>(ri.ndms, 65535)));
-        hipLaunchKernelGGL(k_pad_rows_f32, grid, dim3(256), 0, stream, d_g + ri.out_offset,
-                           ri.nout, int64_t(ri.max_shift), gpad, ri.gpitch, ri.ndms);
-        dd_status st = launch_check("k_pad_rows_f32");
-        if (st != DD_OK)
-            return st;
+        if (d_g) {
+            const dim3 grid(unsigned(std::min<int64_t>((ri.gpitch + 1023) / 1024, 1024)),
+                            unsigned(std::min<int32_t>(ri.ndms, 65535)));
+            hipLaunchKernelGGL(k_pad_rows_f32, grid, dim3(256), 0, stream, d_g + ri.out_offset,
+                               ri.nout, int64_t(ri.max_shift), gpad, ri.gpitch, ri.ndms);
+            dd_status st = launch_check("k_pad_rows_f32");
+            if (st != DD_OK)
+                return st;
+        }
         a.p[i] = sum_args(ri.adj, t, gpad, ri.gpitch,
                           reinterpret_cast<float *>(d_ws + ri.G_offset), ri.Gpitch);
     }
@@ -2331,11 +2355,10 @@ dd_status adjoint_f32(const Plan &p, const DeviceTables &t, const float *d_g, co
         std::memset(&fin, 0, sizeof(fin));
         fin.t_stride = kFTileT;
         fin.partial = partial;
-        fin.ntime_tiles = p.dw_tiles;
         fin.x = d_dw ? d_x : nullptr;
         fin.w = d_w;
         fin.dX = d_dx;
-        fin.x_pitch = p.nsamp;
+        a.p[0].x_pitch = p.nsamp;
         dd_status st = launch_sum_mode<kAdjFinal>(a, p.adj_blocks, p.adj_lds_bytes, fin, stream);
         if (st != DD_OK || !d_dw)
             return st;
@@ -2451,15 +2474,35 @@ dd_status boxcar_backward_f32(const Plan &p, const DeviceTables &t, const float 
                               int32_t nbeams, const float *d_w, int32_t max_width, float *d_dx,
                               float *d_dw, char *d_ws, hipStream_t stream)
 {
-    float *gout = reinterpret_cast<float *>(d_ws + p.gout_offset);
     float *dwb = reinterpret_cast<float *>(d_ws + p.dwb_offset);
     for (int32_t b = 0; b < nbeams; ++b) {
         const int64_t xoff = int64_t(b) * p.nchans * p.nsamp;
         dd_status st = bin_f32(p, d_in + xoff, d_w, d_ws, stream);
         if (st != DD_OK)
             return st;
+        // dL/dout straight into the adjoint's padded rows: their padding
+        // zeroed, the gradient tiles written between
         SumBatch a;
-        const int64_t blocks = box_batch(p, t, d_ws, gout, dd::kBoxGradStride, a);
+        std::memset(&a, 0, sizeof(a));
+        a.nprob = int32_t(p.ranges.size());
+        int64_t blocks = 0;
+        for (size_t i = 0; i < p.ranges.size(); ++i) {
+            const RangeInfo &ri = p.ranges[i];
+            const dd::BinLevel &lv = p.levels[ri.level];
+            float *gpad = reinterpret_cast<float *>(d_ws + ri.gpad_offset);
+            const int64_t P = ri.max_shift;
+            const dim3 zgrid(unsigned(std::min<int64_t>((ri.gpitch - ri.nout + 255) / 256, 64)),
+                             unsigned(std::min<int32_t>(ri.ndms, 65535)));
+            hipLaunchKernelGGL(k_zero_pads, zgrid, dim3(256), 0, stream, gpad, ri.gpitch, P, ri.nout,
+                               ri.ndms);
+            st = launch_check("k_zero_pads");
+            if (st != DD_OK)
+                return st;
+            a.p[i] = sum_args(ri.fwd, t, reinterpret_cast<const float *>(d_ws + lv.ws_offset) + lv.lead,
+                              lv.pitch, gpad + P, ri.gpitch);
+            a.p[i].block_start = blocks;
+            blocks += (ri.nout + dd::kBoxGradStride - 1) / dd::kBoxGradStride * ri.fwd.nout_tiles;
+        }
         BoxArgs bx;
         std::memset(&bx, 0, sizeof(bx));
         bx.t_stride = dd::kBoxGradStride;
@@ -2468,7 +2511,7 @@ dd_status boxcar_backward_f32(const Plan &p, const DeviceTables &t, const float 
         st = launch_sum_mode<kBoxGrad>(a, blocks, box_lds(p, kBoxGrad), bx, stream);
         if (st != DD_OK)
             return st;
-        st = adjoint_f32(p, t, gout, d_in + xoff, d_w, d_dx ? d_dx + xoff : nullptr,
+        st = adjoint_f32(p, t, nullptr, d_in + xoff, d_w, d_dx ? d_dx + xoff : nullptr,
                          d_dw ? dwb : nullptr, d_ws, stream);
         if (st != DD_OK)
             return st;

@@ -470,9 +470,8 @@ dd_status build_f32(Plan *p, int32_t want_stage, int32_t sb_mode, std::string *e
     p->dw_offset = ws;
     ws = align_up(ws + size_t(nchans) * size_t(std::max(p->dw_chunks, p->dw_tiles)) * sizeof(float),
                   kWsAlign);
-    // boxcar loss buffers
-    p->gout_offset = ws;
-    ws = align_up(ws + size_t(p->out_elems) * sizeof(float), kWsAlign);
+    // boxcar loss buffers (the backward writes dL/dout straight into the
+    // adjoint's padded rows)
     int64_t lp = 0;
     for (const RangeInfo &ri : p->ranges)
         lp += (ri.nout + kBoxLossStride - 1) / kBoxLossStride * ri.fwd.nout_tiles;

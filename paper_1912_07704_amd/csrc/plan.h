@@ -237,9 +237,8 @@ struct Plan {
     // weight-gradient partials itself, one per (channel, time tile).
     bool adj_fused = false;
     int32_t dw_tiles = 0;
-    // boxcar loss (float32 plans): dL/dout of one beam, the loss partials of
-    // one launch, and one beam's weight gradient.
-    size_t gout_offset = 0;                // [out_elems] floats
+    // boxcar loss (float32 plans): the loss partials of one launch and one
+    // beam's weight gradient.
     size_t box_offset = 0;                 // [box_partials + 64] floats
     int64_t box_partials = 0;
     size_t dwb_offset = 0;                 // [nchans] floats
