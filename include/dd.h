@@ -398,6 +398,26 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
  *                   in beam order, concatenated (sum of nchans floats),
  *                   or NULL for unit weights.  DD_ERR_DTYPE for an integer
  *                   batch with weights.
+ *
+ * Boxcar loss and its backward over a float32 batch (the loss of
+ * dd_boxcar_loss, each beam with its own plan):
+ * dd_batch_boxcar_workspace  bytes of the workspace these two calls need
+ *                   (more than dd_batch_info's: the padded gradient rows and
+ *                   the partials of every beam).  DD_ERR_DTYPE for an
+ *                   integer batch.
+ * dd_batch_boxcar_loss  the beams' levels, ONE loss launch over every (beam,
+ *                   range), ONE reduction: d_loss[b] = beam b's loss.
+ *                   d_in: the batch input; d_weights: each beam's weights
+ *                   concatenated (as dd_batch_forward_weighted), or NULL.
+ * dd_batch_boxcar_backward  its gradients, for plans with one range at full
+ *                   resolution (else DD_ERR_INVALID): the beams' levels, ONE
+ *                   launch zeroing the padding of the gradient rows, ONE
+ *                   gradient launch writing dL/dout into them, ONE adjoint
+ *                   launch forming dX and the weight-gradient partials, ONE
+ *                   reduction.  d_grad_in: dL/dx in the batch input's layout
+ *                   (float32 at each beam's in_offset), or NULL; d_grad_w:
+ *                   each beam's dL/dw concatenated like the weights, or NULL.
+ *                   Both calls allocate nothing and contain no memset.
  */
 typedef struct dd_batch dd_batch;
 
@@ -416,6 +436,13 @@ dd_status dd_batch_forward(const dd_batch *batch, const void *d_in, void *d_out,
 dd_status dd_batch_forward_weighted(const dd_batch *batch, const void *d_in, const float *d_weights,
                                     void *d_out, int64_t out_capacity, void *d_ws, size_t ws_bytes,
                                     void *stream);
+dd_status dd_batch_boxcar_workspace(const dd_batch *batch, size_t *bytes);
+dd_status dd_batch_boxcar_loss(const dd_batch *batch, const void *d_in, const float *d_weights,
+                               int32_t max_width, float *d_loss, void *d_ws, size_t ws_bytes,
+                               void *stream);
+dd_status dd_batch_boxcar_backward(const dd_batch *batch, const void *d_in, const float *d_weights,
+                                   int32_t max_width, float *d_grad_in, float *d_grad_w, void *d_ws,
+                                   size_t ws_bytes, void *stream);
 
 /*
  * Streaming (paper, "Pipeline": the pipeline walks the input in chunks and

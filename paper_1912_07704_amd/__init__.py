@@ -210,6 +210,20 @@ class Batch:
         """Per-beam flat outputs (views)."""
         return [out[o: o + p.out_elems] for p, o in zip(self.plans, self.out_offsets)]
 
+    def split_input(self, buf):
+        """Per-beam [nchans, nsamp] views of a float32 buffer in the batch
+        input's layout (an f32 batch's dL/dx)."""
+        return [buf[o // 4: o // 4 + p.nchans * p.nsamp].view(p.nchans, p.nsamp)
+                for p, o in zip(self.plans, self.in_offsets)]
+
+    def split_weights(self, buf):
+        """Per-beam views of a buffer of every beam's channels concatenated."""
+        out, at = [], 0
+        for p in self.plans:
+            out.append(buf[at: at + p.nchans])
+            at += p.nchans
+        return out
+
     def close(self) -> None:
         if self._h:
             lib().dd_batch_destroy(self._h)
@@ -487,6 +501,63 @@ def boxcar_backward(x, plan: Plan, weights=None, max_width: int = 32, grad_in=Tr
     check(lib().dd_boxcar_backward(plan.handle, _ptr(x), nb, _ptr(weights), int(max_width),
                                    _ptr(dx), _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)),
           "dd_boxcar_backward")
+    return dx, dw
+
+
+def batch_boxcar_workspace(batch: Batch, device=None):
+    """A workspace for the batch boxcar calls (dd_batch_boxcar_workspace)."""
+    import torch
+    n = ctypes.c_size_t()
+    check(lib().dd_batch_boxcar_workspace(batch.handle, ctypes.byref(n)), "dd_batch_boxcar_workspace")
+    return torch.empty(max(1, n.value), dtype=torch.uint8, device=device or "cuda")
+
+
+def _check_batch_input(x, batch: Batch):
+    import torch
+    if x.dtype != torch.uint8 or not x.is_cuda or not x.is_contiguous() or x.numel() < batch.in_bytes:
+        raise ValueError("x must be the packed batch input (bytes) on the device")
+    if batch.dtype != "f32":
+        raise ValueError("the batch boxcar calls take f32 batches")
+
+
+def _check_batch_weights(weights, batch: Batch):
+    import torch
+    if weights is not None and (weights.dtype != torch.float32 or not weights.is_contiguous()
+                                or weights.numel() != sum(p.nchans for p in batch.plans)):
+        raise ValueError("weights must be the packed float32 weights of every beam")
+
+
+def batch_boxcar_loss(x, batch: Batch, weights=None, max_width: int = 32, ws=None, stream=None):
+    """Per-beam boxcar losses of a float32 batch (dd_batch_boxcar_loss): x
+    and weights packed as for dedisperse_batch.  Returns [nbeams] float32."""
+    import torch
+    _check_batch_input(x, batch)
+    _check_batch_weights(weights, batch)
+    loss = torch.empty(len(batch.plans), dtype=torch.float32, device=x.device)
+    if ws is None:
+        ws = batch_boxcar_workspace(batch, x.device)
+    check(lib().dd_batch_boxcar_loss(batch.handle, _ptr(x), _ptr(weights), int(max_width), _ptr(loss),
+                                     _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_batch_boxcar_loss")
+    return loss
+
+
+def batch_boxcar_backward(x, batch: Batch, weights=None, max_width: int = 32, grad_in=True,
+                          grad_w=True, ws=None, stream=None):
+    """Gradients of the summed per-beam boxcar losses (dd_batch_boxcar_backward):
+    dL/dx as a float32 buffer in the batch input's layout (beam b's block at
+    in_offsets[b] // 4; see Batch.split_input) and dL/dw as every beam's
+    weight gradient concatenated."""
+    import torch
+    _check_batch_input(x, batch)
+    _check_batch_weights(weights, batch)
+    dx = torch.zeros(batch.in_bytes // 4, dtype=torch.float32, device=x.device) if grad_in else None
+    dw = (torch.empty(sum(p.nchans for p in batch.plans), dtype=torch.float32, device=x.device)
+          if grad_w else None)
+    if ws is None:
+        ws = batch_boxcar_workspace(batch, x.device)
+    check(lib().dd_batch_boxcar_backward(batch.handle, _ptr(x), _ptr(weights), int(max_width), _ptr(dx),
+                                         _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+          "dd_batch_boxcar_backward")
     return dx, dw
 
 

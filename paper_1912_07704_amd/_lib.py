@@ -38,6 +38,9 @@ SIGNATURES = {
     "dd_batch_prepare": (ctypes.c_int, [P]),
     "dd_batch_forward": (ctypes.c_int, [P, P, P, I64, P, SZ, P]),
     "dd_batch_forward_weighted": (ctypes.c_int, [P, P, P, P, I64, P, SZ, P]),
+    "dd_batch_boxcar_workspace": (ctypes.c_int, [P, P]),
+    "dd_batch_boxcar_loss": (ctypes.c_int, [P, P, P, I32, P, P, SZ, P]),
+    "dd_batch_boxcar_backward": (ctypes.c_int, [P, P, P, I32, P, P, P, SZ, P]),
     "dd_stream_create": (ctypes.c_int, [P, I32, P]),
     "dd_stream_destroy": (None, [P]),
     "dd_stream_info": (ctypes.c_int, [P, P, P]),

@@ -86,6 +86,27 @@ dd_status build_batch(const Plan *const *plans, int32_t nbeams, Batch *b, std::s
         b->out_elems = int64_t(out);
         b->w_elems = wn;
         b->ws_bytes = ws;
+        // float32: the boxcar calls' part of the workspace
+        b->gpad_off.assign(size_t(nbeams), std::vector<size_t>());
+        b->dwp_off.assign(size_t(nbeams), 0);
+        b->box_fused = b->dtype == DD_F32;
+        b->loss_blocks = 0;
+        if (b->dtype == DD_F32) {
+            for (int32_t i = 0; i < nbeams; ++i) {
+                const Plan *p = plans[i];
+                for (const RangeInfo &ri : p->ranges) {
+                    b->gpad_off[size_t(i)].push_back(ws);
+                    ws = align_up(ws + size_t(ri.ndms) * size_t(ri.gpitch) * sizeof(float), 256);
+                    b->loss_blocks += (ri.nout + kBoxLossStride - 1) / kBoxLossStride * ri.fwd.nout_tiles;
+                }
+                b->dwp_off[size_t(i)] = ws;
+                ws = align_up(ws + size_t(p->nchans) * size_t(std::max(p->dw_tiles, 1)) * sizeof(float), 256);
+                b->box_fused = b->box_fused && p->adj_fused;
+            }
+            b->loss_part_off = ws;
+            ws = align_up(ws + size_t(b->loss_blocks) * sizeof(float), 256);
+        }
+        b->box_ws_bytes = ws;
         // Work items: every (beam, range) contributes time tiles x DM tiles
         // items of equal shape whose cost grows with the beam's channels.
         b->descs.clear();

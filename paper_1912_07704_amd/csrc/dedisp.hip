@@ -2630,6 +2630,21 @@ dd_status forward_sum(const Plan &p, const DeviceTables &t, void *d_out, const c
 
 // Device-side batch state, per device: one allocation holding, per kernel
 // group, its descriptor array (BatchDesc or SbBatchDesc) and item starts.
+struct ZeroDesc {              // one range's padded gradient rows (k_zero_pads_batch)
+    int64_t off;              // floats from the workspace
+    int64_t gpitch;
+    int64_t P;
+    int64_t nout;
+    int64_t nrows;
+};
+
+struct SpanDesc {             // a beam's workgroups of a launch, or its channels' partials
+    int64_t first;            // first partial (floats from the partial base)
+    int64_t count;            // partials per output (k_reduce_spans: the whole span)
+    int64_t out;              // output index (beam, or the beam's first channel)
+    int64_t nrows;            // rows (channels) to reduce (1 for a loss span)
+};
+
 struct BatchDevice {
     void *mem = nullptr;
     std::vector<const void *> descs;       // per group
@@ -2637,6 +2652,15 @@ struct BatchDevice {
     const BinJob *bin_jobs = nullptr;      // beams with power-of-two levels
     int32_t nbin_jobs = 0;
     int64_t bin_blocks = 0;
+    // float32 boxcar calls: descriptors of the loss, gradient and adjoint
+    // launches (same problem order as the forward's), the padded rows to
+    // zero, and the reductions' spans
+    const SumArgs *box_loss = nullptr, *box_grad = nullptr, *adj = nullptr;
+    int64_t loss_blocks = 0, grad_blocks = 0, adj_blocks = 0;
+    int32_t max_stage_fwd = 0, max_stage_adj = 0;
+    const ZeroDesc *zero = nullptr;
+    int32_t nzero = 0;
+    const SpanDesc *loss_spans = nullptr, *dw_spans = nullptr;
 };
 
 struct BatchState {
@@ -2716,6 +2740,71 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
             D.widen_every = ri.widen_every;
         }
     }
+    // float32 boxcar descriptors (problem order as the forward group's)
+    size_t off_bl = 0, off_bg = 0, off_ad = 0, off_z = 0, off_ls = 0, off_dw = 0;
+    int64_t nbl = 0, nbg = 0, nad = 0;
+    int32_t ms_fwd = 0, ms_adj = 0, nz = 0;
+    if (b.dtype == DD_F32 && !b.groups.empty()) {
+        const dd::BatchGroup &G = b.groups[0];
+        const size_t n = G.desc_end - G.desc_begin;
+        std::vector<SumArgs> L(n), Gr(n), Ad(n);
+        std::vector<ZeroDesc> Z;
+        std::vector<SpanDesc> LS(b.plans.size()), DW(b.plans.size());
+        std::vector<int64_t> first(b.plans.size(), -1), last(b.plans.size(), 0);
+        for (size_t k = 0; k < n; ++k) {
+            const dd::BatchDescHost &d = b.descs[G.desc_begin + k];
+            const Plan &p = *b.plans[d.beam];
+            DeviceTables *t = nullptr;
+            dd_status s2 = device_tables(p, &t);
+            if (s2 != DD_OK)
+                return s2;
+            const RangeInfo &ri = p.ranges[d.range];
+            const dd::BinLevel &lv = p.levels[ri.level];
+            const size_t src_off = b.ws_off[d.beam] + lv.ws_offset + size_t(lv.lead) * sizeof(float);
+            const size_t gpad = b.gpad_off[d.beam][d.range];
+            // loss: partial index = the launch's workgroup index
+            L[k] = sum_args(ri.fwd, *t, reinterpret_cast<const float *>(src_off), lv.pitch, nullptr, ri.nout);
+            L[k].block_start = nbl;
+            if (first[d.beam] < 0)
+                first[d.beam] = nbl;
+            nbl += (ri.nout + dd::kBoxLossStride - 1) / dd::kBoxLossStride * ri.fwd.nout_tiles;
+            last[d.beam] = nbl;
+            // gradient: dL/dout into the padded rows, after their P zeros
+            const size_t g_dst = gpad + size_t(ri.max_shift) * sizeof(float);
+            Gr[k] = sum_args(ri.fwd, *t, reinterpret_cast<const float *>(src_off), lv.pitch,
+                             reinterpret_cast<float *>(g_dst), ri.gpitch);
+            Gr[k].block_start = nbg;
+            nbg += (ri.nout + dd::kBoxGradStride - 1) / dd::kBoxGradStride * ri.fwd.nout_tiles;
+            // adjoint over the padded rows; dX, x and the partials per beam
+            Ad[k] = sum_args(ri.adj, *t, reinterpret_cast<const float *>(gpad), ri.gpitch, nullptr, ri.Gpitch);
+            Ad[k].block_start = nad;
+            Ad[k].x_off = b.in_off[d.beam] / int64_t(sizeof(float));
+            Ad[k].x_pitch = p.nsamp;
+            Ad[k].part_off = int64_t(b.dwp_off[d.beam] / sizeof(float));
+            Ad[k].w_off = int32_t(b.w_off[d.beam]);
+            nad += ri.adj.ntime_tiles * ri.adj.nout_tiles;
+            ms_fwd = std::max(ms_fwd, ri.fwd.stage_rows);
+            ms_adj = std::max(ms_adj, ri.adj.stage_rows);
+            Z.push_back(ZeroDesc{int64_t(gpad / sizeof(float)), ri.gpitch, ri.max_shift, ri.nout, ri.ndms});
+        }
+        for (size_t i = 0; i < b.plans.size(); ++i) {
+            LS[i] = SpanDesc{first[i], last[i] - first[i], int64_t(i), 1};
+            const Plan &p = *b.plans[i];
+            DW[i] = SpanDesc{int64_t(b.dwp_off[i] / sizeof(float)), std::max(p.dw_tiles, 1), b.w_off[i], p.nchans};
+        }
+        auto put = [&](const void *src, size_t bytes) {
+            const size_t at = grow(std::max<size_t>(bytes, 1));
+            std::memcpy(img.data() + at, src, bytes);
+            return at;
+        };
+        off_bl = put(L.data(), n * sizeof(SumArgs));
+        off_bg = put(Gr.data(), n * sizeof(SumArgs));
+        off_ad = put(Ad.data(), n * sizeof(SumArgs));
+        off_z = put(Z.data(), Z.size() * sizeof(ZeroDesc));
+        off_ls = put(LS.data(), LS.size() * sizeof(SpanDesc));
+        off_dw = put(DW.data(), DW.size() * sizeof(SpanDesc));
+        nz = int32_t(Z.size());
+    }
     // binning jobs: every beam's power-of-two levels, one launch
     std::vector<BinJob> jobs;
     int64_t bin_blocks = 0;
@@ -2745,6 +2834,21 @@ dd_status batch_device(const dd::Batch &b, BatchDevice **out)
     bd.bin_jobs = reinterpret_cast<const BinJob *>(static_cast<const char *>(bd.mem) + off_jobs);
     bd.nbin_jobs = int32_t(jobs.size());
     bd.bin_blocks = bin_blocks;
+    if (b.dtype == DD_F32) {
+        const char *m = static_cast<const char *>(bd.mem);
+        bd.box_loss = reinterpret_cast<const SumArgs *>(m + off_bl);
+        bd.box_grad = reinterpret_cast<const SumArgs *>(m + off_bg);
+        bd.adj = reinterpret_cast<const SumArgs *>(m + off_ad);
+        bd.loss_blocks = nbl;
+        bd.grad_blocks = nbg;
+        bd.adj_blocks = nad;
+        bd.max_stage_fwd = ms_fwd;
+        bd.max_stage_adj = ms_adj;
+        bd.zero = reinterpret_cast<const ZeroDesc *>(m + off_z);
+        bd.nzero = nz;
+        bd.loss_spans = reinterpret_cast<const SpanDesc *>(m + off_ls);
+        bd.dw_spans = reinterpret_cast<const SpanDesc *>(m + off_dw);
+    }
     for (size_t g = 0; g < b.groups.size(); ++g) {
         bd.descs.push_back(static_cast<const char *>(bd.mem) + off_desc[g]);
         bd.starts.push_back(
@@ -2786,6 +2890,68 @@ const void *subband_batch_kernel(int dm_tile, int time_tile)
     }
 }
 
+// Float32 batch boxcar helpers.  k_zero_pads_batch: the padding of every
+// (beam, range)'s gradient rows (one descriptor per blockIdx.y).
+// k_reduce_spans: out[s.out] = fixed-order sum of partials [s.first,
+// s.first + s.count) (one span per block: a beam's loss).  k_reduce_rows_spans:
+// for span s and its channel c (blockIdx.x), out[s.out + c] = fixed-order sum
+// of the c-th row of s.count partials (a beam's weight gradient).
+__global__ __launch_bounds__(256) void k_zero_pads_batch(float *__restrict__ ws, const ZeroDesc *__restrict__ zd)
+{
+    const ZeroDesc z = zd[blockIdx.y];
+    const int64_t tail = z.gpitch - z.P - z.nout;
+    const int64_t per_row = z.P + tail;
+    const int64_t total = per_row * z.nrows;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i / per_row, k = i - r * per_row;
+        ws[z.off + r * z.gpitch + (k < z.P ? k : z.P + z.nout + (k - z.P))] = 0.0f;
+    }
+}
+
+__device__ __forceinline__ float block_sum_256(float v, float *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_spans(const float *__restrict__ partial,
+                                                      const SpanDesc *__restrict__ spans,
+                                                      float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const SpanDesc sp = spans[blockIdx.x];
+    float acc = 0.0f;
+    for (int64_t i = threadIdx.x; i < sp.count; i += 256)
+        acc += partial[sp.first + i];
+    const float total = block_sum_256(acc, red);
+    if (threadIdx.x == 0)
+        out[sp.out] = total;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_rows_spans(const float *__restrict__ partial,
+                                                           const SpanDesc *__restrict__ spans,
+                                                           float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const SpanDesc sp = spans[blockIdx.y];
+    for (int64_t c = blockIdx.x; c < sp.nrows; c += gridDim.x) {
+        float acc = 0.0f;
+        for (int64_t i = threadIdx.x; i < sp.count; i += 256)
+            acc += partial[sp.first + c * sp.count + i];
+        const float total = block_sum_256(acc, red);
+        if (threadIdx.x == 0)
+            out[sp.out + c] = total;
+        __syncthreads();
+    }
+}
+
 // Float32 batch: every beam's weighted levels (k_level_f32, beam by beam),
 // then one shift-and-sum launch over all (beam, range) problems, the most
 // expensive beams' workgroups first.
@@ -2812,6 +2978,104 @@ dd_status batch_forward_f32(const dd::Batch &b, const BatchDevice &bd, const cha
     std::memset(&bx, 0, sizeof(bx));
     bx.t_stride = kFTileT;
     return launch_sum_mode<kWrite, true>(a, G.nitems, G.lds_bytes, bx, stream);
+}
+
+size_t batch_lds(const dd::Batch &b, int mode)
+{
+    size_t lds = 0;
+    for (const dd::Plan *p : b.plans)
+        lds = std::max(lds, mode == kAdjFinal ? p->adj_lds_bytes : box_lds(*p, mode));
+    return lds;
+}
+
+// Float32 batch boxcar loss: the beams' levels, ONE loss launch over every
+// (beam, range) problem, ONE reduction to the per-beam losses.
+dd_status batch_boxcar_loss_f32(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
+                                const float *d_w, int32_t max_width, float *d_loss, char *d_ws,
+                                hipStream_t stream)
+{
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+        dd_status st = bin_f32(*b.plans[i], reinterpret_cast<const float *>(d_in + b.in_off[i]),
+                               d_w ? d_w + b.w_off[i] : nullptr, d_ws + b.ws_off[i], stream);
+        if (st != DD_OK)
+            return st;
+    }
+    float *partial = reinterpret_cast<float *>(d_ws + b.loss_part_off);
+    SumBatch a;
+    std::memset(&a, 0, sizeof(a));
+    a.pd = bd.box_loss;
+    a.nprob = int32_t(b.groups[0].desc_end - b.groups[0].desc_begin);
+    a.src_base = reinterpret_cast<uintptr_t>(d_ws);
+    a.max_stage = bd.max_stage_fwd;
+    BoxArgs bx;
+    std::memset(&bx, 0, sizeof(bx));
+    bx.partial = partial;
+    bx.t_stride = dd::kBoxLossStride;
+    bx.max_width = max_width;
+    dd_status st = launch_sum_mode<kBoxLoss, true>(a, bd.loss_blocks, batch_lds(b, kBoxLoss), bx, stream);
+    if (st != DD_OK)
+        return st;
+    hipLaunchKernelGGL(k_reduce_spans, dim3(unsigned(b.plans.size())), dim3(256), 0, stream, partial,
+                       bd.loss_spans, d_loss);
+    return launch_check("k_reduce_spans");
+}
+
+// Float32 batch boxcar backward (plans with one full-resolution range):
+// the beams' levels, ONE launch zeroing every padded row's padding, ONE
+// gradient launch writing dL/dout into the padded rows, ONE adjoint launch
+// forming dX and the weight-gradient partials, ONE reduction of those.
+dd_status batch_boxcar_backward_f32(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
+                                    const float *d_w, int32_t max_width, float *d_dx, float *d_dw,
+                                    char *d_ws, hipStream_t stream)
+{
+    for (size_t i = 0; i < b.plans.size(); ++i) {
+        dd_status st = bin_f32(*b.plans[i], reinterpret_cast<const float *>(d_in + b.in_off[i]),
+                               d_w ? d_w + b.w_off[i] : nullptr, d_ws + b.ws_off[i], stream);
+        if (st != DD_OK)
+            return st;
+    }
+    float *wsf = reinterpret_cast<float *>(d_ws);
+    hipLaunchKernelGGL(k_zero_pads_batch, dim3(64, unsigned(bd.nzero)), dim3(256), 0, stream, wsf, bd.zero);
+    dd_status st = launch_check("k_zero_pads_batch");
+    if (st != DD_OK)
+        return st;
+    const int32_t nprob = int32_t(b.groups[0].desc_end - b.groups[0].desc_begin);
+    SumBatch a;
+    std::memset(&a, 0, sizeof(a));
+    a.pd = bd.box_grad;
+    a.nprob = nprob;
+    a.src_base = a.dst_base = reinterpret_cast<uintptr_t>(d_ws);
+    a.max_stage = bd.max_stage_fwd;
+    BoxArgs bx;
+    std::memset(&bx, 0, sizeof(bx));
+    bx.t_stride = dd::kBoxGradStride;
+    bx.t_lead = dd::kBoxLead;
+    bx.max_width = max_width;
+    st = launch_sum_mode<kBoxGrad, true>(a, bd.grad_blocks, batch_lds(b, kBoxGrad), bx, stream);
+    if (st != DD_OK)
+        return st;
+    SumBatch j;
+    std::memset(&j, 0, sizeof(j));
+    j.pd = bd.adj;
+    j.nprob = nprob;
+    j.src_base = reinterpret_cast<uintptr_t>(d_ws);
+    j.max_stage = bd.max_stage_adj;
+    BoxArgs fin;
+    std::memset(&fin, 0, sizeof(fin));
+    fin.t_stride = kFTileT;
+    fin.partial = wsf;
+    fin.x = d_dw ? reinterpret_cast<const float *>(d_in) : nullptr;
+    fin.w = d_w;
+    fin.dX = d_dx;
+    st = launch_sum_mode<kAdjFinal, true>(j, bd.adj_blocks, batch_lds(b, kAdjFinal), fin, stream);
+    if (st != DD_OK || !d_dw)
+        return st;
+    int32_t max_ch = 1;
+    for (const dd::Plan *p : b.plans)
+        max_ch = std::max(max_ch, p->nchans);
+    hipLaunchKernelGGL(k_reduce_rows_spans, dim3(unsigned(std::min(max_ch, 4096)), unsigned(b.plans.size())),
+                       dim3(256), 0, stream, wsf, bd.dw_spans, d_dw);
+    return launch_check("k_reduce_rows_spans");
 }
 
 dd_status batch_forward(const dd::Batch &b, const BatchDevice &bd, const char *d_in,
@@ -3240,6 +3504,95 @@ static dd_status check_box_args(const dd_plan *plan, const float *d_in, int32_t 
         return DD_ERR_WORKSPACE;
     }
     return DD_OK;
+}
+
+namespace {
+
+dd_status check_batch_box(const dd_batch *batch, const void *d_in, int32_t max_width, const void *d_ws,
+                          size_t ws_bytes)
+{
+    if (!batch || !d_in || !d_ws) {
+        dd::set_error("batch, d_in and d_ws must not be NULL");
+        return DD_ERR_NULL;
+    }
+    const dd::Batch &b = batch->b;
+    if (b.dtype != DD_F32) {
+        dd::set_error("the boxcar calls take DD_F32 batches");
+        return DD_ERR_DTYPE;
+    }
+    if (max_width < 1 || max_width > dd::kBoxMaxWidth || (max_width & (max_width - 1)) != 0) {
+        dd::set_error("max_width must be a power of two in [1, 32]");
+        return DD_ERR_INVALID;
+    }
+    if (ws_bytes < b.box_ws_bytes || reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) {
+        dd::set_error("workspace of " + std::to_string(ws_bytes) + " bytes < required " +
+                      std::to_string(b.box_ws_bytes) + " (dd_batch_boxcar_workspace) or not 256-byte aligned");
+        return DD_ERR_WORKSPACE;
+    }
+    if (reinterpret_cast<uintptr_t>(d_in) % 256 != 0) {
+        dd::set_error("d_in must be 256-byte aligned");
+        return DD_ERR_INVALID;
+    }
+    return DD_OK;
+}
+
+}  // namespace
+
+dd_status dd_batch_boxcar_workspace(const dd_batch *batch, size_t *bytes)
+{
+    dd::clear_error();
+    if (!batch || !bytes) {
+        dd::set_error("batch and bytes must not be NULL");
+        return DD_ERR_NULL;
+    }
+    if (batch->b.dtype != DD_F32) {
+        dd::set_error("the boxcar calls take DD_F32 batches");
+        return DD_ERR_DTYPE;
+    }
+    *bytes = batch->b.box_ws_bytes;
+    return DD_OK;
+}
+
+dd_status dd_batch_boxcar_loss(const dd_batch *batch, const void *d_in, const float *d_weights,
+                               int32_t max_width, float *d_loss, void *d_ws, size_t ws_bytes,
+                               void *stream)
+{
+    dd::clear_error();
+    dd_status st = check_batch_box(batch, d_in, max_width, d_ws, ws_bytes);
+    if (st != DD_OK)
+        return st;
+    if (!d_loss) {
+        dd::set_error("d_loss must not be NULL");
+        return DD_ERR_NULL;
+    }
+    BatchDevice *bd = nullptr;
+    st = batch_device(batch->b, &bd);
+    if (st != DD_OK)
+        return st;
+    return batch_boxcar_loss_f32(batch->b, *bd, static_cast<const char *>(d_in), d_weights, max_width,
+                                 d_loss, static_cast<char *>(d_ws), static_cast<hipStream_t>(stream));
+}
+
+dd_status dd_batch_boxcar_backward(const dd_batch *batch, const void *d_in, const float *d_weights,
+                                   int32_t max_width, float *d_grad_in, float *d_grad_w, void *d_ws,
+                                   size_t ws_bytes, void *stream)
+{
+    dd::clear_error();
+    dd_status st = check_batch_box(batch, d_in, max_width, d_ws, ws_bytes);
+    if (st != DD_OK)
+        return st;
+    if (!batch->b.box_fused) {
+        dd::set_error("the batched boxcar backward takes plans of one range at full resolution "
+                      "(dd_boxcar_backward covers the others beam by beam)");
+        return DD_ERR_INVALID;
+    }
+    BatchDevice *bd = nullptr;
+    st = batch_device(batch->b, &bd);
+    if (st != DD_OK)
+        return st;
+    return batch_boxcar_backward_f32(batch->b, *bd, static_cast<const char *>(d_in), d_weights,
+                                     max_width, d_grad_in, d_grad_w, static_cast<char *>(d_ws),
+                                     static_cast<hipStream_t>(stream));
 }
 
 dd_status dd_boxcar_loss(const dd_plan *plan, const float *d_in, int32_t nbeams,

@@ -304,6 +304,15 @@ struct Batch {
     int64_t out_elems = 0;
     int64_t w_elems = 0;                   // float32: weights of all beams
     size_t ws_bytes = 0;
+    // float32 boxcar calls: after every beam's levels, per beam the
+    // adjoint's padded gradient rows of each range and its weight-gradient
+    // partials, then the loss partials of all beams
+    std::vector<std::vector<size_t>> gpad_off;   // [beam][range] bytes
+    std::vector<size_t> dwp_off;           // [beam] bytes: partials [nchans][dw_tiles]
+    size_t loss_part_off = 0;              // bytes
+    int64_t loss_blocks = 0;               // loss workgroups of all beams
+    size_t box_ws_bytes = 0;
+    bool box_fused = false;                // every plan's adjoint is fused (one range, ds 1)
     std::vector<BatchDescHost> descs;      // by group, most expensive items first in each
     std::vector<BatchGroup> groups;
     int64_t nitems = 0;                    // all groups

@@ -185,3 +185,112 @@ def test_boxcar_loss_autograd_vs_oracle():
                                        O.BOXCAR_WIDTHS)
     torch.cuda.synchronize()
     assert normwise(xt.grad[0].cpu().numpy(), gX1[0]) <= 1e-5
+
+
+def uneven_float_beams(seed, n, multi_range=False):
+    """Float32 beams of uneven channel counts and lengths, one full-resolution
+    range each (or, with multi_range, a second downsampled range on odd beams),
+    random channel weights."""
+    rng = np.random.default_rng(1300 + seed)
+    beams = []
+    for b in range(n):
+        nch = int(rng.choice([9, 40, 70]))
+        nsamp = int(rng.integers(2500, 6000))
+        freqs = synth.band_freqs(1500.0, float(rng.uniform(1250.0, 1400.0)), nch)
+        ranges = [(0.0, float(rng.integers(8, 30)), 1.0, 1)]
+        if multi_range and b % 2:
+            ranges.append((ranges[0][1], ranges[0][1] + 10.0, 2.0, 2))
+        x = rng.standard_normal((nch, nsamp)).astype(np.float32)
+        w = rng.uniform(0.5, 1.5, nch).astype(np.float32)
+        beams.append((x, freqs, 2.56e-4, ranges, w))
+    return beams
+
+
+@pytest.mark.parametrize("max_width", [32, 4])
+def test_batch_boxcar_matches_single_plans_and_oracle(max_width):
+    """The batched boxcar loss and backward (one launch per phase over every
+    beam) equal each beam's own dd_boxcar_loss / dd_boxcar_backward bit for
+    bit (the same partial sums in the same order) and the FP64 oracle within
+    the float32 tolerance."""
+    beams = uneven_float_beams(0, 5)
+    widths = tuple(2 ** i for i in range(int(np.log2(max_width)) + 1))
+    say("batch boxcar", max_width, [b[0].shape for b in beams])
+    plans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in beams]
+    batch = dd.Batch(plans)
+    xin = batch.pack([b[0] for b in beams])
+    wts = batch.pack_weights([b[4] for b in beams])
+    losses = dd.batch_boxcar_loss(xin, batch, wts, max_width)
+    dx, dw = dd.batch_boxcar_backward(xin, batch, wts, max_width)
+    torch.cuda.synchronize()
+    for i, ((x, f, t, r, w), p) in enumerate(zip(beams, plans)):
+        xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+        l1 = dd.boxcar_loss(xt, p, wt, max_width)
+        dx1, dw1 = dd.boxcar_backward(xt, p, wt, max_width)
+        torch.cuda.synchronize()
+        assert float(losses[i]) == float(l1), i
+        assert torch.equal(batch.split_input(dx)[i], dx1), i
+        assert torch.equal(batch.split_weights(dw)[i], dw1), i
+        L, gX, gw = oracle_loss_and_grads([x], f, t, r, w, widths)
+        assert abs(float(losses[i]) - L) <= 1e-5 * L
+        assert normwise(dx1.cpu().numpy().astype(np.float64), gX[0]) <= 1e-5
+        assert normwise(dw1.cpu().numpy().astype(np.float64), gw) <= 1e-5
+
+
+def test_batch_boxcar_graph_replay_and_limits():
+    """The batched boxcar loss and backward replay from a HIP graph (the
+    workspace scribbled and eager work between replays); a multi-range plan
+    batch computes the loss but refuses the batched backward."""
+    beams = uneven_float_beams(1, 3)
+    plans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in beams]
+    batch = dd.Batch(plans)
+    batch.prepare()
+    xin = batch.pack([b[0] for b in beams])
+    wts = batch.pack_weights([b[4] for b in beams])
+    ws = dd.batch_boxcar_workspace(batch)
+    e_loss = dd.batch_boxcar_loss(xin, batch, wts, 16, ws=ws).clone()
+    e_dx, e_dw = dd.batch_boxcar_backward(xin, batch, wts, 16, ws=ws)
+    loss = torch.zeros(len(plans), dtype=torch.float32, device="cuda")
+    dx = torch.zeros_like(e_dx)
+    dw = torch.zeros_like(e_dw)
+    L = dd.lib()
+
+    def run():
+        dd.check(L.dd_batch_boxcar_loss(batch.handle, dd._ptr(xin), dd._ptr(wts), 16, dd._ptr(loss),
+                                        dd._ptr(ws), ws.numel(), dd._stream_ptr(None)), "loss")
+        dd.check(L.dd_batch_boxcar_backward(batch.handle, dd._ptr(xin), dd._ptr(wts), 16, dd._ptr(dx),
+                                            dd._ptr(dw), dd._ptr(ws), ws.numel(), dd._stream_ptr(None)),
+                 "backward")
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for i in range(3):
+        loss.zero_()
+        dx.zero_()
+        dw.zero_()
+        ws.fill_(0x7F)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(loss, e_loss) and torch.equal(dw, e_dw), i
+        assert all(torch.equal(a, b) for a, b in zip(batch.split_input(dx), batch.split_input(e_dx))), i
+        other = dd.batch_boxcar_loss(xin, batch, wts, 16)       # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(other, e_loss)
+    mbeams = uneven_float_beams(2, 3, multi_range=True)
+    mplans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in mbeams]
+    mb = dd.Batch(mplans)
+    mx = mb.pack([b[0] for b in mbeams])
+    ml = dd.batch_boxcar_loss(mx, mb, None, 8)
+    torch.cuda.synchronize()
+    for i, ((x, f, t, r, _), p) in enumerate(zip(mbeams, mplans)):
+        assert float(ml[i]) == float(dd.boxcar_loss(torch.from_numpy(x).cuda(), p, None, 8))
+    with pytest.raises(dd.DDError) as e:
+        dd.batch_boxcar_backward(mx, mb, None, 8)
+    assert e.value.status == -2
