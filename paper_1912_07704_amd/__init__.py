@@ -546,13 +546,22 @@ def batch_boxcar_backward(x, batch: Batch, weights=None, max_width: int = 32, gr
     """Gradients of the summed per-beam boxcar losses (dd_batch_boxcar_backward):
     dL/dx as a float32 buffer in the batch input's layout (beam b's block at
     in_offsets[b] // 4; see Batch.split_input) and dL/dw as every beam's
-    weight gradient concatenated."""
+    weight gradient concatenated.  grad_in / grad_w: True (allocate), False
+    (skip) or a float32 tensor to write into."""
     import torch
     _check_batch_input(x, batch)
     _check_batch_weights(weights, batch)
-    dx = torch.zeros(batch.in_bytes // 4, dtype=torch.float32, device=x.device) if grad_in else None
-    dw = (torch.empty(sum(p.nchans for p in batch.plans), dtype=torch.float32, device=x.device)
-          if grad_w else None)
+    nw = sum(p.nchans for p in batch.plans)
+
+    def buf(arg, n):
+        if isinstance(arg, torch.Tensor):
+            if arg.dtype != torch.float32 or not arg.is_contiguous() or arg.numel() < n:
+                raise ValueError(f"output buffers must be contiguous float32 tensors of {n} or more")
+            return arg
+        return torch.zeros(n, dtype=torch.float32, device=x.device) if arg else None
+
+    dx = buf(grad_in, batch.in_bytes // 4)
+    dw = buf(grad_w, nw)
     if ws is None:
         ws = batch_boxcar_workspace(batch, x.device)
     check(lib().dd_batch_boxcar_backward(batch.handle, _ptr(x), _ptr(weights), int(max_width), _ptr(dx),
