@@ -138,9 +138,10 @@ dd_status dd_plan_create(const double *freqs_mhz, int32_t nchans, double tsamp_s
  *                default) or 128 (16 wavefronts), or 96 or 64 (8
  *                wavefronts); any of these for variant 0.
  *   time_tile    DD_U8 output samples per workgroup: 256 or 512 for variants
- *                1 and 2 (default 512) and for variant 3 at DM tiles 96 and
- *                64 (default 512); 256 only for variant 3 at DM tiles 192 and
- *                128.  DD_ERR_INVALID for other values.
+ *                1 and 2 (default 512, or 256 when 512-sample tiles would
+ *                give the plan fewer than 512 workgroups) and for variant 3
+ *                at DM tiles 96 and 64 (default 512); 256 only for variant 3
+ *                at DM tiles 192 and 128.  DD_ERR_INVALID for other values.
  */
 typedef struct {
     int32_t variant;

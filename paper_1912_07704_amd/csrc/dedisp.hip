@@ -255,25 +255,43 @@ __device__ __forceinline__ void wait_loads()
 // into the A copy at `buf` (row j at buf + j*Wr).  One wave instruction
 // moves 64 lanes x 16 bytes of one row.
 template <int WAVES, class RA>
-__device__ __forceinline__ void stage_issue(const RA &R, int nchans, int tile, int64_t t0,
-                                            int cs, int cn, uint32_t *buf, int wave, int lane)
+__device__ __forceinline__ int32_t stage_starts(const RA &R, int nchans, int tile, int cs, int cn, int lane)
 {
+    // the stage's window starts, lane j holding channel cs + j's
+    return lane < cn ? R.baseT[int64_t(tile) * nchans + cs + lane] : 0;
+}
+
+// Wavefront w stages channels w, w + WAVES, ... of the stage (at most
+// kMaxStageChans); their window starts are read out of ws (stage_starts,
+// loaded a stage earlier) before the first direct load is issued, so that
+// waiting for ws waits for nothing in flight.
+template <int WAVES, class RA>
+__device__ __forceinline__ void stage_issue(const RA &R, int nchans, int tile, int64_t t0,
+                                            int cs, int cn, int32_t ws, uint32_t *buf, int wave,
+                                            int lane)
+{
+    constexpr int kPer = (dd::kMaxStageChans + WAVES - 1) / WAVES;
+    int32_t w0s[kPer];
+#pragma unroll
+    for (int h = 0; h < kPer; ++h)
+        w0s[h] = __builtin_amdgcn_readlane(ws, min(wave + h * WAVES, kWave - 1));
     const int Wr = R.row_words;
     const int chunks = Wr >> 2;
-    const int ipr = (chunks + kWave - 1) / kWave;
-    for (int i = wave; i < cn * ipr; i += WAVES) {
-        const int j = i / ipr;
-        const int part = i - j * ipr;
-        const int q = part * kWave + lane;
+    const int CW = R.stage_chans * Wr;
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) {
+        const int j = wave + h * WAVES;
+        if (j >= cn)
+            break;
         const int64_t c = cs + j;
-        const int32_t w0 = table1(R.baseT + int64_t(tile) * nchans + c);
-        if (q < chunks) {
-            // even copy, and the odd-aligned copy: the same row one sample later
-            const uint16_t *g = R.src + c * R.pitch + t0 + 2 * int64_t(w0) + 8 * q;
-            const int CW = R.stage_chans * Wr;
-            __builtin_amdgcn_global_load_lds(g, buf + j * Wr + part * (4 * kWave), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds(g + 1, buf + CW + j * Wr + part * (4 * kWave), 16, 0,
-                                             0);
+        const uint16_t *g = R.src + c * R.pitch + t0 + 2 * int64_t(w0s[h]);
+        for (int c0 = 0; c0 < chunks; c0 += kWave) {
+            const int q = c0 + lane;
+            if (q < chunks) {
+                // even copy, and the odd-aligned copy: the same row one sample later
+                __builtin_amdgcn_global_load_lds(g + 8 * q, buf + j * Wr + 4 * c0, 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(g + 8 * q + 1, buf + CW + j * Wr + 4 * c0, 16, 0, 0);
+            }
         }
     }
 }
@@ -313,7 +331,12 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
             acc32[dd][k][1] = 0;
         }
 
-    stage_issue<WAVES>(R, nchans, tile, t0, 0, min(C, nchans), lds, wave, lane);
+    {
+        const int32_t ws0 = stage_starts<WAVES>(R, nchans, tile, 0, min(C, nchans), lane);
+        stage_issue<WAVES>(R, nchans, tile, t0, 0, min(C, nchans), ws0, lds, wave, lane);
+    }
+    // window starts of the next stage to issue, loaded one stage ahead
+    int32_t ws_next = nst > 1 ? stage_starts<WAVES>(R, nchans, tile, C, min(C, nchans - C), lane) : 0;
     int widen_left = R.widen_every;
     for (int st = 0; st < nst; ++st) {
         const int c0 = st * C;
@@ -326,8 +349,10 @@ __device__ __forceinline__ void dedisp_tile_u8(const RangeArgs &R, int64_t lb, u
         lds_barrier();
         if (st + 1 < nst) {
             const int cs = c0 + C;
-            stage_issue<WAVES>(R, nchans, tile, t0, cs, min(C, nchans - cs),
-                        lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+            stage_issue<WAVES>(R, nchans, tile, t0, cs, min(C, nchans - cs), ws_next,
+                               lds + ((st + 1) & 1) * (2 * CW), wave, lane);
+            const int cs2 = cs + C;
+            ws_next = st + 2 < nst ? stage_starts<WAVES>(R, nchans, tile, cs2, min(C, nchans - cs2), lane) : 0;
         }
 
         for (int jp = 0; jp < cn; jp += 2) {

@@ -1105,9 +1105,16 @@ dd_status build_plan(const double *freqs, int32_t nchans, double tsamp, int64_t 
             p->dm_tile = dm_tile;
             p->waves = dm_tile / kDmPerWave;
             // variant 3 at 192- and 128-DM tiles: 256-sample tiles; else the
-            // requested time tile, 512 by default
-            p->time_tile = want_time_tile ? want_time_tile
+            // requested time tile, by default 512, or for the direct kernel
+            // 256 when 512-sample tiles would leave fewer than
+            // kMinWorkgroups workgroups (a small plan then fills the GPU
+            // with twice as many)
+            int64_t wg512 = 0;
+            for (const RangeInfo &ri : p->ranges)
+                wg512 += (ri.nout + kTimeTile - 1) / kTimeTile * ((ri.ndms + dm_tile - 1) / dm_tile);
+            p->time_tile = want_time_tile                     ? want_time_tile
                            : (variant == 3 && dm_tile >= 128) ? kTimeTile / 2
+                           : variant != 3 && wg512 < kMinWorkgroups ? kTimeTile / 2
                                                               : kTimeTile;
             return p->subband ? build_subband(p, want_stage, e) : build_direct(p, want_stage, e);
         };

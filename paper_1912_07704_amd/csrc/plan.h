@@ -21,6 +21,7 @@ constexpr int kDmPerWave = 8;
 constexpr int kTimeTile = 128 * kWaveWords;      // samples per workgroup
 constexpr int kDmTile = kWaves * kDmPerWave;     // default DMs per workgroup
 constexpr int kMaxStageChans = 16;               // channels staged at once
+constexpr int64_t kMinWorkgroups = 512;          // 2 per CU: below, default time tiles halve
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr size_t kLdsTwoBlocks = 80 * 1024;      // LDS that still fits two workgroups per CU
 constexpr int kLevelAlign = 64;                  // samples; row pitch granule of a level
