@@ -1199,10 +1199,10 @@ __device__ __forceinline__ void add_class(float *acc, const float *A, const int 
     }
 }
 
-// Level 1 of sub-band reuse: one pattern row pass, the sum of its group's
-// rows (up to kSbGroup entries, ordered by class) at their offsets, G = 4
-// granules per lane (samples 0..1007 of the pattern row) or G = 1 (samples
-// 1008..1259); lanes 0..62 store their granules at the job's destination.
+// Level 1 of sub-band reuse: one pattern row, the sum of its group's rows
+// (up to kSbGroup entries, ordered by class) at their offsets, G = 5
+// granules per lane (samples 4(l + 63g) + j of the row's 1260); lanes 0..62
+// store their granules at the job's destination.
 constexpr int kSbJobInts = dd::kSbJobInts;
 
 template <int G>
@@ -1245,14 +1245,10 @@ __device__ __forceinline__ void build_pattern(float *lds, const float *job, int 
 {
     const int *rec = reinterpret_cast<const int *>(job);
     const int dest = __builtin_amdgcn_readfirstlane(rec[0]);
-    const int g4 = __builtin_amdgcn_readfirstlane(rec[1]);
     const uint32_t ends = uint32_t(__builtin_amdgcn_readfirstlane(rec[2]));
     const int e[4] = {__builtin_amdgcn_readfirstlane(rec[3]), __builtin_amdgcn_readfirstlane(rec[4]),
                       __builtin_amdgcn_readfirstlane(rec[5]), __builtin_amdgcn_readfirstlane(rec[6])};
-    if (g4 == 4)
-        pattern_pass<4>(lds, e, ends, dest, lane);
-    else
-        pattern_pass<1>(lds, e, ends, dest, lane);
+    pattern_pass<dd::kSbPatWords / 252>(lds, e, ends, dest, lane);   // rec[1] is always 5
 }
 
 // NL: 16-byte granules per output list (2 when every problem's stage has at

@@ -252,7 +252,7 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
                 }
             }
             words = (words + 3) / 4 * 4;
-            const int32_t block = kF32OutTile * stride_for(kSbStage) + kSbJobInts * 2 * cap + 4;
+            const int32_t block = kF32OutTile * stride_for(kSbStage) + kSbJobInts * cap + 4;
             if (bytes_for(kSbStage, words, cap, block) <= kLdsTwoBlocks) {
                 sb_fits = true;
                 sb_cap = cap;
@@ -278,7 +278,7 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
         sp.stage_rows = kSbStage;
         sp.row_words = sb_words;
         sp.npat = sb_cap;
-        sp.njobs_max = 2 * sb_cap;
+        sp.njobs_max = sb_cap;
     } else {
         sp.stage_rows = stage;
         sp.row_words = direct_words;
@@ -352,22 +352,20 @@ dd_status build_sum_problem(SumProblem &sp, int32_t nrows, int32_t nouts, int64_
                 continue;
             int32_t *jobs = blk + size_t(kF32OutTile) * TS;
             const int32_t np = int32_t(P->pats.size());
-            for (int32_t pass = 0; pass < 2; ++pass)
-                for (int32_t k = 0; k < np; ++k) {
-                    const SbPattern &pt = P->pats[size_t(k)];
-                    int32_t *J = jobs + size_t(pass * np + k) * kSbJobInts;
-                    const int32_t shift = pass == 0 ? 0 : kF32TimeTile;
-                    J[0] = C * Wr + k * kSbPatWords + shift;
-                    J[1] = pass == 0 ? 4 : 1;
-                    items.clear();
-                    for (int32_t j = 0; j < pt.gn; ++j) {
-                        const int32_t slot = pt.group * kSbGroup + j;
-                        const int32_t e = pt.u0 + pt.rel[size_t(j)] - W0(tile, b0 + slot);
-                        items.emplace_back(slot * Wr + 4 * (e >> 2) + shift, e & 3);
-                    }
-                    emit_sorted(J + 3, J + 2);
+            for (int32_t k = 0; k < np; ++k) {
+                const SbPattern &pt = P->pats[size_t(k)];
+                int32_t *J = jobs + size_t(k) * kSbJobInts;
+                J[0] = C * Wr + k * kSbPatWords;
+                J[1] = kSbPatWords / 252;         // granules per lane: the whole pattern row in one pass
+                items.clear();
+                for (int32_t j = 0; j < pt.gn; ++j) {
+                    const int32_t slot = pt.group * kSbGroup + j;
+                    const int32_t e = pt.u0 + pt.rel[size_t(j)] - W0(tile, b0 + slot);
+                    items.emplace_back(slot * Wr + 4 * (e >> 2), e & 3);
                 }
-            jobs[size_t(sp.njobs_max) * kSbJobInts] = 2 * np;
+                emit_sorted(J + 3, J + 2);
+            }
+            jobs[size_t(sp.njobs_max) * kSbJobInts] = np;
         }
     return DD_OK;
 }

@@ -71,15 +71,15 @@ constexpr int kBoxGradStride = kF32TimeTile - 2 * kBoxMaxWidth;      // 944
 // on a group differ by one common offset (the same delay pattern) share a
 // pattern row, PR[u] = sum_{b in group} rows[b][u0 + u + rel(b)], built once
 // in LDS (level 1) and added by each of them at its own offset (level 2).
-// A pattern row is computed over kSbPatWords samples: a 1008-sample pass of
-// 4 granules per lane, then a 252-sample pass of one; a level-2 read of it
+// A pattern row is computed over kSbPatWords samples in one pass of 5
+// granules per lane (lane l: granules l + 63g, g < 5); a level-2 read of it
 // at offset o reaches float 4*(o >> 2) + 1011, so patterns spread by at most
 // kSbMaxSpread samples over their outputs.
 constexpr int kSbGroup = 4;
 constexpr int kSbStage = 8;                      // rows per stage (two groups)
 constexpr int kSbPatWords = kF32TimeTile + kF32TimeTile / 4;     // 1260
 constexpr int kSbMaxSpread = kSbPatWords - 1012;                 // 248
-constexpr int kSbJobInts = 8;                    // dest, granule passes, class ends, 4 entries, pad
+constexpr int kSbJobInts = 8;                    // dest, granules per lane, class ends, 4 entries, pad
 
 struct SumProblem {
     int32_t nrows = 0;          // b: rows summed
@@ -98,7 +98,7 @@ struct SumProblem {
                                 // then (sub-band) the level-1 jobs and their count
     // sub-band reuse (0 patterns: every output adds the stage's rows directly)
     int32_t npat = 0;           // pattern-row slots per stage
-    int32_t njobs_max = 0;      // level-1 jobs per stage (2 per pattern)
+    int32_t njobs_max = 0;      // level-1 jobs per stage (one per pattern row)
     // With m = min over the output tile of S[.][b], e = m & 3 and
     // o = e + S[a][b] - m (the delay inside the staged window):
     size_t base_offset = 0;     // baseF: [nout_tiles][nrows] = m - e
@@ -115,8 +115,8 @@ struct SumProblem {
                                 // at stage_rows * row_words + slot *
                                 // kSbPatWords + 4 * (o >> 2)), then njobs_max
                                 // jobs of kSbJobInts {destination float,
-                                // 4 or 1 granules per lane, class ends, up to
-                                // 4 row entries}, then the job count
+                                // granules per lane (5), class ends, up to 4
+                                // row entries}, then the job count
 };
 
 // One 16-bit copy of the input, binned by ds (ds = 1: the samples widened

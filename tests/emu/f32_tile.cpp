@@ -36,10 +36,10 @@ static long fails = 0;
 // must lie inside [lo, hi) and carry tag `want` (or any tag >= 0 when want
 // is -1).
 static void lane_windows(const std::vector<float> &lds, const std::vector<int> &tag, long lo, long hi,
-                         int ent, int cls, int G, int want, double (*out)[16], const char *name,
+                         int ent, int cls, int G, int want, double (*out)[20], const char *name,
                          const char *what)
 {
-    static double gr[64][4][4];
+    static double gr[64][5][4];
     for (int l = 0; l < 64; ++l)
         for (int k = 0; k < G; ++k)
             for (int j = 0; j < 4; ++j) {
@@ -82,7 +82,7 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
     // the stage buffer: rows, then pattern rows (tags: row b, or -2 - slot)
     std::vector<float> lds(static_cast<size_t>(pat_end));
     std::vector<int> tag(static_cast<size_t>(pat_end));
-    static double win[64][16];
+    static double win[64][20];
     for (long lb = 0; lb < nblocks; lb = lb + block_stride < nblocks ? lb + block_stride : (lb == nblocks - 1 ? nblocks : nblocks - 1)) {
         const long tt = lb / sp.nout_tiles;
         const int tile = int(lb - tt * sp.nout_tiles);
@@ -111,27 +111,26 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
             if (sp.npat) {
                 const int32_t *jobs = blk + kF32OutTile * TS;
                 const int nj = jobs[kSbJobInts * sp.njobs_max];
-                CHECK(nj >= 0 && nj <= sp.njobs_max && nj % 2 == 0, "[%s] %d jobs", name, nj);
+                CHECK(nj >= 0 && nj <= sp.njobs_max, "[%s] %d jobs", name, nj);
                 for (int jb = 0; jb < nj; ++jb) {
                     const int32_t *J = jobs + kSbJobInts * jb;
                     const int dest = J[0], G = J[1];
                     const uint32_t ends = uint32_t(J[2]);
                     const int pslot = (dest - int(rows_end)) / kSbPatWords;
                     const int pbase = int(rows_end) + pslot * kSbPatWords;
-                    CHECK(G == (jb < nj / 2 ? 4 : 1), "[%s] job %d granules %d", name, jb, G);
-                    CHECK(pslot >= 0 && pslot < sp.npat && dest - pbase == (G == 4 ? 0 : kF32TimeTile),
-                          "[%s] job %d destination %d", name, jb, dest);
-                    if (!(pslot >= 0 && pslot < sp.npat)) continue;
+                    CHECK(G == 5, "[%s] job %d granules %d", name, jb, G);
+                    CHECK(pslot >= 0 && pslot < sp.npat && dest == pbase, "[%s] job %d destination %d", name, jb, dest);
+                    if (!(pslot >= 0 && pslot < sp.npat) || G != 5) continue;
                     int e[4] = {int(ends & 0xFF), int((ends >> 8) & 0xFF), int((ends >> 16) & 0xFF), int(ends >> 24)};
                     CHECK(e[0] <= e[1] && e[1] <= e[2] && e[2] <= e[3] && e[3] >= 1 && e[3] <= kSbGroup,
                           "[%s] job class ends %d %d %d %d", name, e[0], e[1], e[2], e[3]);
-                    std::vector<double> pr(size_t(64) * 16, 0.0);
+                    std::vector<double> pr(size_t(64) * 20, 0.0);
                     std::vector<int> rows_of;
                     int i = 0;
                     for (int cls = 0; cls < 4; ++cls)
                         for (; i < e[cls]; ++i) {
                             const int ent = J[3 + i];
-                            const int slot = (ent - (G == 4 ? 0 : kF32TimeTile)) / Wr;
+                            const int slot = ent / Wr;
                             CHECK(slot >= 0 && slot < bn && ent % 4 == 0, "[%s] job entry %d", name, ent);
                             if (!(slot >= 0 && slot < bn)) continue;
                             rows_of.push_back(slot);
@@ -139,20 +138,18 @@ static long emulate(const Plan &P, const SumProblem &sp, const std::vector<float
                                          name, "level 1");
                             for (int l = 0; l < 64; ++l)
                                 for (int k = 0; k < 4 * G; ++k)
-                                    pr[size_t(l) * 16 + k] += win[l][k];
+                                    pr[size_t(l) * 20 + k] += win[l][k];
                         }
                     std::sort(rows_of.begin(), rows_of.end());
-                    if (G == 4)
-                        pat_rows[size_t(pslot)] = rows_of;
-                    else
-                        CHECK(pat_rows[size_t(pslot)] == rows_of, "[%s] pattern %d passes differ in rows", name, pslot);
+                    CHECK(pat_rows[size_t(pslot)].empty(), "[%s] pattern %d built twice", name, pslot);
+                    pat_rows[size_t(pslot)] = rows_of;
                     for (int l = 0; l < 63; ++l)
                         for (int k = 0; k < G; ++k)
                             for (int j = 0; j < 4; ++j) {
                                 const long li = long(dest) + 4 * (l + 63 * k) + j;
                                 CHECK(li >= pbase && li < pbase + kSbPatWords, "[%s] pattern write %ld", name, li);
                                 if (li >= pbase && li < pbase + kSbPatWords) {
-                                    lds[li] = float(pr[size_t(l) * 16 + 4 * k + j]);
+                                    lds[li] = float(pr[size_t(l) * 20 + 4 * k + j]);
                                     tag[li] = -2 - pslot;
                                 }
                             }
