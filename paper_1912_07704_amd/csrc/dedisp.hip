@@ -2917,16 +2917,19 @@ const void *subband_batch_kernel(int dm_tile, int time_tile)
 // s.first + s.count) (one span per block: a beam's loss).  k_reduce_rows_spans:
 // for span s and its channel c (blockIdx.x), out[s.out + c] = fixed-order sum
 // of the c-th row of s.count partials (a beam's weight gradient).
-__global__ __launch_bounds__(256) void k_zero_pads_batch(float *__restrict__ ws, const ZeroDesc *__restrict__ zd)
+__global__ __launch_bounds__(256) void k_zero_pads_batch(float *__restrict__ ws, const ZeroDesc *__restrict__ zd,
+                                                         int nzd)
 {
-    const ZeroDesc z = zd[blockIdx.y];
-    const int64_t tail = z.gpitch - z.P - z.nout;
-    const int64_t per_row = z.P + tail;
-    const int64_t total = per_row * z.nrows;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t r = i / per_row, k = i - r * per_row;
-        ws[z.off + r * z.gpitch + (k < z.P ? k : z.P + z.nout + (k - z.P))] = 0.0f;
+    for (int di = blockIdx.y; di < nzd; di += gridDim.y) {
+        const ZeroDesc z = zd[di];
+        const int64_t tail = z.gpitch - z.P - z.nout;
+        const int64_t per_row = z.P + tail;
+        const int64_t total = per_row * z.nrows;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+             i += int64_t(gridDim.x) * blockDim.x) {
+            const int64_t r = i / per_row, k = i - r * per_row;
+            ws[z.off + r * z.gpitch + (k < z.P ? k : z.P + z.nout + (k - z.P))] = 0.0f;
+        }
     }
 }
 
@@ -2957,19 +2960,21 @@ __global__ __launch_bounds__(256) void k_reduce_spans(const float *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_reduce_rows_spans(const float *__restrict__ partial,
-                                                           const SpanDesc *__restrict__ spans,
+                                                           const SpanDesc *__restrict__ spans, int nspans,
                                                            float *__restrict__ out)
 {
     __shared__ float red[256];
-    const SpanDesc sp = spans[blockIdx.y];
-    for (int64_t c = blockIdx.x; c < sp.nrows; c += gridDim.x) {
-        float acc = 0.0f;
-        for (int64_t i = threadIdx.x; i < sp.count; i += 256)
-            acc += partial[sp.first + c * sp.count + i];
-        const float total = block_sum_256(acc, red);
-        if (threadIdx.x == 0)
-            out[sp.out + c] = total;
-        __syncthreads();
+    for (int si = blockIdx.y; si < nspans; si += gridDim.y) {
+        const SpanDesc sp = spans[si];
+        for (int64_t c = blockIdx.x; c < sp.nrows; c += gridDim.x) {
+            float acc = 0.0f;
+            for (int64_t i = threadIdx.x; i < sp.count; i += 256)
+                acc += partial[sp.first + c * sp.count + i];
+            const float total = block_sum_256(acc, red);
+            if (threadIdx.x == 0)
+                out[sp.out + c] = total;
+            __syncthreads();
+        }
     }
 }
 
@@ -3056,7 +3061,8 @@ dd_status batch_boxcar_backward_f32(const dd::Batch &b, const BatchDevice &bd, c
             return st;
     }
     float *wsf = reinterpret_cast<float *>(d_ws);
-    hipLaunchKernelGGL(k_zero_pads_batch, dim3(64, unsigned(bd.nzero)), dim3(256), 0, stream, wsf, bd.zero);
+    hipLaunchKernelGGL(k_zero_pads_batch, dim3(64, unsigned(std::min(bd.nzero, 65535))), dim3(256), 0, stream,
+                       wsf, bd.zero, bd.nzero);
     dd_status st = launch_check("k_zero_pads_batch");
     if (st != DD_OK)
         return st;
@@ -3094,8 +3100,9 @@ dd_status batch_boxcar_backward_f32(const dd::Batch &b, const BatchDevice &bd, c
     int32_t max_ch = 1;
     for (const dd::Plan *p : b.plans)
         max_ch = std::max(max_ch, p->nchans);
-    hipLaunchKernelGGL(k_reduce_rows_spans, dim3(unsigned(std::min(max_ch, 4096)), unsigned(b.plans.size())),
-                       dim3(256), 0, stream, wsf, bd.dw_spans, d_dw);
+    const int nspans = int(b.plans.size());
+    hipLaunchKernelGGL(k_reduce_rows_spans, dim3(unsigned(std::min(max_ch, 4096)), unsigned(std::min(nspans, 65535))),
+                       dim3(256), 0, stream, wsf, bd.dw_spans, nspans, d_dw);
     return launch_check("k_reduce_rows_spans");
 }
 
