@@ -248,20 +248,23 @@ def dedisperse_batch(x, batch: Batch, out=None, ws=None, stream=None, weights=No
     odt = torch.int32 if batch.dtype == "u8" else torch.float32
     if out is None:
         out = torch.empty(batch.out_elems, dtype=odt, device=x.device)
-    if out.dtype != odt or not out.is_contiguous():
-        raise ValueError(f"out must be a contiguous {odt} tensor")
+    if out.dtype != odt:
+        raise ValueError(f"out must be a {odt} tensor")
+    _on(out, x.device, "out")
     if ws is None:
         ws = torch.empty(batch.workspace_bytes, dtype=torch.uint8, device=x.device)
+    wsb = _ws_bytes(ws, x.device)
     if weights is not None:
-        if (weights.dtype != torch.float32 or not weights.is_contiguous()
+        if (weights.dtype != torch.float32
                 or weights.numel() != sum(p.nchans for p in batch.plans)):
             raise ValueError("weights must be the packed float32 weights of every beam")
+        _on(weights, x.device, "weights")
         check(lib().dd_batch_forward_weighted(batch.handle, _ptr(x), _ptr(weights), _ptr(out),
-                                              out.numel(), _ptr(ws), ws.numel(),
+                                              out.numel(), _ptr(ws), wsb,
                                               _stream_ptr(stream)), "dd_batch_forward_weighted")
         return out
     check(lib().dd_batch_forward(batch.handle, _ptr(x), _ptr(out), out.numel(), _ptr(ws),
-                                 ws.numel(), _stream_ptr(stream)), "dd_batch_forward")
+                                 wsb, _stream_ptr(stream)), "dd_batch_forward")
     return out
 
 
@@ -291,9 +294,15 @@ class Stream:
         """Feed the next block ([nchans, n] channel-major or [n, nchans]
         time-major device tensor, n = first for the first push, then step).
         Returns (chunk index, flat output of the chunk)."""
+        if block.dim() != 2 or block.dtype != self.chunk.dtype or \
+                block.shape[1 if self.time_major else 0] != self.plan.nchans:
+            raise ValueError(f"block must be a {self.chunk.dtype} "
+                             + ("[n, nchans]" if self.time_major else "[nchans, n]") + " tensor")
         samples = block.shape[0] if self.time_major else block.shape[1]
+        block = _on(block.contiguous(), self.chunk.device, "block")
+        _check_weights(weights, self.plan, self.chunk.device)
         idx = ctypes.c_int64()
-        check(lib().dd_stream_push(self._h, _ptr(block.contiguous()), int(samples), _ptr(self.chunk),
+        check(lib().dd_stream_push(self._h, _ptr(block), int(samples), _ptr(self.chunk),
                                    _ptr(weights), _ptr(self.out), self.out.numel(), _ptr(self.ws),
                                    self.ws.numel(), ctypes.byref(idx), _stream_ptr(stream)),
               "dd_stream_push")
@@ -349,6 +358,20 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _on(t, dev, what):
+    """t (when given) must be a contiguous tensor on the device `dev`: the
+    library hands its address to kernels, which would fault on host memory."""
+    if t is not None and (not t.is_cuda or t.device != dev or not t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous tensor on {dev}")
+    return t
+
+
+def _ws_bytes(ws, dev):
+    """Bytes of a caller's workspace tensor on `dev` (any dtype)."""
+    _on(ws, dev, "ws")
+    return ws.numel() * ws.element_size() if ws is not None else 0
+
+
 def _check_input(x, plan):
     import torch
     want = torch.uint8 if plan.dtype == "u8" else torch.float32
@@ -359,13 +382,15 @@ def _check_input(x, plan):
         raise ValueError("input must be a contiguous device tensor")
 
 
-def _check_weights(weights, plan):
+def _check_weights(weights, plan, dev=None):
     import torch
     if weights is None:
         return
     if (weights.dtype != torch.float32 or not weights.is_cuda or not weights.is_contiguous()
             or weights.numel() != plan.nchans):
         raise ValueError(f"weights must be a contiguous device float32 tensor of {plan.nchans}")
+    if dev is not None:
+        _on(weights, dev, "weights")
 
 
 def _out_tensor(plan, out, device):
@@ -375,6 +400,8 @@ def _out_tensor(plan, out, device):
         return torch.empty(plan.out_elems, dtype=odt, device=device)
     if out.dtype != odt or not out.is_cuda or not out.is_contiguous():
         raise ValueError(f"out must be a contiguous device {odt} tensor")
+    if not isinstance(device, str):
+        _on(out, device, "out")
     return out
 
 
@@ -389,17 +416,18 @@ def dedisperse(x, plan: Plan, out=None, weights=None, ws=None, stream=None, step
         raise ValueError("step must be 'all' or 'sum'")
     if step == "all":
         _check_input(x, plan)
-        _check_weights(weights, plan)
+        _check_weights(weights, plan, x.device)
     out = _out_tensor(plan, out, x.device if x is not None else "cuda")
     if ws is None:
         if step == "sum":
             raise ValueError("step='sum' needs the workspace bin_input() filled")
         ws = workspace(plan, out.device)
+    wsb = _ws_bytes(ws, out.device)
     if step == "all":
         check(lib().dd_forward(plan.handle, _ptr(x), _ptr(weights), _ptr(out), out.numel(),
-                               _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_forward")
+                               _ptr(ws), wsb, _stream_ptr(stream)), "dd_forward")
     else:
-        check(lib().dd_forward_sum(plan.handle, _ptr(out), out.numel(), _ptr(ws), ws.numel(),
+        check(lib().dd_forward_sum(plan.handle, _ptr(out), out.numel(), _ptr(ws), wsb,
                                    _stream_ptr(stream)), "dd_forward_sum")
     return out
 
@@ -409,7 +437,7 @@ def dedisperse_noalloc(x, plan: Plan, out, weights=None, stream=None):
     (no device allocation in the call).  `out` must be given; the plan must
     have been prepared on the device (plan.prepare())."""
     _check_input(x, plan)
-    _check_weights(weights, plan)
+    _check_weights(weights, plan, x.device)
     if out is None:
         raise ValueError("dedisperse_noalloc needs a preallocated `out`")
     out = _out_tensor(plan, out, x.device)
@@ -421,9 +449,9 @@ def dedisperse_noalloc(x, plan: Plan, out, weights=None, stream=None):
 def bin_input(x, plan: Plan, ws, weights=None, stream=None):
     """The binning step alone (dd_forward_bin) into the workspace ws."""
     _check_input(x, plan)
-    _check_weights(weights, plan)
+    _check_weights(weights, plan, x.device)
     check(lib().dd_forward_bin(plan.handle, _ptr(x), _ptr(weights), _ptr(ws),
-                               ws.numel() if ws is not None else 0, _stream_ptr(stream)),
+                               _ws_bytes(ws, x.device), _stream_ptr(stream)),
           "dd_forward_bin")
     return ws
 
@@ -439,12 +467,14 @@ def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=Tru
     if (grad_out.dtype != torch.float32 or not grad_out.is_cuda or not grad_out.is_contiguous()
             or grad_out.numel() != plan.out_elems):
         raise ValueError(f"grad_out must be a contiguous device float32 tensor of {plan.out_elems}")
+    dev = grad_out.device
     if grad_w:
         if x is None:
             raise ValueError("x is needed for the weight gradient")
+    if x is not None:
         _check_input(x, plan)
-    _check_weights(weights, plan)
-    dev = grad_out.device
+        _on(x, dev, "x")
+    _check_weights(weights, plan, dev)
     if isinstance(grad_in, torch.Tensor):
         if (grad_in.dtype != torch.float32 or grad_in.device != dev or not grad_in.is_contiguous()
                 or tuple(grad_in.shape) != (plan.nchans, plan.nsamp)):
@@ -458,7 +488,7 @@ def adjoint(grad_out, plan: Plan, x=None, weights=None, grad_in=True, grad_w=Tru
     if ws is None:
         ws = workspace(plan, dev)
     check(lib().dd_adjoint(plan.handle, _ptr(grad_out), _ptr(x), _ptr(weights), _ptr(dx),
-                           _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_adjoint")
+                           _ptr(dw), _ptr(ws), _ws_bytes(ws, dev), _stream_ptr(stream)), "dd_adjoint")
     return dx, dw
 
 
@@ -477,12 +507,12 @@ def boxcar_loss(x, plan: Plan, weights=None, max_width: int = 32, ws=None, strea
     stored (dd_boxcar_loss).  x: [nbeams, nchans, nsamp] or [nchans, nsamp]."""
     import torch
     nb = _check_beams(x, plan)
-    _check_weights(weights, plan)
+    _check_weights(weights, plan, x.device)
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
     if ws is None:
         ws = workspace(plan, x.device)
     check(lib().dd_boxcar_loss(plan.handle, _ptr(x), nb, _ptr(weights), int(max_width),
-                               _ptr(loss), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+                               _ptr(loss), _ptr(ws), _ws_bytes(ws, x.device), _stream_ptr(stream)),
           "dd_boxcar_loss")
     return loss[0]
 
@@ -493,13 +523,14 @@ def boxcar_backward(x, plan: Plan, weights=None, max_width: int = 32, grad_in=Tr
     (dd_boxcar_backward)."""
     import torch
     nb = _check_beams(x, plan)
-    _check_weights(weights, plan)
+    _check_weights(weights, plan, x.device)
     dx = torch.empty_like(x) if grad_in else None
     dw = torch.empty(plan.nchans, dtype=torch.float32, device=x.device) if grad_w else None
     if ws is None:
         ws = workspace(plan, x.device)
     check(lib().dd_boxcar_backward(plan.handle, _ptr(x), nb, _ptr(weights), int(max_width),
-                                   _ptr(dx), _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+                                   _ptr(dx), _ptr(dw), _ptr(ws), _ws_bytes(ws, x.device),
+                                   _stream_ptr(stream)),
           "dd_boxcar_backward")
     return dx, dw
 
@@ -520,11 +551,12 @@ def _check_batch_input(x, batch: Batch):
         raise ValueError("the batch boxcar calls take f32 batches")
 
 
-def _check_batch_weights(weights, batch: Batch):
+def _check_batch_weights(weights, batch: Batch, dev):
     import torch
-    if weights is not None and (weights.dtype != torch.float32 or not weights.is_contiguous()
+    if weights is not None and (weights.dtype != torch.float32
                                 or weights.numel() != sum(p.nchans for p in batch.plans)):
         raise ValueError("weights must be the packed float32 weights of every beam")
+    _on(weights, dev, "weights")
 
 
 def batch_boxcar_loss(x, batch: Batch, weights=None, max_width: int = 32, ws=None, stream=None):
@@ -532,12 +564,13 @@ def batch_boxcar_loss(x, batch: Batch, weights=None, max_width: int = 32, ws=Non
     and weights packed as for dedisperse_batch.  Returns [nbeams] float32."""
     import torch
     _check_batch_input(x, batch)
-    _check_batch_weights(weights, batch)
+    _check_batch_weights(weights, batch, x.device)
     loss = torch.empty(len(batch.plans), dtype=torch.float32, device=x.device)
     if ws is None:
         ws = batch_boxcar_workspace(batch, x.device)
     check(lib().dd_batch_boxcar_loss(batch.handle, _ptr(x), _ptr(weights), int(max_width), _ptr(loss),
-                                     _ptr(ws), ws.numel(), _stream_ptr(stream)), "dd_batch_boxcar_loss")
+                                     _ptr(ws), _ws_bytes(ws, x.device), _stream_ptr(stream)),
+          "dd_batch_boxcar_loss")
     return loss
 
 
@@ -550,14 +583,14 @@ def batch_boxcar_backward(x, batch: Batch, weights=None, max_width: int = 32, gr
     (skip) or a float32 tensor to write into."""
     import torch
     _check_batch_input(x, batch)
-    _check_batch_weights(weights, batch)
+    _check_batch_weights(weights, batch, x.device)
     nw = sum(p.nchans for p in batch.plans)
 
     def buf(arg, n):
         if isinstance(arg, torch.Tensor):
-            if arg.dtype != torch.float32 or not arg.is_contiguous() or arg.numel() < n:
-                raise ValueError(f"output buffers must be contiguous float32 tensors of {n} or more")
-            return arg
+            if arg.dtype != torch.float32 or arg.numel() < n:
+                raise ValueError(f"output buffers must be float32 tensors of {n} or more")
+            return _on(arg, x.device, "an output buffer")
         return torch.zeros(n, dtype=torch.float32, device=x.device) if arg else None
 
     dx = buf(grad_in, batch.in_bytes // 4)
@@ -565,7 +598,7 @@ def batch_boxcar_backward(x, batch: Batch, weights=None, max_width: int = 32, gr
     if ws is None:
         ws = batch_boxcar_workspace(batch, x.device)
     check(lib().dd_batch_boxcar_backward(batch.handle, _ptr(x), _ptr(weights), int(max_width), _ptr(dx),
-                                         _ptr(dw), _ptr(ws), ws.numel(), _stream_ptr(stream)),
+                                         _ptr(dw), _ptr(ws), _ws_bytes(ws, x.device), _stream_ptr(stream)),
           "dd_batch_boxcar_backward")
     return dx, dw
 

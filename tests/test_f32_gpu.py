@@ -314,3 +314,36 @@ def test_adjoint_rejects_integer_plans():
     plan = dd.Plan(w.freqs, w.tsamp, w.nsamp, w.ranges, "u8")
     with pytest.raises(ValueError):
         dd.adjoint(torch.zeros(plan.out_elems, device="cuda"), plan)
+
+
+def test_host_tensors_are_refused_before_any_launch():
+    """Every tensor the binding hands to the library must live on the
+    input's device: host tensors are refused with ValueError (a host address
+    in a kernel would fault it)."""
+    x, freqs, tsamp, ranges, w = case(1, nch=16, nsamp=2000)
+    plan = gpu_plan(freqs, tsamp, x.shape[1], ranges)
+    xd = torch.from_numpy(x).cuda()
+    wd = torch.from_numpy(w).cuda()
+    say("host tensors refused", plan.nchans, plan.nsamp)
+    with pytest.raises(ValueError):
+        dd.dedisperse(xd, plan, weights=torch.from_numpy(w))
+    with pytest.raises(ValueError):
+        dd.dedisperse(xd, plan, out=torch.empty(plan.out_elems, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        dd.dedisperse(xd, plan, ws=torch.empty(plan.workspace_bytes, dtype=torch.uint8))
+    g = torch.ones(plan.out_elems, device="cuda")
+    with pytest.raises(ValueError):
+        dd.adjoint(g, plan, x=torch.from_numpy(x), weights=wd)
+    with pytest.raises(ValueError):
+        dd.boxcar_loss(xd, plan, weights=wd, ws=torch.empty(plan.workspace_bytes, dtype=torch.uint8))
+    s = dd.Stream(plan)
+    with pytest.raises(ValueError):
+        s.push(torch.zeros((plan.nchans, s.first), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        s.push(torch.zeros((plan.nchans, s.first), dtype=torch.float32))
+    # a workspace of another dtype counts in bytes
+    ws = torch.empty((plan.workspace_bytes + 3) // 4, dtype=torch.float32, device="cuda")
+    out = dd.dedisperse(xd, plan, weights=wd, ws=ws)
+    ref = dd.dedisperse(xd, plan, weights=wd)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
