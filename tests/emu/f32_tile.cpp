@@ -293,5 +293,38 @@ int main(int argc, char **argv)
     ++tried; ok += run(rnd, 2.56e-4, 4000, {{0, 33, 1, 1}, {33, 40, 0.5, 2}}, 0, 11, 1, "permuted sb", 3);
     ++tried; ok += run(band(1670, 1370, 4096), 6.4e-5, 1 << 13, {{0, 200, 1, 1}}, 0, 12, 13, "4096ch sb", 3);
     printf("plans %d of %d, fails %ld\n", ok, tried, fails);
+    // random plans: band, sampling, length, one to three ranges of random
+    // step and downsample, any strategy; a plan the library rejects (its
+    // patterns do not fit, or no output is left) is counted, not failed
+    std::mt19937 fz(20240611);
+    auto uni = [&](double a, double b) { return std::uniform_real_distribution<double>(a, b)(fz); };
+    auto pick = [&](int a, int b) { return std::uniform_int_distribution<int>(a, b)(fz); };
+    int fuzz_ok = 0;
+    const int fuzz_n = 24;
+    for (int i = 0; i < fuzz_n; ++i) {
+        const int nch = pick(1, 160);
+        const double top = uni(1300, 1700);
+        std::vector<double> f = band(top, top - uni(50, 400), nch);
+        if (i % 3 == 1) std::shuffle(f.begin(), f.end(), fz);
+        const double ts[4] = {6.4e-5, 1.28e-4, 2.56e-4, 1e-3};
+        const double tsamp = ts[pick(0, 3)];
+        const long nsamp = pick(1500, 6000);
+        std::vector<dd_range> rg;
+        double lo = 0;
+        for (int r = pick(1, 3); r > 0; --r) {
+            const double steps[4] = {0.25, 0.5, 1.0, 2.0};
+            const double step = steps[pick(0, 3)];
+            const double hi = lo + step * pick(3, 60);
+            rg.push_back(dd_range{lo, hi, step, pick(1, 4)});
+            lo = hi;
+        }
+        const int variants[3] = {0, 1, 3};
+        const int variant = variants[i % 3];
+        const int stage = i % 4 == 3 ? pick(1, 14) : 0;
+        char nm[64];
+        snprintf(nm, sizeof nm, "fuzz %d v%d", i, variant);
+        fuzz_ok += run(f, tsamp, nsamp, rg, stage, 100 + i, 2, nm, variant);
+    }
+    printf("fuzz plans %d of %d accepted, fails %ld\n", fuzz_ok, fuzz_n, fails);
     return fails ? 1 : 0;
 }
