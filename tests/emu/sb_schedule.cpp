@@ -337,6 +337,41 @@ int main(int argc, char **argv)
             run(band(1670, 1370, 17), 64e-6, 20000, {{0, 30, 0.1, 1}, {30, 60, 0.5, 16}}, dt, 0, 20, stride,
                 N("17ch"));
         }
+    } else if (!strcmp(which, "random")) {
+        // random plans: band (possibly permuted), sampling, length, one to
+        // three ranges of random step and downsample, every DM tile and time
+        // tile; plans whose patterns do not fit the LDS are skipped
+        std::mt19937 fz(7331);
+        auto uni = [&](double a, double b) { return std::uniform_real_distribution<double>(a, b)(fz); };
+        auto pick = [&](int a, int b) { return std::uniform_int_distribution<int>(a, b)(fz); };
+        const int tiles[6][2] = {{192, 0}, {128, 0}, {96, 0}, {64, 0}, {96, 256}, {64, 256}};
+        const int nplans = argc > 3 ? atoi(argv[3]) : 36;
+        for (int i = 0; i < nplans; ++i) {
+            const int nch = pick(1, 300);
+            const double top = uni(1300, 1700);
+            std::vector<double> f = band(top, top - uni(50, 400), nch);
+            if (i % 4 == 2)
+                std::shuffle(f.begin(), f.end(), fz);
+            const double ts[3] = {6.4e-5, 1.28e-4, 2.56e-4};
+            const double tsamp = ts[pick(0, 2)];
+            const int64_t nsamp = pick(3000, 24000);
+            std::vector<dd_range> rg;
+            double lo = 0;
+            for (int r = pick(1, 3); r > 0; --r) {
+                const double steps[5] = {0.1, 0.2, 0.5, 1.0, 2.0};
+                const double step = steps[pick(0, 4)];
+                const double hi = lo + step * pick(5, 250);
+                const int dss[6] = {1, 2, 3, 4, 8, 16};
+                rg.push_back(dd_range{lo, hi, step, dss[pick(0, 5)]});
+                lo = hi;
+            }
+            const int *tl = tiles[i % 6];
+            g_time_tile = tl[1];
+            const int stage = i % 5 == 4 ? 8 : 0;
+            char nm[64];
+            snprintf(nm, sizeof nm, "random%d-dt%d-tt%d", i, tl[0], g_time_tile);
+            run(f, tsamp, nsamp, rg, tl[0], stage, 300 + i, stride, nm);
+        }
     } else {
         const std::vector<dd_range> rg = {{0, 150, 0.1, 1}, {150, 300, 0.2, 2}, {300, 500, 0.5, 4},
                                           {500, 1000, 1, 8}, {1000, 2000, 2, 16}};
