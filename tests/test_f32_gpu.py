@@ -70,7 +70,7 @@ def test_forward_random_shapes(seed):
 
 
 @pytest.mark.parametrize("variant", [1, 3])
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(8))
 def test_direct_and_subband_sums_vs_oracle(seed, variant):
     """The two float32 strategies -- direct sums (variant 1) and sub-band
     reuse (variant 3: pattern rows of 4-row groups built in LDS, added at
@@ -81,7 +81,14 @@ def test_direct_and_subband_sums_vs_oracle(seed, variant):
     except ValueError:
         pytest.skip("plan has no valid output")
     say("f32 variant", variant, seed, x.shape, ranges)
-    plan = dd.Plan(freqs, tsamp, x.shape[1], ranges, "f32", variant=variant)
+    try:
+        plan = dd.Plan(freqs, tsamp, x.shape[1], ranges, "f32", variant=variant)
+    except dd.DDError as e:
+        # sub-band reuse asked for where its tables exceed the LDS is refused
+        # at plan creation (the default then takes the direct sums)
+        if variant == 3 and e.status == -2:
+            pytest.skip(f"sub-band tables do not fit the LDS: {e}")
+        raise
     assert plan.strategy["variant"] == (3 if variant == 3 else 2)
     xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
     out = dd.dedisperse(xt, plan, weights=wt)
