@@ -418,7 +418,10 @@ dd_status dd_boxcar_backward(const dd_plan *plan, const float *d_in, int32_t nbe
  *                   reduction.  d_grad_in: dL/dx in the batch input's layout
  *                   (float32 at each beam's in_offset), or NULL; d_grad_w:
  *                   each beam's dL/dw concatenated like the weights, or NULL.
- *                   Both calls allocate nothing and contain no memset.
+ *                   Once dd_batch_prepare has run on the device, both
+ *                   calls allocate nothing and contain no memset (graph
+ *                   capture); before it, the first call on a device
+ *                   uploads the batch's descriptors.
  */
 typedef struct dd_batch dd_batch;
 
