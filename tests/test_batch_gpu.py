@@ -245,3 +245,32 @@ def test_float_batch_graph_replay():
                               weights=torch.from_numpy(beams[0][4]).cuda())
         torch.cuda.synchronize()
         assert torch.equal(other, batch.split(eager)[0])
+
+
+def test_many_tiny_beams():
+    """200 tiny integer beams (1 to 17 channels, one or two ranges) in one
+    batch of default plans: every beam equals its own forward bit for bit
+    (descriptor search, queue slices and work stealing over many short
+    items)."""
+    rng = np.random.default_rng(4242)
+    beams = []
+    for b in range(200):
+        nch = int(rng.choice([1, 3, 8, 17]))
+        nsamp = int(rng.integers(800, 3000))
+        freqs = synth.band_freqs(1500.0, float(rng.uniform(1250.0, 1450.0)), nch)
+        ranges = [(0.0, float(rng.integers(2, 30)), 1.0, 1)]
+        if b % 3 == 1:
+            ranges.append((ranges[0][1], ranges[0][1] + 10.0, 2.0, int(rng.choice([2, 4]))))
+        beams.append((rng.integers(0, 256, size=(nch, nsamp)).astype(np.uint8), freqs, 2.56e-4, ranges))
+    say("many tiny beams", len(beams))
+    plans = make_plans(beams, {})
+    batch = dd.Batch(plans)
+    xin = batch.pack([b[0] for b in beams])
+    out = dd.dedisperse_batch(xin, batch)
+    torch.cuda.synchronize()
+    for i, ((x, f, t, r), p, o) in enumerate(zip(beams, plans, batch.split(out))):
+        single = dd.dedisperse(torch.from_numpy(x).cuda(), p)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), i
+        if i % 25 == 0:
+            assert np.array_equal(o.cpu().numpy(), cref.dedisperse_u8(x, f, t, r)), i

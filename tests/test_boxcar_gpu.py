@@ -294,3 +294,39 @@ def test_batch_boxcar_graph_replay_and_limits():
     with pytest.raises(dd.DDError) as e:
         dd.batch_boxcar_backward(mx, mb, None, 8)
     assert e.value.status == -2
+
+
+def test_many_tiny_float_beams_batch():
+    """120 tiny float32 beams (1 to 17 channels) in one batch: the forward,
+    the boxcar loss and its backward equal each beam's own calls bit for bit
+    (descriptor search over many short problems; the helper launches loop
+    over their descriptors)."""
+    rng = np.random.default_rng(777)
+    beams = []
+    for b in range(120):
+        nch = int(rng.choice([1, 3, 8, 17]))
+        nsamp = int(rng.integers(1200, 3000))
+        freqs = synth.band_freqs(1500.0, float(rng.uniform(1250.0, 1450.0)), nch)
+        ranges = [(0.0, float(rng.integers(2, 20)), 1.0, 1)]
+        x = rng.standard_normal((nch, nsamp)).astype(np.float32)
+        w = rng.uniform(0.5, 1.5, nch).astype(np.float32)
+        beams.append((x, freqs, 2.56e-4, ranges, w))
+    say("many tiny float beams", len(beams))
+    plans = [dd.Plan(f, t, x.shape[1], r, "f32") for (x, f, t, r, _) in beams]
+    batch = dd.Batch(plans)
+    xin = batch.pack([b[0] for b in beams])
+    wts = batch.pack_weights([b[4] for b in beams])
+    out = dd.dedisperse_batch(xin, batch, weights=wts)
+    losses = dd.batch_boxcar_loss(xin, batch, wts, 8)
+    dx, dw = dd.batch_boxcar_backward(xin, batch, wts, 8)
+    torch.cuda.synchronize()
+    for i, ((x, f, t, r, w), p, o) in enumerate(zip(beams, plans, batch.split(out))):
+        xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+        single = dd.dedisperse(xt, p, weights=wt)
+        l1 = dd.boxcar_loss(xt, p, wt, 8)
+        dx1, dw1 = dd.boxcar_backward(xt, p, wt, 8)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single), i
+        assert float(losses[i]) == float(l1), i
+        assert torch.equal(batch.split_input(dx)[i], dx1), i
+        assert torch.equal(batch.split_weights(dw)[i], dw1), i
